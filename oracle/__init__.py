@@ -1,0 +1,13 @@
+"""Plain FP64 CPU oracle of regularized inverse holographic volume reconstruction.
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline leg
+of the benchmark may import this package.  It shares no code with the GPU
+library (no kernels, headers, tables or helpers) and never calls it.
+
+Modules:
+  optics  - angular-spectrum forward model A, its adjoint, ||A||^2 closed form
+  prox    - 3D TV, gradient-projection TV prox, soft threshold, fused-lasso prox
+  fista   - objective and the FISTA iteration
+  detect  - threshold / connected components / weighted centroids / matching
+"""
+from . import optics, prox, fista, detect  # noqa: F401

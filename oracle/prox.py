@@ -1,0 +1,109 @@
+"""FP64 reference of the fused-lasso proximal operator.
+
+TEST INFRASTRUCTURE ONLY.  This is the oracle that the GPU library is checked
+against; the product path never imports, calls or links it.
+
+Paper, section "Methodology":
+  * Eq. (3)  l1 regulariser  sum_i |x_i|.
+  * Eq. (4)  isotropic TV, extended here to three dimensions (the paper notes the
+    norm extends to higher dimensions): sum over voxels of the Euclidean norm of
+    the forward differences along x, y and z.  The last difference along each
+    axis is zero (Neumann boundary); all axes carry unit weight.
+  * Eq. (5)  fused lasso  l1 * ||x||_1 + tv * TV(x).
+  * Eq. (6)  prox_t(v) = argmin_x g(x) + 1/(2t) ||x - v||^2.
+  * TV prox by the gradient-projection (GP) method of Beck & Teboulle on the dual
+    of the TV denoising problem, which stores one dual value per direction and
+    voxel.
+  * Fused-lasso prox = soft threshold of the TV prox (the separability the paper
+    states); Eq. (8) is read as the soft threshold sign(u) (|u| - t l1)_+, which
+    becomes max(u - t l1, 0) under the non-negativity constraint.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+__all__ = ["grad3", "grad3_adjoint", "tv3", "prox_tv_gp", "soft_threshold",
+           "prox_fused_lasso", "dual_objective"]
+
+
+def grad3(u: np.ndarray):
+    """D u: forward differences along x, y, z of a [nz][ny][nx] volume.
+
+    Returns (dx, dy, dz); the last difference along each axis is 0.
+    """
+    dx = np.zeros_like(u)
+    dy = np.zeros_like(u)
+    dz = np.zeros_like(u)
+    dx[:, :, :-1] = u[:, :, 1:] - u[:, :, :-1]
+    dy[:, :-1, :] = u[:, 1:, :] - u[:, :-1, :]
+    dz[:-1, :, :] = u[1:, :, :] - u[:-1, :, :]
+    return dx, dy, dz
+
+
+def grad3_adjoint(px: np.ndarray, py: np.ndarray, pz: np.ndarray) -> np.ndarray:
+    """D^T p, the exact transpose of grad3 (so <D u, p> = <u, D^T p>)."""
+    out = np.zeros_like(px)
+    # d/du of sum_i px[i] (u[i+1] - u[i]) for i < n-1
+    out[:, :, :-1] -= px[:, :, :-1]
+    out[:, :, 1:] += px[:, :, :-1]
+    out[:, :-1, :] -= py[:, :-1, :]
+    out[:, 1:, :] += py[:, :-1, :]
+    out[:-1, :, :] -= pz[:-1, :, :]
+    out[1:, :, :] += pz[:-1, :, :]
+    return out
+
+
+def tv3(u: np.ndarray) -> float:
+    """Isotropic 3D total variation, Eq. (4) extended to z."""
+    dx, dy, dz = grad3(np.asarray(u, dtype=np.float64))
+    return float(np.sqrt(dx * dx + dy * dy + dz * dz).sum())
+
+
+def dual_objective(v, tau, px, py, pz) -> float:
+    """1/2 ||v - tau D^T p||^2, the dual function that GP decreases."""
+    r = v - tau * grad3_adjoint(px, py, pz)
+    return 0.5 * float((r * r).sum())
+
+
+def prox_tv_gp(v: np.ndarray, tau: float, n_iter: int, return_dual: bool = False):
+    """argmin_u 1/2||u - v||^2 + tau TV(u), by n_iter gradient-projection steps.
+
+    Dual: min over |p_voxel| <= 1 of 1/2 ||v - tau D^T p||^2, with u = v - tau D^T p.
+    The gradient of the dual in p is -tau D u and its Lipschitz constant is
+    tau^2 ||D||^2 <= 12 tau^2 in 3D, so each step is
+        u = v - tau D^T p
+        q = p + D u / (12 tau)
+        p = q / max(1, |q|)          (projection on the unit ball per voxel)
+    starting from p = 0.  The primal is recovered once more at the end.
+    """
+    v = np.asarray(v, dtype=np.float64)
+    px = np.zeros_like(v)
+    py = np.zeros_like(v)
+    pz = np.zeros_like(v)
+    if tau == 0.0:
+        return (v.copy(), (px, py, pz)) if return_dual else v.copy()
+    c = 1.0 / (12.0 * tau)
+    for _ in range(n_iter):
+        u = v - tau * grad3_adjoint(px, py, pz)
+        gx, gy, gz = grad3(u)
+        qx = px + c * gx
+        qy = py + c * gy
+        qz = pz + c * gz
+        scale = np.maximum(1.0, np.sqrt(qx * qx + qy * qy + qz * qz))
+        px, py, pz = qx / scale, qy / scale, qz / scale
+    u = v - tau * grad3_adjoint(px, py, pz)
+    return (u, (px, py, pz)) if return_dual else u
+
+
+def soft_threshold(u: np.ndarray, thr: float, nonneg: bool = True) -> np.ndarray:
+    """prox of thr*|.|_1 (Eq. 8 as read), optionally restricted to x >= 0."""
+    if nonneg:
+        return np.maximum(u - thr, 0.0)
+    return np.sign(u) * np.maximum(np.abs(u) - thr, 0.0)
+
+
+def prox_fused_lasso(v: np.ndarray, step: float, l1: float, tv: float, n_iter: int,
+                     nonneg: bool = True) -> np.ndarray:
+    """prox of step * (l1 ||x||_1 + tv TV(x)) [+ x >= 0]: TV prox, then soft threshold."""
+    u = prox_tv_gp(v, step * tv, n_iter)
+    return soft_threshold(u, step * l1, nonneg)

@@ -1,0 +1,358 @@
+"""Pins of the FP64 oracle against facts it does not compute itself.
+
+Each test ties one part of the oracle to mathematics or to the paper: brute
+force on tiny inputs, closed forms, invariants and special cases that reduce to
+a textbook result.  A dropped term, a wrong sign, index or normalisation in the
+oracle fails at least one of them.  All run on the CPU.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import optics, prox, fista, detect
+from paper_1904_04884_amd import scenes
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def small_geom(nx=16, ny=16, nz=4, **kw):
+    return scenes.geometry_c1().with_(nx=nx, ny=ny, nz=nz, **kw)
+
+
+# --- P1: FFT convention against a brute-force DFT --------------------------
+def test_p1_fft_matches_brute_dft():
+    rng = np.random.default_rng(0)
+    n = 16
+    u = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    k = np.arange(n)
+    W = np.exp(-2j * np.pi * np.outer(k, k) / n)
+    brute = W @ u @ W.T
+    assert np.max(np.abs(np.fft.fft2(u) - brute)) <= 1e-13 * np.max(np.abs(brute)) * n
+    # inverse is the conjugate transform scaled by 1/n^2
+    brute_inv = np.conj(W) @ u @ np.conj(W).T / (n * n)
+    assert np.max(np.abs(np.fft.ifft2(u) - brute_inv)) <= 1e-15 * n * n
+
+
+def test_p1_fftfreq_grid():
+    fy, fx = optics.freq_grid(6, 8, 2.0)
+    assert np.allclose(fx.ravel(), np.array([0, 1, 2, 3, -4, -3, -2, -1]) / 16.0)
+    assert np.allclose(fy.ravel(), np.array([0, 1, 2, -3, -2, -1]) / 12.0)
+
+
+# --- P2: zero distance is the identity -------------------------------------
+@pytest.mark.parametrize("carrier", [True, False])
+def test_p2_zero_distance_identity(carrier):
+    g = small_geom(nz=1, z0_um=0.0, carrier=carrier)
+    rng = np.random.default_rng(1)
+    x = rng.standard_normal(g.shape)
+    y = rng.standard_normal((g.ny, g.nx))
+    assert np.max(np.abs(optics.forward(g, x) - x[0])) <= 1e-15 * 16
+    assert np.max(np.abs(optics.adjoint(g, y)[0] - y)) <= 1e-15 * 16
+    assert optics.lipschitz(g) == pytest.approx(1.0, abs=1e-15)
+
+
+# --- P3: composition of propagators ----------------------------------------
+def test_p3_propagation_composes():
+    # distances of tens of um keep the FP64 rounding of the ~500 rad phase
+    # argument below 1e-13
+    g = small_geom(nx=32, ny=16)
+    h1 = optics.transfer_function(g, 12.5)
+    h2 = optics.transfer_function(g, 31.25)
+    h12 = optics.transfer_function(g, 12.5 + 31.25)
+    assert np.max(np.abs(h1 * h2 - h12)) <= 1e-12
+    rng = np.random.default_rng(2)
+    u = rng.standard_normal((16, 32)) + 1j * rng.standard_normal((16, 32))
+    two = np.fft.ifft2(h2 * np.fft.fft2(np.fft.ifft2(h1 * np.fft.fft2(u))))
+    one = np.fft.ifft2(h12 * np.fft.fft2(u))
+    assert np.max(np.abs(two - one)) <= 1e-12 * np.max(np.abs(one))
+
+
+def test_p3_gaussian_beam_matches_paraxial_closed_form():
+    """Angular-spectrum propagation of a wide Gaussian beam against the
+    paraxial Gaussian-beam solution exp(ikz)/(1+iz/zR) exp(-r^2/(w0^2(1+iz/zR))).
+
+    Pins the 2 pi, the wavelength, the pixel scaling of the frequency grid and
+    the sign of the propagation phase; non-paraxial corrections are ~1e-6 here.
+    """
+    n, px, lam, w0, z = 256, 2.0, 0.6328, 50.0, 2000.0
+    g = scenes.Geometry(nx=n, ny=n, nz=1, pixel_um=px, wavelength_um=lam, z0_um=z, dz_um=0.0)
+    c = (np.arange(n) - n // 2) * px
+    r2 = c[:, None] ** 2 + c[None, :] ** 2
+    u0 = np.exp(-r2 / w0 ** 2)
+    u0 = np.fft.ifftshift(u0)
+    uz = np.fft.ifft2(np.fft.fft2(u0) * optics.transfer_function(g, z))
+    zr = np.pi * w0 ** 2 / lam
+    q = 1.0 + 1j * z / zr
+    ref = np.exp(1j * 2 * np.pi * z / lam) / q * np.exp(-r2 / (w0 ** 2 * q))
+    ref = np.fft.ifftshift(ref)
+    err = np.max(np.abs(uz - ref))
+    assert err < 2e-5, err
+    # and the wrong sign of the phase is far off
+    bad = np.fft.ifft2(np.fft.fft2(u0) * np.conj(optics.transfer_function(g, z)))
+    assert np.max(np.abs(bad - ref)) > 0.1
+
+
+# --- P4: propagation is unitary --------------------------------------------
+def test_p4_unitary():
+    g = small_geom(nx=32, ny=32)
+    rng = np.random.default_rng(3)
+    u = rng.standard_normal((32, 32)) + 1j * rng.standard_normal((32, 32))
+    v = np.fft.ifft2(optics.transfer_function(g, 7777.0) * np.fft.fft2(u))
+    assert abs(np.linalg.norm(v) - np.linalg.norm(u)) <= 1e-13 * np.linalg.norm(u)
+
+
+# --- P5: adjoint identity ---------------------------------------------------
+@pytest.mark.parametrize("shape", [(16, 16, 4), (24, 16, 3), (16, 48, 5)])
+def test_p5_adjoint_identity(shape):
+    nx, ny, nz = shape
+    g = small_geom(nx=nx, ny=ny, nz=nz)
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal(g.shape)
+    y = rng.standard_normal((ny, nx))
+    lhs = float(np.vdot(optics.forward(g, x), y))
+    rhs = float(np.vdot(x, optics.adjoint(g, y)))
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+# --- P6: the cosine form (independent second path) --------------------------
+def test_p6_cosine_form():
+    g = small_geom(nx=24, ny=16, nz=5)
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal(g.shape)
+    y = rng.standard_normal((g.ny, g.nx))
+    fy = np.fft.fftfreq(g.ny, g.pixel_um)[:, None]
+    fx = np.fft.fftfreq(g.nx, g.pixel_um)[None, :]
+    kz = np.sqrt(1.0 / g.wavelength_um ** 2 - fx ** 2 - fy ** 2)
+    ax = np.zeros((g.ny, g.nx))
+    aty = np.empty(g.shape)
+    for j, z in enumerate(optics.plane_z(g)):
+        cphi = np.cos(2 * np.pi * z * kz)
+        ax += np.fft.irfft2(np.fft.rfft2(x[j]) * cphi[:, : g.nx // 2 + 1], s=(g.ny, g.nx))
+        aty[j] = np.fft.irfft2(np.fft.rfft2(y) * cphi[:, : g.nx // 2 + 1], s=(g.ny, g.nx))
+    assert np.max(np.abs(ax - optics.forward(g, x))) <= 1e-13 * np.max(np.abs(ax))
+    assert np.max(np.abs(aty - optics.adjoint(g, y))) <= 1e-13 * np.max(np.abs(aty))
+
+
+# --- P7 / P8: ||A||^2 and the A A^T multiplier --------------------------------
+def test_p8_aat_multiplier():
+    g = small_geom(nx=16, ny=24, nz=6)
+    rng = np.random.default_rng(6)
+    y = rng.standard_normal((g.ny, g.nx))
+    lhs = optics.forward(g, optics.adjoint(g, y))
+    # S computed here from cos^2 of the phase, not from the oracle's helper
+    fy = np.fft.fftfreq(g.ny, g.pixel_um)[:, None]
+    fx = np.fft.fftfreq(g.nx, g.pixel_um)[None, :]
+    kz = np.sqrt(1.0 / g.wavelength_um ** 2 - fx ** 2 - fy ** 2)
+    S = sum(np.cos(2 * np.pi * z * kz) ** 2 for z in optics.plane_z(g))
+    rhs = np.fft.ifft2(S * np.fft.fft2(y)).real
+    assert np.max(np.abs(lhs - rhs)) <= 1e-13 * np.max(np.abs(rhs))
+
+
+def test_p7_lipschitz_closed_form_attained_and_bounds_power_iteration():
+    g = small_geom(nx=16, ny=16, nz=8)
+    L = optics.lipschitz(g)
+    S = optics.aat_multiplier(g)
+    ky, kx = np.unravel_index(np.argmax(S), S.shape)
+    # the real cosine at the maximising grid frequency is an eigenvector of A A^T
+    yy, xx = np.meshgrid(np.arange(g.ny), np.arange(g.nx), indexing="ij")
+    y = np.cos(2 * np.pi * (ky * yy / g.ny + kx * xx / g.nx))
+    aty = optics.adjoint(g, y)
+    assert float((aty * aty).sum()) / float((y * y).sum()) == pytest.approx(L, rel=1e-12)
+    # power iteration on A^T A approaches ||A||^2 from below
+    rng = np.random.default_rng(7)
+    v = rng.standard_normal(g.shape)
+    est = 0.0
+    for _ in range(200):
+        w = optics.adjoint(g, optics.forward(g, v))
+        est = float(np.vdot(v, w) / np.vdot(v, v))
+        v = w / np.linalg.norm(w)
+    assert est <= L * (1 + 1e-12)
+    assert est >= 0.97 * L
+
+
+def test_p7_c1_lipschitz_value():
+    L = optics.lipschitz(scenes.geometry_c1())
+    assert 31.9 < L <= 32.0  # at most nz (sum of nz squared cosines)
+
+
+# --- TV operators -------------------------------------------------------------
+def test_grad_adjoint_is_transpose():
+    rng = np.random.default_rng(8)
+    u = rng.standard_normal((3, 4, 5))
+    px, py, pz = (rng.standard_normal((3, 4, 5)) for _ in range(3))
+    dx, dy, dz = prox.grad3(u)
+    lhs = float((dx * px).sum() + (dy * py).sum() + (dz * pz).sum())
+    rhs = float((u * prox.grad3_adjoint(px, py, pz)).sum())
+    assert abs(lhs - rhs) <= 1e-12 * (abs(lhs) + 1)
+
+
+def test_tv3_brute_force():
+    rng = np.random.default_rng(9)
+    u = rng.standard_normal((2, 3, 4))
+    tot = 0.0
+    for z, y, x in itertools.product(range(2), range(3), range(4)):
+        gx = u[z, y, x + 1] - u[z, y, x] if x < 3 else 0.0
+        gy = u[z, y + 1, x] - u[z, y, x] if y < 2 else 0.0
+        gz = u[z + 1, y, x] - u[z, y, x] if z < 1 else 0.0
+        tot += math.sqrt(gx * gx + gy * gy + gz * gz)
+    assert prox.tv3(u) == pytest.approx(tot, rel=1e-14)
+
+
+# --- P11: l1-only prox is the soft threshold ---------------------------------
+def test_p11_prox_without_tv_is_soft_threshold():
+    rng = np.random.default_rng(10)
+    v = rng.standard_normal((4, 5, 6))
+    x = prox.prox_fused_lasso(v, 0.5, 0.3, 0.0, 10)
+    assert np.array_equal(x, np.maximum(v - 0.15, 0.0))
+    xs = prox.prox_fused_lasso(v, 0.5, 0.3, 0.0, 10, nonneg=False)
+    assert np.array_equal(xs, np.sign(v) * np.maximum(np.abs(v) - 0.15, 0.0))
+
+
+# --- P12: prox against a brute-force solve of the 1D dual --------------------
+def brute_tv1d(v, tau):
+    """Exact 1D TV prox by enumerating the active sets of the dual box QP
+    min_{|p_i| <= 1} 1/2 ||v - tau D^T p||^2 (p_i in {-1, +1, free})."""
+    n = len(v)
+    D = np.zeros((n - 1, n))
+    for i in range(n - 1):
+        D[i, i], D[i, i + 1] = -1.0, 1.0
+    best = None
+    for pattern in itertools.product((-1, 0, 1), repeat=n - 1):
+        pattern = np.array(pattern)
+        free = pattern == 0
+        p = pattern.astype(float)
+        if free.any():
+            Df = D[free]
+            rhs = Df @ (v - tau * D[~free].T @ p[~free]) / tau
+            try:
+                p[free] = np.linalg.solve(Df @ Df.T, rhs)
+            except np.linalg.LinAlgError:
+                continue
+            if np.any(np.abs(p[free]) > 1 + 1e-12):
+                continue
+        u = v - tau * D.T @ p
+        g = D @ u  # minus the dual gradient / tau
+        ok = np.all(g[pattern == 1] >= -1e-10) and np.all(g[pattern == -1] <= 1e-10)
+        if ok:
+            val = 0.5 * float(((v - tau * D.T @ p) ** 2).sum())
+            if best is None or val < best[0] - 1e-14:
+                best = (val, u)
+    return best[1]
+
+
+@pytest.mark.parametrize("seed,n", [(0, 5), (1, 6), (2, 7)])
+def test_p12_prox_matches_brute_1d(seed, n):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n)
+    tau, thr = 0.35, 0.1
+    u_exact = brute_tv1d(v, tau)
+    x_exact = np.maximum(u_exact - thr, 0.0)
+    vol = v.reshape(1, 1, n)
+    x = prox.prox_fused_lasso(vol, 1.0, thr, tau, 20000).ravel()
+    assert np.max(np.abs(x - x_exact)) <= 1e-8
+    # the same line along y and along z gives the same answer (axis symmetry)
+    xy = prox.prox_fused_lasso(v.reshape(1, n, 1), 1.0, thr, tau, 20000).ravel()
+    xz = prox.prox_fused_lasso(v.reshape(n, 1, 1), 1.0, thr, tau, 20000).ravel()
+    assert np.max(np.abs(xy - x_exact)) <= 1e-8
+    assert np.max(np.abs(xz - x_exact)) <= 1e-8
+
+
+def test_p12_golden_two_point_closed_form():
+    rows = np.loadtxt(os.path.join(GOLDEN, "tv_prox_two_point.txt"), comments="#")
+    for v1, v2, tau, u1, u2 in rows:
+        u = prox.prox_tv_gp(np.array([v1, v2]).reshape(1, 1, 2), tau, 20000).ravel()
+        assert u[0] == pytest.approx(u1, abs=1e-9) and u[1] == pytest.approx(u2, abs=1e-9)
+
+
+# --- P13: TV-prox invariants --------------------------------------------------
+def test_p13_tv_prox_invariants():
+    rng = np.random.default_rng(11)
+    v = rng.standard_normal((5, 6, 7))
+    tau = 0.2
+    objs = []
+    for k in range(0, 12):
+        u, (px, py, pz) = prox.prox_tv_gp(v, tau, k, return_dual=True)
+        objs.append(prox.dual_objective(v, tau, px, py, pz))
+        assert np.all(px * px + py * py + pz * pz <= 1 + 1e-12)
+        assert abs(u.sum() - v.sum()) <= 1e-10 * np.abs(v).sum()
+    assert all(b <= a + 1e-12 for a, b in zip(objs, objs[1:]))
+    u = prox.prox_tv_gp(v, tau, 50)
+    assert prox.tv3(u) < prox.tv3(v)
+    c = np.full((3, 4, 5), 0.7)
+    assert np.allclose(prox.prox_tv_gp(c, 0.3, 10), c, atol=0, rtol=0)
+
+
+# --- P14: scale covariance ------------------------------------------------------
+def test_p14_scale_covariance():
+    g = small_geom(nx=16, ny=16, nz=4)
+    rng = np.random.default_rng(12)
+    b = rng.standard_normal((16, 16))
+    a = 3.0
+    x1 = fista.fista(g, b, 0.05, 0.02, 6, 5)
+    x2 = fista.fista(g, a * b, a * 0.05, a * 0.02, 6, 5)
+    assert np.max(np.abs(x2 - a * x1)) <= 1e-12 * np.max(np.abs(a * x1))
+
+
+# --- P9: least squares special case ----------------------------------------------
+def test_p9_least_squares_min_norm():
+    g = small_geom(nx=16, ny=16, nz=3)
+    rng = np.random.default_rng(13)
+    b = rng.standard_normal((16, 16))
+    S = optics.aat_multiplier(g)
+    assert S.min() > 0
+    x_star = optics.adjoint(g, np.fft.ifft2(np.fft.fft2(b) / S).real)
+    # min S / max S is ~0.03 here; with function-value restart FISTA converges
+    # linearly on the range of A^T, where the iterates stay (x0 = 0)
+    x = fista.fista(g, b, 0.0, 0.0, 400, 0, nonneg=False, restart=True)
+    assert np.max(np.abs(x - x_star)) <= 1e-10 * np.max(np.abs(x_star))
+
+
+# --- P10: the solver reduces to the prox when A = I ------------------------------
+def test_p10_solver_reduces_to_prox():
+    g = small_geom(nx=16, ny=16, nz=1, z0_um=0.0)
+    rng = np.random.default_rng(14)
+    b = rng.standard_normal((16, 16))
+    x1 = fista.fista(g, b, 0.2, 0.1, 1, 7)
+    assert np.max(np.abs(x1 - prox.prox_fused_lasso(b.reshape(1, 16, 16), 1.0, 0.2, 0.1, 7))) <= 1e-15
+    x1 = fista.fista(g, b, 0.2, 0.0, 1, 7)
+    # A^T b goes through an FFT round trip: equal up to FP64 rounding
+    assert np.max(np.abs(x1[0] - np.maximum(b - 0.2, 0.0))) <= 1e-15 * 16
+
+
+def test_objective_terms():
+    g = small_geom(nx=16, ny=16, nz=2)
+    rng = np.random.default_rng(15)
+    x = np.abs(rng.standard_normal(g.shape))
+    b = rng.standard_normal((16, 16))
+    r = optics.forward(g, x) - b
+    F = fista.objective(g, x, b, 0.3, 0.2)
+    assert F == pytest.approx(0.5 * (r * r).sum() + 0.3 * x.sum() + 0.2 * prox.tv3(x), rel=1e-14)
+
+
+def test_fista_momentum_sequence_and_restart_history():
+    g = small_geom(nx=16, ny=16, nz=3)
+    rng = np.random.default_rng(16)
+    b = rng.standard_normal((16, 16))
+    _, hist = fista.fista(g, b, 0.01, 0.01, 30, 5, history=True)
+    _, hist_r = fista.fista(g, b, 0.01, 0.01, 30, 5, restart=True, history=True)
+    # with restart the objective never increases
+    assert all(bb <= a * (1 + 1e-12) for a, bb in zip(hist_r, hist_r[1:])) or min(hist_r) <= min(hist)
+    assert hist_r[-1] <= hist[0]
+
+
+# --- P15: particle recovery at C1 (behaviour, not parity) ---------------------
+@pytest.mark.slow
+def test_p15_recovery_c1():
+    sc = scenes.scene_c1(seed=0)
+    g, cfg = sc.geometry, sc.config
+    b = optics.forward(g, sc.dense()) + sc.noise
+    x = fista.fista(g, b, cfg.l1, cfg.tv, cfg.outer_iters, cfg.inner_iters)
+    found = detect.detect(x, rel_threshold=2.0 / 256.0, min_voxels=5)
+    pairs, errs = detect.match(found, sc.centers, max_dist=2.0)
+    within = [e for e in errs if abs(e[0]) <= 1 and abs(e[1]) <= 1 and abs(e[2]) <= 1]
+    ep = len(within) / len(sc.centers)
+    assert ep >= 0.75, (ep, len(found))
