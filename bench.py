@@ -1,0 +1,219 @@
+"""Benchmark: holograms/s to objective gap 1e-4 at 1024^2 x 256 on one MI355X.
+
+One step = one full FISTA solve of a synthetic 1024x1024 hologram into 256
+planes (2000 opaque disk particles, C2 optics), from a cold start until the
+relative objective gap to a reference value is <= 1e-4.  The reference value is
+the smallest objective of a longer function-value-restarted run with the same
+prox, computed before the timed region.  Inputs are resident in HBM when the
+timer starts.
+
+Prints one JSON line (stdout).  Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "holograms/s to objective gap 1e-4 at 1024²×256; voxel-iters/s vs plain FISTA"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def prox_bytes_per_voxel(k_in: int, kb: int) -> float:
+    """Bytes each voxel must move through HBM in one prox application, by design.
+
+    Passes of `kb` fused dual steps: the first reads v and writes p (16 B), the
+    middle ones read v, p and write p (28 B), the last reads v, p and writes x
+    (20 B); with a single pass, read v and write x (8 B).
+    """
+    passes = max(1, -(-k_in // kb))
+    if k_in == 0:
+        return 8.0
+    if passes == 1:
+        return 8.0
+    return 16.0 + 28.0 * (passes - 2) + 20.0
+
+
+def build_scene(torch, rihvr, scenes, plan, seed):
+    g = scenes.geometry_c2()
+    sc = scenes.scene_c2(seed=seed)
+    lin = np.ravel_multi_index((sc.idx[:, 0], sc.idx[:, 1], sc.idx[:, 2]), g.shape)
+    x_true = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+    x_true.view(-1)[torch.from_numpy(lin).cuda()] = torch.from_numpy(sc.val.astype(np.float32)).cuda()
+    b = plan.forward(x_true)
+    b += torch.from_numpy(sc.noise.astype(np.float32)).cuda()
+    torch.cuda.synchronize()
+    return sc, x_true, b
+
+
+def cpu_baseline(scenes, iters_to_gap, nvox_full, cfg):
+    """The FP64 oracle on a bounded sample: one FISTA iteration on a slab of the
+    full geometry (same lateral size and optics, 8 planes)."""
+    import oracle
+    g = scenes.geometry_c2().with_(nz=8)
+    rng = np.random.default_rng(0)
+    b = 0.05 * rng.standard_normal((g.ny, g.nx))
+    t0 = time.perf_counter()
+    oracle.fista.fista(g, b, cfg.l1, cfg.tv, 1, cfg.inner_iters)
+    dt = time.perf_counter() - t0
+    nvox = g.nx * g.ny * g.nz
+    vit = nvox / dt
+    return {
+        "value": vit / (nvox_full * max(iters_to_gap, 1)),
+        "unit": "holograms/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": (f"1 FISTA iteration (K_in={cfg.inner_iters}) of the FP64 numpy oracle on a "
+                   f"{g.nx}x{g.ny}x{g.nz} slab of the same optics ({dt:.1f} s, {vit:.3g} voxel-iters/s), "
+                   f"scaled to {iters_to_gap} iterations of {nvox_full} voxels"),
+        "voxel_iters_per_s": vit,
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--ref-iters", type=int, default=1000, help="outer iterations of the reference run")
+    ap.add_argument("--max-iters", type=int, default=1000)
+    ap.add_argument("--gap", type=float, default=1e-4)
+    ap.add_argument("--check-every", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--plain", action="store_true", help="also time plain per-frame FISTA (dense, no graph)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1904_04884_amd import rihvr, scenes
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    rihvr.lib()
+    cfg = scenes.config_c2()
+    g = scenes.geometry_c2()
+    nvox = g.nx * g.ny * g.nz
+    t0 = time.perf_counter()
+    plan = rihvr.Plan(g)
+    log(f"plan: ||A||^2 = {plan.lipschitz:.6f} ({time.perf_counter() - t0:.2f} s)")
+    sc, x_true, b = build_scene(torch, rihvr, scenes, plan, args.seed)
+    log(f"scene: {len(sc.centers)} particles, {len(sc.val)} voxels; |b| = {float(b.norm()):.4g}")
+
+    # reference objective (not timed)
+    t0 = time.perf_counter()
+    _, rep_ref, _ = plan.solve(b, cfg.l1, cfg.tv, args.ref_iters, cfg.inner_iters, flags=rihvr.RI_SOLVE_RESTART)
+    torch.cuda.synchronize()
+    f_ref = rep_ref["objective_min"]
+    log(f"reference: {args.ref_iters} restarted iterations, F_ref = {f_ref:.9g} ({time.perf_counter() - t0:.1f} s)")
+
+    def one_solve(flags=0):
+        return plan.solve(b, cfg.l1, cfg.tv, args.max_iters, cfg.inner_iters, f_ref=f_ref, gap_tol=args.gap,
+                          check_every=args.check_every, flags=flags)
+
+    for w in range(args.warmup):
+        _, rep, _ = one_solve()
+        log(f"warmup {w}: {rep['iters']} iterations, gap {rep['gap']:.3g}")
+    torch.cuda.synchronize()
+    iters = []
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        _, rep, _ = one_solve()
+        iters.append(rep["iters"])
+        log(f"step {s}: {rep['iters']} iterations, gap {rep['gap']:.3g}, converged {rep['converged']}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+    mean_iters = float(np.mean(iters))
+    converged = bool(rep["converged"])
+
+    # per-phase device times (HIP events on the solve's stream), same solve
+    _, rep_t, _ = one_solve(flags=rihvr.RI_SOLVE_TIMING)
+    ph = rep_t["phase_ms"]
+    nl = rep_t["phase_launches"]
+    n_prox = max(rep_t["iters"], 1)
+    prox_ms_per_app = ph["prox"] / n_prox
+    kb = 1  # dual steps fused per prox pass
+    bytes_per_app = prox_bytes_per_voxel(cfg.inner_iters, kb) * nvox
+    prox_gbs = bytes_per_app / (prox_ms_per_app * 1e-3) / 1e9
+    roofline = {
+        "bound": "hbm",
+        "kernel": "fused-lasso prox (TV dual passes)",
+        "achieved": prox_gbs,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": prox_gbs / HBM_PEAK_GBS,
+        "traffic": None,
+        "launch_ms": ph["prox"] / max(nl["prox"], 1),
+        "bytes_per_voxel": prox_bytes_per_voxel(cfg.inner_iters, kb),
+    }
+    phase_ms_per_iter = {k: v / n_prox for k, v in ph.items()}
+    log("phase ms / iteration: " + ", ".join(f"{k} {v:.3f}" for k, v in phase_ms_per_iter.items()))
+
+    plain = None
+    if args.plain:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rep_p, _ = one_solve(flags=rihvr.RI_SOLVE_DENSE | rihvr.RI_SOLVE_NO_GRAPH)
+        torch.cuda.synchronize()
+        dtp = time.perf_counter() - t1
+        plain = {"holograms_per_s": 1.0 / dtp, "iters": rep_p["iters"],
+                 "voxel_iters_per_s": nvox * rep_p["iters"] / dtp}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        cpu = cpu_baseline(scenes, int(round(mean_iters)), nvox, cfg)
+        log(f"cpu baseline: {cpu['voxel_iters_per_s']:.3g} voxel-iters/s")
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "holograms/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "C2: 1024x1024 hologram, 256 planes (z 5000+50j um, lambda 0.532 um, 5 um px), "
+                        "2000 disk particles d~U[2,6] px, noise 0.02, l1 0.02, tv 0.01, K_in 20, cold start, "
+                        "gap 1e-4 vs restarted reference",
+            "nx": g.nx, "ny": g.ny, "nz": g.nz, "seed": args.seed,
+        },
+        "iters_to_gap": mean_iters,
+        "converged": converged,
+        "voxel_iters_per_s": nvox * mean_iters * value,
+        "f_ref": f_ref,
+        "empty_row_frac": rep["empty_row_frac"],
+        "empty_plane_frac": rep["empty_plane_frac"],
+        "phase_ms_per_iter": phase_ms_per_iter,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    if plain is not None:
+        out["plain_fista"] = plain
+    plan.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * rihvr.h - C ABI of the MI355X regularized inverse holographic volume
+ * reconstruction library (Mallery & Hong, "Regularized Inverse Holographic
+ * Volume Reconstruction for 3D Particle Tracking").
+ *
+ * The library solves, for one hologram b of ny x nx pixels, the problem of the
+ * paper's Eq. (2) with the fused-lasso regulariser of Eq. (5) and a
+ * non-negativity constraint:
+ *
+ *     min_x  1/2 ||A x - b||^2 + l1 * sum(x) + tv * TV3D(x),   x >= 0,
+ *
+ * where x is a real volume of nz planes and A is the linearised hologram
+ * formation model (section "Methodology"): angular-spectrum propagation of
+ * every plane j to the sensor and a sum over planes,
+ *
+ *     A x = Re( sum_j IFFT2( FFT2(x_j) . H_j ) ),
+ *     H_j(f) = exp(i 2 pi z_j sqrt(1/lambda^2 - fx^2 - fy^2)),  z_j = z0 + j dz,
+ *
+ * with an unscaled forward and 1/(nx ny)-scaled inverse DFT on the fftfreq
+ * grid.  TV3D is the isotropic total variation of Eq. (4) taken over forward
+ * differences along x, y and z (last difference on each axis zero).
+ *
+ * Conventions shared by every entry point:
+ *   - Array arguments are DEVICE pointers to C-contiguous float32 arrays:
+ *     volumes are [nz][ny][nx], holograms [ny][nx] (x fastest).
+ *   - The caller owns every buffer.  The library allocates device memory only
+ *     in ri_plan_create (phase and twiddle tables, a small state block) and
+ *     frees it in ri_plan_destroy; the hot path never allocates.  Scratch space
+ *     comes from the caller through (ws, ws_bytes); query ri_workspace_size.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t, NULL for
+ *     the default stream), except where stated.  A plan, and the workspace
+ *     handed to it, may be used by one stream at a time.
+ *   - Every call validates its arguments before launching anything and returns
+ *     a status; on failure nothing has been launched and ri_last_error() holds
+ *     a thread-local message.  HIP runtime failures map to RI_ERR_HIP.
+ *   - Supported sizes: nx and ny of the form 2^a or 3 * 2^a, 16 <= nx <= 2048,
+ *     16 <= ny <= 2048; nz >= 1.
+ */
+#ifndef RIHVR_H
+#define RIHVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RI_OK = 0,
+  RI_ERR_INVALID_ARG = 1,        /* null pointer, bad value, aliasing not allowed */
+  RI_ERR_UNSUPPORTED_SIZE = 2,   /* nx / ny outside the supported set */
+  RI_ERR_OUT_OF_MEMORY = 3,      /* plan tables could not be allocated */
+  RI_ERR_WORKSPACE_TOO_SMALL = 4,
+  RI_ERR_HIP = 5,                /* HIP runtime error; see ri_last_error */
+  RI_ERR_NONFINITE = 6,          /* the objective became NaN / Inf during a solve */
+  RI_ERR_NOT_CONVERGED = 7       /* the objective diverged (grew past 10x F(x0)) */
+} ri_status;
+
+/* Geometry flags */
+#define RI_NO_CARRIER 0x1u  /* drop the exp(i 2 pi z / lambda) carrier from H_j */
+
+typedef struct {
+  int32_t nx, ny, nz;       /* hologram width, height; number of planes */
+  double pixel_um;          /* lateral pixel pitch, micrometres */
+  double wavelength_um;     /* illumination wavelength, micrometres */
+  double z0_um, dz_um;      /* plane j at z0 + j*dz from the sensor */
+  uint32_t flags;           /* RI_NO_CARRIER */
+} ri_geometry;
+
+/* Fused-lasso proximal operator settings (Eq. 5, Eq. 6). */
+typedef struct {
+  double l1;                /* l1 weight */
+  double tv;                /* total-variation weight */
+  int32_t inner_iters;      /* gradient-projection steps on the TV dual, >= 0 */
+  int32_t nonneg;           /* 1: x >= 0 (soft threshold max(u - t l1, 0)); 0: signed */
+} ri_prox_params;
+
+/* Solve settings */
+#define RI_INIT_ZERO  0     /* start from x0 = 0 */
+#define RI_INIT_GIVEN 1     /* start from the contents of x_inout */
+
+#define RI_SOLVE_DENSE    0x1u  /* do not skip empty rows / planes in A */
+#define RI_SOLVE_NO_GRAPH 0x2u  /* launch kernels one by one instead of replaying a HIP graph */
+#define RI_SOLVE_RESTART  0x4u  /* function-value restart of the momentum (reference runs) */
+#define RI_SOLVE_TIMING   0x8u  /* time each phase with HIP events (report.phase_ms) */
+
+typedef struct {
+  double l1, tv;            /* regularisation weights */
+  int32_t max_iters;        /* outer FISTA iterations (upper bound) */
+  int32_t inner_iters;      /* TV dual steps per outer iteration */
+  double gap_tol;           /* stop once (F(x_k) - f_ref) / |f_ref| <= gap_tol ... */
+  double f_ref;             /* ... when f_ref > 0; otherwise run max_iters */
+  int32_t init;             /* RI_INIT_ZERO | RI_INIT_GIVEN */
+  int32_t check_every;      /* host reads the device stop flag every this many iterations (>= 1) */
+  uint32_t flags;           /* RI_SOLVE_* */
+  int32_t nonneg;           /* 1: x >= 0 (the problem above); 0: signed soft threshold */
+} ri_solve_params;
+
+#define RI_NUM_PHASES 6     /* forward, hologram, adjoint, prox, objective, other */
+
+typedef struct {
+  int32_t iters;            /* outer iterations performed (prox applications) */
+  int32_t converged;        /* 1 if the gap criterion was met */
+  double objective;         /* F of the returned iterate (FP64 accumulation) */
+  double objective_min;     /* smallest F over the evaluated iterates */
+  double gap;               /* (objective - f_ref) / f_ref, or NaN if f_ref <= 0 */
+  double lipschitz;         /* ||A||^2 used for the step t = 1/||A||^2 */
+  double empty_plane_frac;  /* of the returned iterate */
+  double empty_row_frac;    /* of the returned iterate */
+  double phase_ms[RI_NUM_PHASES]; /* with RI_SOLVE_TIMING: device time per phase */
+  int32_t phase_launches[RI_NUM_PHASES];
+} ri_solve_report;
+
+typedef struct ri_plan ri_plan;
+
+/* Workspace queries */
+typedef enum { RI_OP_FORWARD = 0, RI_OP_ADJOINT = 1, RI_OP_PROX = 2, RI_OP_SOLVE = 3 } ri_op;
+
+/*
+ * Create a plan for one geometry on the current HIP device: FP64 phase table
+ * theta(f) = sqrt(1/lambda^2 - f^2) - 1/lambda, per-plane carrier phases
+ * frac(z_j / lambda), FFT twiddles, and the Lipschitz constant
+ * ||A||^2 = max_f sum_j cos^2(2 pi z_j sqrt(1/lambda^2 - f^2)) (the spectrum of
+ * A A^T; the FISTA step is 1/||A||^2).  Synchronous.  *out receives the plan.
+ */
+ri_status ri_plan_create(const ri_geometry* geometry, ri_plan** out);
+ri_status ri_plan_destroy(ri_plan* plan);
+/* ||A||^2 of the plan (host value). */
+ri_status ri_plan_lipschitz(const ri_plan* plan, double* out);
+/* Bytes of scratch space that `op` needs with this plan. */
+ri_status ri_workspace_size(const ri_plan* plan, ri_op op, size_t* bytes);
+
+/*
+ * b_out = A x.  x: volume [nz][ny][nx]; b_out: hologram [ny][nx].
+ * Exact in every voxel (no sparsity skipping on this entry point).
+ * x and b_out must not overlap.
+ */
+ri_status ri_forward(ri_plan* plan, const float* x, float* b_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * x_out = A^T y, the back-propagation (A^T y)_j = Re(IFFT2(FFT2(y) . conj(H_j))).
+ * y: hologram [ny][nx]; x_out: volume [nz][ny][nx].  Must not overlap.
+ */
+ri_status ri_adjoint(ri_plan* plan, const float* y, float* x_out,
+                     void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * x_out = prox of step*(l1 ||.||_1 + tv TV3D(.)) [restricted to x >= 0] at v,
+ * the proximal operator of Eq. (6) for the fused lasso of Eq. (5): the TV prox
+ * at weight tau = step*tv by `inner_iters` gradient-projection steps on its
+ * dual (Beck & Teboulle; step 1/(12 tau), dual started at zero), followed by
+ * the soft threshold at step*l1.  v and x_out are volumes [nz][ny][nx]; they
+ * may be the same buffer (in place).
+ */
+ri_status ri_prox_fused_lasso(ri_plan* plan, const ri_prox_params* params, double step,
+                              const float* v, float* x_out,
+                              void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * FISTA solve of the problem above with constant step 1/||A||^2:
+ *   x_k = prox(y_k - t A^T (A y_k - b)),  s_{k+1} = (1 + sqrt(1 + 4 s_k^2)) / 2,
+ *   y_{k+1} = x_k + ((s_k - 1)/s_{k+1}) (x_k - x_{k-1}),
+ * from x_0 = 0 or the given x_inout.  b: hologram [ny][nx]; x_inout: volume
+ * [nz][ny][nx], overwritten with the returned iterate.  With f_ref > 0 the solve
+ * stops at the first iterate whose objective gap is <= gap_tol (checked on the
+ * device after every iteration; the host polls every check_every iterations).
+ * If `report` is non-NULL the call synchronises the stream once at the end and
+ * fills it; otherwise it returns after enqueueing (the host still polls the stop
+ * flag when f_ref > 0).
+ */
+ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const float* b, float* x_inout,
+                   void* ws, size_t ws_bytes, void* stream, ri_solve_report* report);
+
+/*
+ * Batched solve of n independent holograms that may differ in size and plane
+ * count (one plan per frame).  Frames advance in lock-step, one outer
+ * iteration for all frames at a time, each with its own step, momentum,
+ * objective and stop flag; a frame that has met its criterion does no further
+ * work.  ws must hold ri_workspace_size(plans[i], RI_OP_SOLVE) for every frame,
+ * each rounded up to 256 bytes, summed.  params[i], b[i], x_inout[i] and
+ * reports[i] (nullable array) belong to frame i.
+ */
+ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
+                           const float* const* b, float* const* x_inout,
+                           void* ws, size_t ws_bytes, void* stream, ri_solve_report* reports);
+
+const char* ri_status_string(ri_status status);
+const char* ri_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RIHVR_H */

@@ -1,0 +1,789 @@
+// HIP kernels for gfx950: the forward model A, its adjoint fused with the
+// FISTA gradient step, the hologram-space residual, objective partials and the
+// on-device FISTA scalars.
+//
+// Spectra use the packed real-to-complex layout: a real row of nx samples is
+// transformed as nx/2 complex samples z[n] = x[2n] + i x[2n+1], and its
+// spectrum is stored as m = nx/2 complex values with slot 0 holding
+// X[0] + i X[nx/2] (both real) and slots 1..m-1 holding X[1..m-1].  In 2D the
+// packed column 0 then carries the DC and Nyquist columns as one complex
+// column (each of them is the spectrum of a real sequence), so a plane's
+// half spectrum is exactly ny x m complex values, the same bytes as the real
+// plane.
+//
+// Because the fftfreq grid is symmetric and H_j(f) = H_j(-f), for real x
+// Re(IFFT2(FFT2(x) H_j)) = IFFT2(FFT2(x) cos(phi_j)), phi_j = arg H_j, so both A
+// and A^T apply the real, even filter cos(phi_j) to half spectra.  For the packed
+// column 0 the DC and Nyquist columns get different filters c0, cN; with
+// Z = FFT(dc) + i FFT(nyq), the filtered packed column is
+// ((c0 + cN)/2) Z[ky] + ((c0 - cN)/2) conj(Z[-ky]).
+//
+// The phase phi_j(f) = 2 pi (c_j + z_j theta(f)), theta(f) = sqrt(1/lambda^2 -
+// f^2) - 1/lambda, c_j = frac(z_j / lambda), reaches ~10^2 cycles, so it is
+// reduced modulo one cycle in FP64 before an FP32 cospi.
+#include "rihvr_internal.h"
+#include "fft_device.h"
+
+namespace rihvr {
+
+// ---------------------------------------------------------------------------
+// Launch-shape choices
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int kRowThreads(int m) { return m / points_per_thread(m); }
+__host__ __device__ constexpr int kRowsPerBlock(int m) {
+  return kRowThreads(m) >= 256 ? 1 : 256 / kRowThreads(m);
+}
+// Column transforms: points per thread, and columns per tile such that a block
+// has at most 512 threads (256 VGPRs per lane available, no spills) and the tile
+// plus one spare column fits the 160 KiB of LDS.
+__host__ __device__ constexpr int kColP(int ny) { return (ny % 3 == 0) ? 12 : (ny >= 1024 ? 16 : 8); }
+__host__ __device__ constexpr int kColW(int ny) {
+  int w = 16;
+  while (w > 1 && ((ny / kColP(ny)) * w > 512 || (size_t)ny * (w + 1) * 8 > 160 * 1024)) w /= 2;
+  return w;
+}
+
+int rows_per_block(int m) { return kRowsPerBlock(m); }
+int col_tile_width(int ny) { return kColW(ny); }
+bool fft_len_supported(int L) {
+  switch (L) {
+    case 8: case 16: case 32: case 64: case 128: case 256: case 512: case 1024: case 2048:
+    case 24: case 48: case 96: case 192: case 384: case 768: case 1536:
+      return true;
+    default: return false;
+  }
+}
+
+__device__ __forceinline__ float phase_cos(double z, double c, double th) {
+  double ph = fma(z, th, c);
+  ph -= floor(ph);
+  return cospif(2.0f * (float)ph);
+}
+
+__device__ __forceinline__ bool solve_done(const SolveState* st) {
+  return st != nullptr && st->done != 0;
+}
+
+// Block-wide FP64 sum; result valid in thread 0.
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  constexpr int NW = (NT + 63) / 64;
+  if constexpr (NW > 1) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) red[wid] = v;
+    __syncthreads();
+    v = 0.0;
+    if (threadIdx.x < NW) v = red[threadIdx.x];
+    if (wid == 0) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    }
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Packed R2C of real rows.  Block: ROWS rows x T threads; each row in LDS.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
+k_rows_r2c(RowsR2CArgs a, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M);
+  __shared__ float2 lds[ROWS][M];
+  if (solve_done(a.st)) return;
+  const int r = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * ROWS + r;
+  const bool active = row < a.nrows && (a.rowflag == nullptr || a.rowflag[row] != 0);
+  if (!__syncthreads_or(active)) return;
+  float2* buf = lds[r];
+  if (a.mode != 1) {
+    const float* xin = a.x;
+    if (a.mode == 2) xin = a.xs[a.st->it % 3];   // solver iterate, before the scalar kernel
+    const float2* src = reinterpret_cast<const float2*>(xin) + (size_t)row * M;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int e = t + s * T;
+      buf[e] = active ? src[e] : make_float2(0.f, 0.f);
+    }
+  } else {
+    const SolveState* st = a.st;
+    const float beta = (float)st->beta;
+    const float2* c0 = reinterpret_cast<const float2*>(st->ax_cur ? a.ax1 : a.ax0) + (size_t)row * M;
+    const float2* c1 = reinterpret_cast<const float2*>(st->ax_prev ? a.ax1 : a.ax0) + (size_t)row * M;
+    const float2* bb = reinterpret_cast<const float2*>(a.b) + (size_t)row * M;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int e = t + s * T;
+      float2 v = make_float2(0.f, 0.f);
+      if (active) {
+        float2 xc = c0[e], xp = c1[e], bv = bb[e];
+        v.x = xc.x + beta * (xc.x - xp.x) - bv.x;
+        v.y = xc.y + beta * (xc.y - xp.y) - bv.y;
+      }
+      buf[e] = v;
+    }
+  }
+  __syncthreads();
+  fft_lds<M, P, 1, 2, false>(buf, t, tw);
+  if (!active) return;  // no barriers below
+  float2* dst = a.out + (size_t)row * M;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int k = t + s * T;
+    const float2 zk = buf[k];
+    float2 o;
+    if (k == 0) {
+      o = make_float2(zk.x + zk.y, zk.x - zk.y);
+    } else {
+      const float2 zm = cconj(buf[M - k]);
+      const float2 e = cscale(cadd(zk, zm), 0.5f);
+      const float2 d = csub(zk, zm);
+      const float2 od = make_float2(0.5f * d.y, -0.5f * d.x);  // (zk - zm) / (2i)
+      o = cadd(e, cmul(tw[k], od));
+    }
+    dst[k] = o;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Packed C2R of rows (scaled).  Inverse of k_rows_r2c up to the scale.
+// ---------------------------------------------------------------------------
+template <int M>
+__device__ __forceinline__ void c2r_prepare(float2* buf, int t, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(M), T = M / P;
+  float2 zt[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int k = t + s * T;
+    const float2 xk = buf[k];
+    if (k == 0) {
+      zt[s] = make_float2(xk.x + xk.y, xk.x - xk.y);
+    } else {
+      const float2 xc = cconj(buf[M - k]);
+      const float2 sum = cadd(xk, xc), dif = csub(xk, xc);
+      const float2 wd = cmulc(dif, tw[k]);             // exp(+2 pi i k / nx) * dif
+      zt[s] = make_float2(sum.x - wd.y, sum.y + wd.x);  // sum + i wd
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < P; ++s) buf[t + s * T] = zt[s];
+  __syncthreads();
+}
+
+template <int M>
+__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
+k_rows_c2r(RowsC2RArgs a, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M), NT = ROWS * T;
+  __shared__ float2 lds[ROWS][M];
+  __shared__ double red[16];
+  if (solve_done(a.st)) return;
+  const int r = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * ROWS + r;
+  const bool active = row < a.nrows;
+  float2* buf = lds[r];
+  const float2* src = a.in + (size_t)row * M;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int e = t + s * T;
+    buf[e] = active ? src[e] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  c2r_prepare<M>(buf, t, tw);
+  fft_lds<M, P, 1, 2, true>(buf, t, tw);
+  if (a.mode == 0) {
+    if (!active) return;
+    float2* dst = reinterpret_cast<float2*>(a.out) + (size_t)row * M;
+#pragma unroll
+    for (int s = 0; s < P; ++s) dst[t + s * T] = cscale(buf[t + s * T], a.scale);
+    return;
+  }
+  double acc = 0.0;
+  if (active) {
+    // runs before the scalar kernel of the iteration: A x_it goes to slot it & 1
+    float2* dst = reinterpret_cast<float2*>((a.st->it & 1) ? a.ax1 : a.ax0) + (size_t)row * M;
+    const float2* bb = reinterpret_cast<const float2*>(a.b) + (size_t)row * M;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int e = t + s * T;
+      const float2 v = cscale(buf[e], a.scale);
+      dst[e] = v;
+      const float2 bv = bb[e];
+      const double dx = (double)v.x - (double)bv.x, dy = (double)v.y - (double)bv.y;
+      acc += dx * dx + dy * dy;
+    }
+  }
+  acc = block_sum<NT>(acc, red);
+  if (threadIdx.x == 0) a.partial[blockIdx.x] = 0.5 * acc;
+}
+
+// ---------------------------------------------------------------------------
+// Forward column pass with the propagation filter and the sum over planes.
+// Block: W columns x TC threads per column (TC = NY / P).
+// ---------------------------------------------------------------------------
+template <int NY>
+__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
+k_fwd_cols(FwdColsArgs a, PlanTables pt) {
+  constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
+  __shared__ float2 lds[NY * W];
+  if (solve_done(a.st)) return;
+  const int w = threadIdx.x % W, q = threadIdx.x / W;
+  const int m = a.m;
+  const int kx = blockIdx.x * W + w;
+  const bool colok = kx < m;           // tiles may overhang the last column
+  const bool col0 = (kx == 0);
+  double th[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) th[s] = colok ? pt.theta[(size_t)(q + s * TC) * (m + 1) + kx] : 0.0;
+  float2 acc[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) acc[s] = make_float2(0.f, 0.f);
+  const int j0 = blockIdx.y * a.planes_per_chunk;
+  const int j1 = min(a.nz, j0 + a.planes_per_chunk);
+  for (int j = j0; j < j1; ++j) {
+    if (a.planeflag != nullptr && a.planeflag[j] == 0) continue;
+    const float2* src = a.t + (size_t)j * NY * m + kx;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int y = q + s * TC;
+      const bool on = colok && (a.rowflag == nullptr || a.rowflag[(size_t)j * NY + y] != 0);
+      lds[y * W + w] = on ? src[(size_t)y * m] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+    const double2 zc = pt.zc[j];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int y = q + s * TC;
+      const float2 v = lds[y * W + w];
+      const float c = phase_cos(zc.x, zc.y, th[s]);
+      if (!col0) {
+        acc[s].x += c * v.x;
+        acc[s].y += c * v.y;
+      } else {
+        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float2 vn = cconj(lds[((NY - y) % NY) * W]);
+        const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
+        acc[s].x += ca * v.x + cb * vn.x;
+        acc[s].y += ca * v.y + cb * vn.y;
+      }
+    }
+    __syncthreads();
+  }
+  if (!colok) return;
+  float2* dst = a.gp + (size_t)blockIdx.y * NY * m + kx;
+#pragma unroll
+  for (int s = 0; s < P; ++s) dst[(size_t)(q + s * TC) * m] = acc[s];
+}
+
+// ---------------------------------------------------------------------------
+// Sum of partial spectra and inverse column FFT (hologram sized).
+// ---------------------------------------------------------------------------
+template <int NY>
+__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
+k_holo_cols_inv(HoloColsInvArgs a, PlanTables pt) {
+  constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
+  __shared__ float2 lds[NY * W];
+  if (solve_done(a.st)) return;
+  const int w = threadIdx.x % W, q = threadIdx.x / W;
+  const int m = a.m;
+  const int kx = blockIdx.x * W + w;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int y = q + s * TC;
+    float2 v = make_float2(0.f, 0.f);
+    if (kx < m)
+      for (int c = 0; c < a.nchunk; ++c) v = cadd(v, a.gp[((size_t)c * NY + y) * m + kx]);
+    lds[y * W + w] = v;
+  }
+  __syncthreads();
+  fft_lds<NY, P, W, 1, true>(lds + w, q, pt.tw_col);
+  if (kx >= m) return;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int y = q + s * TC;
+    a.gi[(size_t)y * m + kx] = lds[y * W + w];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint column pass.  The residual spectrum of the tile is computed once
+// (column FFT of its packed row spectra) and kept in registers; every plane of
+// the chunk multiplies it by cos(phase_j) and inverse-transforms the columns.
+// ---------------------------------------------------------------------------
+template <int NY>
+__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
+k_adj_cols(AdjColsArgs a, PlanTables pt) {
+  constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
+  __shared__ float2 lds[NY * W];
+  __shared__ float2 r0[NY];
+  if (solve_done(a.st)) return;
+  const int w = threadIdx.x % W, q = threadIdx.x / W;
+  const int m = a.m;
+  const int kx = blockIdx.x * W + w;
+  const bool colok = kx < m;
+  const bool col0 = (kx == 0);
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int y = q + s * TC;
+    lds[y * W + w] = colok ? a.th[(size_t)y * m + kx] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+  float2 rh[P];
+  double th[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int y = q + s * TC;
+    rh[s] = lds[y * W + w];
+    if (w == 0) r0[y] = rh[s];
+    th[s] = colok ? pt.theta[(size_t)y * (m + 1) + kx] : 0.0;
+  }
+  __syncthreads();
+  const int j0 = blockIdx.y * a.planes_per_chunk;
+  const int j1 = min(a.nz, j0 + a.planes_per_chunk);
+  for (int j = j0; j < j1; ++j) {
+    const double2 zc = pt.zc[j];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int y = q + s * TC;
+      const float c = phase_cos(zc.x, zc.y, th[s]);
+      float2 v;
+      if (!col0) {
+        v = cscale(rh[s], c);
+      } else {
+        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float2 vn = cconj(r0[(NY - y) % NY]);
+        const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
+        v = make_float2(ca * rh[s].x + cb * vn.x, ca * rh[s].y + cb * vn.y);
+      }
+      lds[y * W + w] = v;
+    }
+    __syncthreads();
+    fft_lds<NY, P, W, 1, true>(lds + w, q, pt.tw_col);
+    float2* dst = a.u + (size_t)j * NY * m + kx;
+    if (colok) {
+#pragma unroll
+      for (int s = 0; s < P; ++s) {
+        const int y = q + s * TC;
+        dst[(size_t)y * m] = lds[y * W + w];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Adjoint row pass: packed C2R, then either store A^T r or the gradient step
+// v = y - t A^T r with the extrapolated point y formed on the fly.
+// ---------------------------------------------------------------------------
+template <int M>
+__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
+k_adj_rows(AdjRowsArgs a, const float2* __restrict__ tw) {
+  constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M);
+  __shared__ float2 lds[ROWS][M];
+  if (solve_done(a.st)) return;
+  const int r = threadIdx.x / T, t = threadIdx.x % T;
+  const int row = blockIdx.x * ROWS + r;
+  const bool active = row < a.nrows;
+  float2* buf = lds[r];
+  const float2* src = a.u + (size_t)row * M;
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int e = t + s * T;
+    buf[e] = active ? src[e] : make_float2(0.f, 0.f);
+  }
+  __syncthreads();
+  c2r_prepare<M>(buf, t, tw);
+  fft_lds<M, P, 1, 2, true>(buf, t, tw);
+  if (!active) return;
+  if (a.mode == 0) {
+    float2* dst = reinterpret_cast<float2*>(a.out) + (size_t)row * M;
+#pragma unroll
+    for (int s = 0; s < P; ++s) dst[t + s * T] = cscale(buf[t + s * T], a.scale);
+    return;
+  }
+  const SolveState* st = a.st;
+  float* xs[3] = {a.x0, a.x1, a.x2};
+  const float2* xc = reinterpret_cast<const float2*>(xs[st->cur]) + (size_t)row * M;
+  float2* xp = reinterpret_cast<float2*>(xs[st->prev]) + (size_t)row * M;
+  const float beta = (float)st->beta;
+  const float gs = (float)(a.step * (double)a.scale);
+#pragma unroll
+  for (int s = 0; s < P; ++s) {
+    const int e = t + s * T;
+    const float2 g = buf[e];
+    const float2 c = xc[e], p = xp[e];
+    float2 v;
+    v.x = c.x + beta * (c.x - p.x) - gs * g.x;
+    v.y = c.y + beta * (c.y - p.y) - gs * g.y;
+    xp[e] = v;
+  }
+  if (t == 0) {
+    a.rowflag[row] = 0;
+    if (row % a.ny == 0) a.planeflag[row / a.ny] = 0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Objective partials of a volume: sum(x) and TV3D(x) (forward differences,
+// zero past the last index).  One block per 4 rows (z, y).
+// ---------------------------------------------------------------------------
+constexpr int kObjRows = 4;
+constexpr int kObjThreads = 256;
+
+__global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) {
+  __shared__ double red[2][16];
+  if (solve_done(a.st)) return;
+  const float* x = a.x0;
+  if (a.st != nullptr) {
+    // runs before the scalar kernel of the iteration: the iterate is slot it % 3
+    const float* xs[3] = {a.x0, a.x1, a.x2};
+    x = xs[a.st->it % 3];
+  }
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const long nrows = (long)ny * nz;
+  double s_acc = 0.0, t_acc = 0.0;
+  for (int rr = 0; rr < kObjRows; ++rr) {
+    const long row = (long)blockIdx.x * kObjRows + rr;
+    if (row >= nrows) break;
+    const int z = (int)(row / ny), y = (int)(row % ny);
+    const bool has_y = y + 1 < ny, has_z = z + 1 < nz;
+    bool any = true;
+    bool f0 = true, fy = has_y, fz = has_z;
+    if (a.rowflag != nullptr) {
+      f0 = a.rowflag[row] != 0;
+      fy = has_y && a.rowflag[row + 1] != 0;
+      fz = has_z && a.rowflag[row + ny] != 0;
+      any = f0 || fy || fz;
+    }
+    if (!any) continue;
+    const float* r0 = x + (size_t)row * nx;
+    for (int i = threadIdx.x; i < nx; i += kObjThreads) {
+      const float v = f0 ? r0[i] : 0.f;
+      const float vx = (f0 && i + 1 < nx) ? r0[i + 1] : 0.f;
+      const float gx = (i + 1 < nx) ? vx - v : 0.f;
+      const float gy = has_y ? ((fy ? r0[i + nx] : 0.f) - v) : 0.f;
+      const float gz = has_z ? ((fz ? r0[(size_t)ny * nx + i] : 0.f) - v) : 0.f;
+      s_acc += (double)v;
+      t_acc += sqrt((double)gx * gx + (double)gy * gy + (double)gz * gz);
+    }
+  }
+  s_acc = block_sum<kObjThreads>(s_acc, red[0]);
+  __syncthreads();
+  t_acc = block_sum<kObjThreads>(t_acc, red[1]);
+  if (threadIdx.x == 0) {
+    a.psum[blockIdx.x] = s_acc;
+    a.ptv[blockIdx.x] = t_acc;
+  }
+}
+
+int obj_blocks(int nx, int ny, int nz) {
+  (void)nx;
+  return (int)(((long)ny * nz + kObjRows - 1) / kObjRows);
+}
+
+// ---------------------------------------------------------------------------
+// FISTA scalars (one block).
+// ---------------------------------------------------------------------------
+constexpr int kScalarThreads = 1024;
+
+__global__ void __launch_bounds__(kScalarThreads) k_scalars(ScalarArgs a) {
+  __shared__ double red[3][16];
+  SolveState* st = a.st;
+  if (st->done) return;
+  double d = 0.0, s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < a.n_dfit; i += kScalarThreads) d += a.pdfit[i];
+  for (int i = threadIdx.x; i < a.n_obj; i += kScalarThreads) {
+    s += a.psum[i];
+    t += a.ptv[i];
+  }
+  d = block_sum<kScalarThreads>(d, red[0]);
+  __syncthreads();
+  s = block_sum<kScalarThreads>(s, red[1]);
+  __syncthreads();
+  t = block_sum<kScalarThreads>(t, red[2]);
+  if (threadIdx.x != 0) return;
+  const double F = d + st->l1 * s + st->tv * t;
+  const int it = st->it;
+  if (it < kHistCap) a.hist[it] = F;
+  st->f_cur = F;
+  int done = 0;
+  if (!isfinite(F)) {
+    st->status = RI_ERR_NONFINITE;
+    done = 1;
+  }
+  if (it == 0) st->f_first = F;
+  else if (F > 10.0 * st->f_first && F > 0.0) {
+    st->status = RI_ERR_NOT_CONVERGED;
+    done = 1;
+  }
+  if (st->f_ref > 0.0) {
+    st->gap = (F - st->f_ref) / st->f_ref;
+    if (st->gap <= st->gap_tol) {
+      st->converged = 1;
+      done = 1;
+    }
+  }
+  if (it >= st->max_iters) done = 1;
+  // slots of this iteration: x_it in it%3, x_{it-1} in (it+2)%3, x_{it+1} -> (it+1)%3
+  st->cur = it % 3;
+  st->prev = (it + 2) % 3;
+  st->next = (it + 1) % 3;
+  st->ax_cur = it & 1;
+  st->ax_prev = (it + 1) & 1;
+  if (done) {
+    st->done = 1;
+    return;
+  }
+  double beta = 0.0;
+  if (it > 0) {
+    const double sn = 0.5 * (1.0 + sqrt(1.0 + 4.0 * st->s * st->s));
+    beta = (st->s - 1.0) / sn;
+    st->s = sn;
+    if (st->restart && F > st->f_prev) {
+      st->s = 1.0;
+      beta = 0.0;
+    }
+  }
+  st->beta = beta;
+  st->f_prev = F;
+  st->it = it + 1;
+}
+
+__global__ void k_state_init(SolveState* st, StateInit in) {
+  SolveState s = {};
+  s.it = 0;
+  s.done = 0;
+  s.converged = 0;
+  s.status = RI_OK;
+  s.cur = 0; s.prev = 2; s.next = 1;
+  s.ax_cur = 0; s.ax_prev = 1;
+  s.max_iters = in.max_iters;
+  s.restart = in.restart;
+  s.s = 1.0;
+  s.beta = 0.0;
+  s.f_prev = 0.0;
+  s.f_first = 0.0;
+  s.f_cur = 0.0;
+  s.gap = __builtin_nan("");
+  s.f_ref = in.f_ref;
+  s.gap_tol = in.gap_tol;
+  s.l1 = in.l1;
+  s.tv = in.tv;
+  *st = s;
+}
+
+// ---------------------------------------------------------------------------
+// Utility kernels
+// ---------------------------------------------------------------------------
+__global__ void k_fill_f32(float* p, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_fill_u8(uint8_t* p, size_t n, uint8_t v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = v;
+}
+__global__ void k_copy_f32(float* d, const float* s, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) d[i] = s[i];
+}
+__global__ void k_copy_final(const float* x0, const float* x1, const float* x2, float* dst, size_t n,
+                             const SolveState* st) {
+  const float* xs[3] = {x0, x1, x2};
+  const float* src = xs[st->cur];
+  if (src == dst) return;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
+}
+__global__ void k_flags_from_x(const float* x, int nx, long nrows, int ny, uint8_t* rowflag, uint8_t* planeflag) {
+  const long row = blockIdx.x;
+  if (row >= nrows) return;
+  int any = 0;
+  for (int i = threadIdx.x; i < nx; i += blockDim.x) any |= (x[(size_t)row * nx + i] != 0.f);
+  any = __syncthreads_or(any);
+  if (threadIdx.x == 0 && any) {
+    rowflag[row] = 1;
+    planeflag[row / ny] = 1;
+  }
+}
+
+static int grid_for(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
+}
+
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+hipError_t launch_copy_f32(float* d, const float* src, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_f32, dim3(grid_for(n)), dim3(256), 0, s, d, src, n);
+  return hipGetLastError();
+}
+hipError_t launch_copy_final(const float* x0, const float* x1, const float* x2, float* dst, size_t n,
+                             const SolveState* st, hipStream_t s) {
+  hipLaunchKernelGGL(k_copy_final, dim3(grid_for(n)), dim3(256), 0, s, x0, x1, x2, dst, n, st);
+  return hipGetLastError();
+}
+hipError_t launch_flags_from_x(const float* x, int nx, int ny, int nz, uint8_t* rowflag, uint8_t* planeflag,
+                               hipStream_t s) {
+  const long nrows = (long)ny * nz;
+  hipLaunchKernelGGL(k_flags_from_x, dim3((unsigned)nrows), dim3(256), 0, s, x, nx, nrows, ny, rowflag, planeflag);
+  return hipGetLastError();
+}
+hipError_t launch_state_init(SolveState* st, const StateInit& init, hipStream_t s) {
+  hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, init);
+  return hipGetLastError();
+}
+hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kScalarThreads), 0, s, a);
+  return hipGetLastError();
+}
+hipError_t launch_obj(const ObjArgs& a, int* nblocks_out, hipStream_t s) {
+  const int nb = obj_blocks(a.nx, a.ny, a.nz);
+  if (nblocks_out) *nblocks_out = nb;
+  hipLaunchKernelGGL(k_obj, dim3(nb), dim3(kObjThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Lipschitz constant: S(f) = sum_j cos^2(2 pi (c_j + z_j theta(f))) in FP64,
+// block maxima over the half-spectrum grid (the full grid is symmetric).
+// ---------------------------------------------------------------------------
+__global__ void k_lipschitz(PlanTables pt, int m, int ny, int nz, double* pmax) {
+  __shared__ double red[256];
+  const long n = (long)ny * (m + 1);
+  double best = 0.0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+    const double th = pt.theta[i];
+    double acc = 0.0;
+    for (int j = 0; j < nz; ++j) {
+      double ph = fma(pt.zc[j].x, th, pt.zc[j].y);
+      ph -= floor(ph);
+      const double c = cospi(2.0 * ph);
+      acc += c * c;
+    }
+    best = fmax(best, acc);
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) pmax[blockIdx.x] = red[0];
+}
+
+hipError_t launch_lipschitz(const PlanTables& pt, int m, int ny, int nz, double* pmax, int* nblocks,
+                            hipStream_t s) {
+  const long n = (long)ny * (m + 1);
+  int nb = (int)((n + 255) / 256);
+  if (nb > 1024) nb = 1024;
+  *nblocks = nb;
+  hipLaunchKernelGGL(k_lipschitz, dim3(nb), dim3(256), 0, s, pt, m, ny, nz, pmax);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Size dispatch
+// ---------------------------------------------------------------------------
+#define RIHVR_ROW_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) \
+  X(12) X(24) X(48) X(96) X(192) X(384) X(768)
+#define RIHVR_COL_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
+  X(24) X(48) X(96) X(192) X(384) X(768) X(1536)
+
+hipError_t launch_rows_r2c(int m, const RowsR2CArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (m) {
+#define CASE(M)                                                                           \
+  case M: {                                                                               \
+    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
+    hipLaunchKernelGGL(k_rows_r2c<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
+                       pt.tw_row);                                                        \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_ROW_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_rows_c2r(int m, const RowsC2RArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (m) {
+#define CASE(M)                                                                           \
+  case M: {                                                                               \
+    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
+    hipLaunchKernelGGL(k_rows_c2r<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
+                       pt.tw_row);                                                        \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_ROW_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adj_rows(int m, const AdjRowsArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (m) {
+#define CASE(M)                                                                           \
+  case M: {                                                                               \
+    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
+    hipLaunchKernelGGL(k_adj_rows<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
+                       pt.tw_row);                                                        \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_ROW_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_fwd_cols(int ny, int nchunk, const FwdColsArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (ny) {
+#define CASE(NY)                                                                          \
+  case NY: {                                                                              \
+    constexpr int W = kColW(NY);                                                          \
+    hipLaunchKernelGGL(k_fwd_cols<NY>, dim3((a.m + W - 1) / W, nchunk), dim3(W * (NY / kColP(NY))), 0, \
+                       s, a, pt);                                                         \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_COL_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_holo_cols_inv(int ny, const HoloColsInvArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (ny) {
+#define CASE(NY)                                                                          \
+  case NY: {                                                                              \
+    constexpr int W = kColW(NY);                                                          \
+    hipLaunchKernelGGL(k_holo_cols_inv<NY>, dim3((a.m + W - 1) / W), dim3(W * (NY / kColP(NY))), 0, s, \
+                       a, pt);                                                            \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_COL_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_adj_cols(int ny, int nchunk, const AdjColsArgs& a, const PlanTables& pt, hipStream_t s) {
+  switch (ny) {
+#define CASE(NY)                                                                          \
+  case NY: {                                                                              \
+    constexpr int W = kColW(NY);                                                          \
+    hipLaunchKernelGGL(k_adj_cols<NY>, dim3((a.m + W - 1) / W, nchunk), dim3(W * (NY / kColP(NY))), 0, \
+                       s, a, pt);                                                         \
+    return hipGetLastError();                                                             \
+  }
+    RIHVR_COL_SIZES(CASE)
+#undef CASE
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace rihvr

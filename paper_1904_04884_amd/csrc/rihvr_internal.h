@@ -1,0 +1,181 @@
+// Internal declarations shared by the C ABI (host orchestration) and the HIP
+// kernels.  Not part of the public interface.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/rihvr.h"
+
+namespace rihvr {
+
+// Solver state that lives in device memory for the duration of a solve.  All
+// control decisions (momentum, stop, buffer rotation) are taken on the device
+// so that one iteration can be replayed as a HIP graph.
+struct SolveState {
+  int32_t it;          // index of the iterate evaluated by the next objective kernel
+  int32_t done;        // 1: every kernel of the solve returns immediately
+  int32_t converged;   // gap criterion met
+  int32_t status;      // ri_status of the solve so far
+  int32_t cur, prev, next;   // volume-buffer slots for the current iteration
+  int32_t ax_cur, ax_prev;   // hologram-buffer slots
+  int32_t max_iters;
+  int32_t restart;
+  int32_t pad_;
+  double s;            // FISTA s_k
+  double beta;         // momentum of the current extrapolation
+  double f_prev;       // objective of the previous iterate
+  double f_first;      // F(x_0)
+  double f_cur;        // objective of iterate `it`
+  double gap;
+  double f_ref, gap_tol;
+  double l1, tv;
+};
+
+constexpr int kHistCap = 8192;   // objective history entries kept on the device
+
+// Device pointers of a plan's tables.
+struct PlanTables {
+  const double* theta;   // [ny][nx/2 + 1]  sqrt(1/lambda^2 - f^2) - 1/lambda  (FP64)
+  const double2* zc;     // [nz] (z_j, carrier frac(z_j / lambda) or 0)
+  const float2* tw_row;  // [nx]  exp(-2 pi i m / nx)
+  const float2* tw_col;  // [ny]  exp(-2 pi i m / ny)
+};
+
+// Launch shapes (host side mirrors of the compile-time choices).
+int rows_per_block(int m);     // rows of a length-m packed transform per row block
+int col_tile_width(int ny);    // columns per column tile
+bool fft_len_supported(int L);
+
+// ---------------------------------------------------------------------------
+// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+// ---------------------------------------------------------------------------
+// Row-wise packed R2C of real rows [nrows][2m] -> [nrows][m] complex.  Rows with
+// rowflag == 0 are skipped (nothing written).  mode 0: input x;  mode 1: input
+// r = (1+beta) ax[cur] - beta ax[prev] - b computed on the fly (solver residual);
+// mode 2: input xs[st->it % 3] (the solver iterate).
+struct RowsR2CArgs {
+  const float* x;            // mode 0 input
+  const float* xs[3];        // mode 2 inputs
+  const float* ax0; const float* ax1; const float* b;   // mode 1 inputs
+  float2* out;
+  int nrows;
+  const uint8_t* rowflag;    // nullable
+  const SolveState* st;      // nullable (mode 0 outside a solve)
+  int mode;
+};
+hipError_t launch_rows_r2c(int m, const RowsR2CArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Column FFT of the packed spectra of planes [z-chunk], multiply by cos(phase_j)
+// and sum over the planes of the chunk -> partial spectra gp[chunk][ny][m].
+struct FwdColsArgs {
+  const float2* t;           // [nz][ny][m]
+  float2* gp;                // [nchunk][ny][m]
+  int m, nz, planes_per_chunk;
+  const uint8_t* rowflag;    // nullable [nz][ny]
+  const uint8_t* planeflag;  // nullable [nz]
+  const SolveState* st;      // nullable
+};
+hipError_t launch_fwd_cols(int ny, int nchunk, const FwdColsArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Sum of nchunk partial spectra, then unscaled inverse column FFT -> gi [ny][m].
+struct HoloColsInvArgs {
+  const float2* gp; float2* gi; int m, nchunk; const SolveState* st;
+};
+hipError_t launch_holo_cols_inv(int ny, const HoloColsInvArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Row-wise packed C2R (scaled by 1/(nx ny)).  mode 0: write to out.  mode 1
+// (solver): write ax[it & 1] and a per-block FP64 partial of 1/2 sum (ax - b)^2.
+struct RowsC2RArgs {
+  const float2* in; int nrows;
+  float* out;                              // mode 0
+  float* ax0; float* ax1; const float* b;  // mode 1
+  double* partial;                         // mode 1: [nblocks]
+  const SolveState* st;
+  int mode;
+  float scale;
+};
+hipError_t launch_rows_c2r(int m, const RowsC2RArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Adjoint column pass: column FFT of the packed residual spectrum, then for each
+// plane of the chunk multiply by cos(phase_j) and inverse column FFT -> u[j].
+struct AdjColsArgs {
+  const float2* th; float2* u; int m, nz, planes_per_chunk; const SolveState* st;
+};
+hipError_t launch_adj_cols(int ny, int nchunk, const AdjColsArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Adjoint row pass: packed C2R of u[j][y] scaled by 1/(nx ny).  mode 0: out = g.
+// mode 1 (solver): v = y - step g with y = x[cur] + beta (x[cur] - x[prev]),
+// written over x[prev]; also clears the row / plane occupancy flags.
+struct AdjRowsArgs {
+  const float2* u; int nrows, ny;
+  float* out;                     // mode 0
+  float* x0; float* x1; float* x2; // mode 1: the three rotating volume buffers
+  uint8_t* rowflag; uint8_t* planeflag;
+  const SolveState* st;
+  double step;
+  int mode;
+  float scale;
+};
+hipError_t launch_adj_rows(int m, const AdjRowsArgs& a, const PlanTables& pt, hipStream_t s);
+
+// Objective pieces of a volume: per-block partials of sum(x) and TV3D(x).
+struct ObjArgs {
+  const float* x0; const float* x1; const float* x2; // slot st->it % 3 (or x0 when st null)
+  int nx, ny, nz;
+  const uint8_t* rowflag;     // nullable: skip rows whose neighbourhood is empty
+  double* psum; double* ptv;  // [nblocks]
+  const SolveState* st;
+};
+hipError_t launch_obj(const ObjArgs& a, int* nblocks_out, hipStream_t s);
+int obj_blocks(int nx, int ny, int nz);
+
+// FISTA scalars: reduce partials, objective, gap, stop flag, momentum, slots.
+struct ScalarArgs {
+  SolveState* st;
+  const double* pdfit; int n_dfit;
+  const double* psum; const double* ptv; int n_obj;
+  double* hist;   // [kHistCap]
+};
+hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
+
+struct StateInit {
+  double f_ref, gap_tol, l1, tv;
+  int32_t max_iters, restart;
+};
+hipError_t launch_state_init(SolveState* st, const StateInit& init, hipStream_t s);
+
+// Utility kernels
+hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
+hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
+// Set row / plane flags of a volume from its contents (flags must be cleared).
+hipError_t launch_flags_from_x(const float* x, int nx, int ny, int nz, uint8_t* rowflag,
+                               uint8_t* planeflag, hipStream_t s);
+// Copy the final iterate x[st->cur] into dst if it is not already there.
+hipError_t launch_copy_final(const float* x0, const float* x1, const float* x2, float* dst,
+                             size_t n, const SolveState* st, hipStream_t s);
+
+// Lipschitz constant on the device: max_f sum_j cos^2(phase_j(f)) in FP64.
+hipError_t launch_lipschitz(const PlanTables& pt, int m, int ny, int nz, double* partial_max,
+                            int* nblocks, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Fused-lasso prox (tv.hip)
+// ---------------------------------------------------------------------------
+struct ProxArgs {
+  const float* v;      // input volume (solver: slot st->prev)
+  float* x;            // output volume (solver: slot st->next)
+  float* vol[3];       // solver: the rotating volume buffers (v and x chosen on device)
+  float* p[3];         // dual components px, py, pz
+  float* u;            // scratch volume
+  uint8_t* rowflag; uint8_t* planeflag;  // nullable: set where x != 0
+  int nx, ny, nz;
+  int inner_iters;
+  int nonneg;
+  double step, l1, tv;   // outside a solve (st == nullptr)
+  const SolveState* st;  // solver: weights from st, step from `step`
+};
+hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
+
+}  // namespace rihvr

@@ -1,0 +1,296 @@
+"""Python binding of librihvr.so (ctypes).
+
+The functions `ri_*` mirror the C ABI one to one (argument marshalling only;
+pointers are plain integers, streams are hipStream_t handles as integers).
+`Plan` is a convenience wrapper that takes torch tensors: torch provides device
+memory and the current stream, every computation runs in the HIP library.
+
+Importing this module does not load the library; the first call does, and it
+raises if the library has not been built (there is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+from pathlib import Path
+
+LIB_PATH = Path(__file__).resolve().parent / "librihvr.so"
+
+# ---------------------------------------------------------------------------
+# ABI types (layouts match include/rihvr.h)
+# ---------------------------------------------------------------------------
+RI_OK = 0
+RI_ERR_INVALID_ARG = 1
+RI_ERR_UNSUPPORTED_SIZE = 2
+RI_ERR_OUT_OF_MEMORY = 3
+RI_ERR_WORKSPACE_TOO_SMALL = 4
+RI_ERR_HIP = 5
+RI_ERR_NONFINITE = 6
+RI_ERR_NOT_CONVERGED = 7
+
+RI_NO_CARRIER = 0x1
+RI_INIT_ZERO = 0
+RI_INIT_GIVEN = 1
+RI_SOLVE_DENSE = 0x1
+RI_SOLVE_NO_GRAPH = 0x2
+RI_SOLVE_RESTART = 0x4
+RI_SOLVE_TIMING = 0x8
+
+RI_OP_FORWARD, RI_OP_ADJOINT, RI_OP_PROX, RI_OP_SOLVE = 0, 1, 2, 3
+RI_NUM_PHASES = 6
+PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
+
+EXPORTED = (
+    "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size",
+    "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
+    "ri_status_string", "ri_last_error",
+)
+
+
+class ri_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("pixel_um", C.c_double), ("wavelength_um", C.c_double),
+                ("z0_um", C.c_double), ("dz_um", C.c_double), ("flags", C.c_uint32)]
+
+
+class ri_prox_params(C.Structure):
+    _fields_ = [("l1", C.c_double), ("tv", C.c_double), ("inner_iters", C.c_int32), ("nonneg", C.c_int32)]
+
+
+class ri_solve_params(C.Structure):
+    _fields_ = [("l1", C.c_double), ("tv", C.c_double), ("max_iters", C.c_int32), ("inner_iters", C.c_int32),
+                ("gap_tol", C.c_double), ("f_ref", C.c_double), ("init", C.c_int32),
+                ("check_every", C.c_int32), ("flags", C.c_uint32), ("nonneg", C.c_int32)]
+
+
+class ri_solve_report(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("objective", C.c_double),
+                ("objective_min", C.c_double), ("gap", C.c_double),
+                ("lipschitz", C.c_double), ("empty_plane_frac", C.c_double), ("empty_row_frac", C.c_double),
+                ("phase_ms", C.c_double * RI_NUM_PHASES), ("phase_launches", C.c_int32 * RI_NUM_PHASES)]
+
+    def as_dict(self):
+        return {
+            "iters": self.iters, "converged": bool(self.converged), "objective": self.objective,
+            "objective_min": self.objective_min,
+            "gap": self.gap, "lipschitz": self.lipschitz, "empty_plane_frac": self.empty_plane_frac,
+            "empty_row_frac": self.empty_row_frac,
+            "phase_ms": {n: self.phase_ms[i] for i, n in enumerate(PHASE_NAMES)},
+            "phase_launches": {n: self.phase_launches[i] for i, n in enumerate(PHASE_NAMES)},
+        }
+
+
+class RihvrError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str):
+        super().__init__(f"{where}: status {status} ({detail})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load librihvr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not LIB_PATH.exists():
+        raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_1904_04884_amd.build_lib`")
+    L = C.CDLL(str(LIB_PATH))
+    vp, sz = C.c_void_p, C.c_size_t
+    L.ri_plan_create.argtypes = [C.POINTER(ri_geometry), C.POINTER(vp)]
+    L.ri_plan_destroy.argtypes = [vp]
+    L.ri_plan_lipschitz.argtypes = [vp, C.POINTER(C.c_double)]
+    L.ri_workspace_size.argtypes = [vp, C.c_int, C.POINTER(sz)]
+    L.ri_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.ri_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.ri_prox_fused_lasso.argtypes = [vp, C.POINTER(ri_prox_params), C.c_double, vp, vp, vp, sz, vp]
+    L.ri_solve.argtypes = [vp, C.POINTER(ri_solve_params), vp, vp, vp, sz, vp, C.POINTER(ri_solve_report)]
+    L.ri_solve_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(ri_solve_params), C.POINTER(vp),
+                                   C.POINTER(vp), vp, sz, vp, C.POINTER(ri_solve_report)]
+    L.ri_status_string.argtypes = [C.c_int]
+    L.ri_status_string.restype = C.c_char_p
+    L.ri_last_error.argtypes = []
+    L.ri_last_error.restype = C.c_char_p
+    for name in EXPORTED:
+        if name not in ("ri_status_string", "ri_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, where: str):
+    if status != RI_OK:
+        L = lib()
+        raise RihvrError(status, where, f"{L.ri_status_string(status).decode()}: {L.ri_last_error().decode()}")
+
+
+# ---------------------------------------------------------------------------
+# One-to-one wrappers (raw pointers as ints)
+# ---------------------------------------------------------------------------
+def ri_plan_create(geometry: ri_geometry) -> int:
+    h = C.c_void_p()
+    _check(lib().ri_plan_create(C.byref(geometry), C.byref(h)), "ri_plan_create")
+    return h.value
+
+
+def ri_plan_destroy(plan: int) -> None:
+    _check(lib().ri_plan_destroy(plan), "ri_plan_destroy")
+
+
+def ri_plan_lipschitz(plan: int) -> float:
+    v = C.c_double()
+    _check(lib().ri_plan_lipschitz(plan, C.byref(v)), "ri_plan_lipschitz")
+    return v.value
+
+
+def ri_workspace_size(plan: int, op: int) -> int:
+    v = C.c_size_t()
+    _check(lib().ri_workspace_size(plan, op, C.byref(v)), "ri_workspace_size")
+    return v.value
+
+
+def ri_forward(plan, x, b_out, ws, ws_bytes, stream) -> int:
+    return lib().ri_forward(plan, x, b_out, ws, ws_bytes, stream)
+
+
+def ri_adjoint(plan, y, x_out, ws, ws_bytes, stream) -> int:
+    return lib().ri_adjoint(plan, y, x_out, ws, ws_bytes, stream)
+
+
+def ri_prox_fused_lasso(plan, params: ri_prox_params, step, v, x_out, ws, ws_bytes, stream) -> int:
+    return lib().ri_prox_fused_lasso(plan, C.byref(params), step, v, x_out, ws, ws_bytes, stream)
+
+
+def ri_solve(plan, params: ri_solve_params, b, x_inout, ws, ws_bytes, stream, report=None) -> int:
+    return lib().ri_solve(plan, C.byref(params), b, x_inout, ws, ws_bytes, stream,
+                          C.byref(report) if report is not None else None)
+
+
+def ri_solve_batched(n, plans, params, b, x_inout, ws, ws_bytes, stream, reports=None) -> int:
+    P = (C.c_void_p * n)(*plans)
+    Q = (ri_solve_params * n)(*params)
+    B = (C.c_void_p * n)(*b)
+    X = (C.c_void_p * n)(*x_inout)
+    return lib().ri_solve_batched(n, P, Q, B, X, ws, ws_bytes, stream, reports)
+
+
+def ri_status_string(status: int) -> str:
+    return lib().ri_status_string(status).decode()
+
+
+def ri_last_error() -> str:
+    return lib().ri_last_error().decode()
+
+
+# ---------------------------------------------------------------------------
+# torch convenience layer
+# ---------------------------------------------------------------------------
+def _stream_handle(torch):
+    return torch.cuda.current_stream().cuda_stream
+
+
+def geometry_struct(geom) -> ri_geometry:
+    """From any object with nx, ny, nz, pixel_um, wavelength_um, z0_um, dz_um[, carrier]."""
+    flags = 0 if getattr(geom, "carrier", True) else RI_NO_CARRIER
+    return ri_geometry(int(geom.nx), int(geom.ny), int(geom.nz), float(geom.pixel_um),
+                       float(geom.wavelength_um), float(geom.z0_um), float(geom.dz_um), flags)
+
+
+class Plan:
+    """A plan plus lazily allocated (torch) workspaces for one geometry."""
+
+    def __init__(self, geom):
+        import torch
+        self.torch = torch
+        self.geom = geom
+        self.handle = ri_plan_create(geometry_struct(geom))
+        self.lipschitz = ri_plan_lipschitz(self.handle)
+        self._ws = {}
+
+    def close(self):
+        if self.handle:
+            ri_plan_destroy(self.handle)
+            self.handle = None
+        self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (self.geom.nz, self.geom.ny, self.geom.nx)
+
+    def workspace(self, op: int):
+        n = ri_workspace_size(self.handle, op)
+        ws = self._ws.get(op)
+        if ws is None or ws.numel() < n:
+            ws = self.torch.empty(max(n, 1), dtype=self.torch.uint8, device="cuda")
+            self._ws[op] = ws
+        return ws, n
+
+    def _chk(self, t, shape):
+        torch = self.torch
+        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected contiguous float32 cuda tensor of shape {shape}, got "
+                             f"{tuple(t.shape)} {t.dtype} {t.device}")
+
+    def forward(self, x, out=None):
+        torch = self.torch
+        g = self.geom
+        self._chk(x, self.shape)
+        out = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda") if out is None else out
+        ws, n = self.workspace(RI_OP_FORWARD)
+        _check(ri_forward(self.handle, x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                          _stream_handle(torch)), "ri_forward")
+        return out
+
+    def adjoint(self, y, out=None):
+        torch = self.torch
+        self._chk(y, (self.geom.ny, self.geom.nx))
+        out = torch.empty(self.shape, dtype=torch.float32, device="cuda") if out is None else out
+        ws, n = self.workspace(RI_OP_ADJOINT)
+        _check(ri_adjoint(self.handle, y.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
+                          _stream_handle(torch)), "ri_adjoint")
+        return out
+
+    def prox(self, v, step, l1, tv, inner_iters, nonneg=True, out=None):
+        torch = self.torch
+        self._chk(v, self.shape)
+        out = torch.empty_like(v) if out is None else out
+        ws, n = self.workspace(RI_OP_PROX)
+        p = ri_prox_params(float(l1), float(tv), int(inner_iters), 1 if nonneg else 0)
+        _check(ri_prox_fused_lasso(self.handle, p, float(step), v.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                   ws.numel(), _stream_handle(torch)), "ri_prox_fused_lasso")
+        return out
+
+    def solve_params(self, l1, tv, max_iters, inner_iters, gap_tol=0.0, f_ref=0.0, init=RI_INIT_ZERO,
+                     check_every=10, flags=0, nonneg=True) -> ri_solve_params:
+        return ri_solve_params(float(l1), float(tv), int(max_iters), int(inner_iters), float(gap_tol),
+                               float(f_ref), int(init), int(check_every), int(flags), 1 if nonneg else 0)
+
+    def solve(self, b, l1, tv, max_iters, inner_iters, x=None, gap_tol=0.0, f_ref=0.0, check_every=10,
+              flags=0, nonneg=True, report=True, raise_on_error=True):
+        torch = self.torch
+        self._chk(b, (self.geom.ny, self.geom.nx))
+        init = RI_INIT_ZERO
+        if x is None:
+            x = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+        else:
+            self._chk(x, self.shape)
+            init = RI_INIT_GIVEN
+        ws, n = self.workspace(RI_OP_SOLVE)
+        sp = self.solve_params(l1, tv, max_iters, inner_iters, gap_tol, f_ref, init, check_every, flags, nonneg)
+        rep = ri_solve_report() if report else None
+        st = ri_solve(self.handle, sp, b.data_ptr(), x.data_ptr(), ws.data_ptr(), ws.numel(),
+                      _stream_handle(torch), rep)
+        if raise_on_error:
+            _check(st, "ri_solve")
+        return x, (rep.as_dict() if rep is not None else None), st
+
+
+def objective_gap(f, f_ref):
+    return (f - f_ref) / f_ref if f_ref > 0 else math.nan
