@@ -28,17 +28,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def prox_bytes_per_voxel(k_in: int, kb: int) -> float:
+def prox_bytes_per_voxel(passes: int) -> float:
     """Bytes each voxel must move through HBM in one prox application, by design.
 
-    Passes of `kb` fused dual steps: the first reads v and writes p (16 B), the
-    middle ones read v, p and write p (28 B), the last reads v, p and writes x
-    (20 B); with a single pass, read v and write x (8 B).
+    The prox runs as `passes` launches of the fused TV pass kernel: the first
+    reads v and writes the dual p (4 + 12 B), each middle one reads v and p and
+    writes p (4 + 12 + 12 B), the last reads v and p and writes x (4 + 12 + 4 B);
+    a single pass reads v and writes x (8 B).  Re-reads of tile halos are not
+    counted (they are overhead, visible in the measured traffic).
     """
-    passes = max(1, -(-k_in // kb))
-    if k_in == 0:
-        return 8.0
-    if passes == 1:
+    if passes <= 1:
         return 8.0
     return 16.0 + 28.0 * (passes - 2) + 20.0
 
@@ -86,12 +85,14 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--seed", type=int, default=0)
-    ap.add_argument("--ref-iters", type=int, default=1000, help="outer iterations of the reference run")
+    ap.add_argument("--ref-iters", type=int, default=2000, help="outer iterations of the reference run")
     ap.add_argument("--max-iters", type=int, default=1000)
     ap.add_argument("--gap", type=float, default=1e-4)
     ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time plain per-frame FISTA (dense, no graph)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run a 1 GiB device copy (for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); multi-GPU sharding is not built.",
@@ -146,23 +147,34 @@ def main():
     ph = rep_t["phase_ms"]
     nl = rep_t["phase_launches"]
     n_prox = max(rep_t["iters"], 1)
-    prox_ms_per_app = ph["prox"] / n_prox
-    kb = 1  # dual steps fused per prox pass
-    bytes_per_app = prox_bytes_per_voxel(cfg.inner_iters, kb) * nvox
-    prox_gbs = bytes_per_app / (prox_ms_per_app * 1e-3) / 1e9
+    passes = nl["prox"] // n_prox
+    launch_ms = ph["prox"] / max(nl["prox"], 1)
+    bytes_per_launch = prox_bytes_per_voxel(passes) * nvox / passes
+    prox_gbs = bytes_per_launch / (launch_ms * 1e-3) / 1e9
     roofline = {
         "bound": "hbm",
-        "kernel": "fused-lasso prox (TV dual passes)",
+        "kernel": "k_tv_pass (fused TV dual steps; the prox is `passes` launches)",
         "achieved": prox_gbs,
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": prox_gbs / HBM_PEAK_GBS,
         "traffic": None,
-        "launch_ms": ph["prox"] / max(nl["prox"], 1),
-        "bytes_per_voxel": prox_bytes_per_voxel(cfg.inner_iters, kb),
+        "launch_ms": launch_ms,
+        "passes": passes,
+        "bytes_per_voxel_per_prox": prox_bytes_per_voxel(passes),
+        "bytes_per_launch": bytes_per_launch,
     }
     phase_ms_per_iter = {k: v / n_prox for k, v in ph.items()}
     log("phase ms / iteration: " + ", ".join(f"{k} {v:.3f}" for k, v in phase_ms_per_iter.items()))
+
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy calibration: 3 x 1 GiB device copies")
 
     plain = None
     if args.plain:

@@ -218,7 +218,7 @@ extern "C" ri_status ri_plan_lipschitz(const ri_plan* p, double* out) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t total = 0;
-  size_t vol1 = 0, vol2 = 0, p[3] = {0, 0, 0}, u = 0;       // volumes (float)
+  size_t vol1 = 0, vol2 = 0, pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};  // volumes (float)
   size_t spec = 0, gp = 0, gi = 0, th = 0;                 // spectra (float2)
   size_t ax0 = 0, ax1 = 0;                                 // holograms (float)
   size_t rowflag = 0, planeflag = 0;                       // bytes
@@ -263,8 +263,8 @@ static Layout make_layout(const ri_plan* p, ri_op op) {
     L.th = take(hspec);
   }
   if (op == RI_OP_PROX || op == RI_OP_SOLVE) {
-    for (int k = 0; k < 3; ++k) L.p[k] = take(vol);
-    L.u = take(vol);
+    for (int k = 0; k < 3; ++k) L.pa[k] = take(vol);
+    for (int k = 0; k < 3; ++k) L.pb[k] = take(vol);
   }
   if (op == RI_OP_SOLVE) {
     L.vol1 = take(vol);
@@ -409,8 +409,8 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   ProxArgs a{};
   a.v = v;
   a.x = x_out;
-  for (int k = 0; k < 3; ++k) a.p[k] = at<float>(ws, L.p[k]);
-  a.u = at<float>(ws, L.u);
+  for (int k = 0; k < 3; ++k) a.pa[k] = at<float>(ws, L.pa[k]);
+  for (int k = 0; k < 3; ++k) a.pb[k] = at<float>(ws, L.pb[k]);
   a.nx = p->g.nx;
   a.ny = p->g.ny;
   a.nz = p->g.nz;
@@ -576,8 +576,8 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   if (tm) tm->begin(PH_PROX);
   ProxArgs pa{};
   for (int k = 0; k < 3; ++k) pa.vol[k] = c.vol[k];
-  for (int k = 0; k < 3; ++k) pa.p[k] = at<float>(c.ws, L.p[k]);
-  pa.u = at<float>(c.ws, L.u);
+  for (int k = 0; k < 3; ++k) pa.pa[k] = at<float>(c.ws, L.pa[k]);
+  for (int k = 0; k < 3; ++k) pa.pb[k] = at<float>(c.ws, L.pb[k]);
   pa.rowflag = rowflag;
   pa.planeflag = planeflag;
   pa.nx = nx; pa.ny = ny; pa.nz = nz;

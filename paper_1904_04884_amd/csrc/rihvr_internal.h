@@ -167,8 +167,8 @@ struct ProxArgs {
   const float* v;      // input volume (solver: slot st->prev)
   float* x;            // output volume (solver: slot st->next)
   float* vol[3];       // solver: the rotating volume buffers (v and x chosen on device)
-  float* p[3];         // dual components px, py, pz
-  float* u;            // scratch volume
+  float* pa[3];        // dual components px, py, pz (ping)
+  float* pb[3];        // dual components (pong)
   uint8_t* rowflag; uint8_t* planeflag;  // nullable: set where x != 0
   int nx, ny, nz;
   int inner_iters;
@@ -177,5 +177,6 @@ struct ProxArgs {
   const SolveState* st;  // solver: weights from st, step from `step`
 };
 hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
+int prox_passes(int inner_iters, double tau);
 
 }  // namespace rihvr

@@ -7,160 +7,352 @@
 // from p = 0; the result is soft(v - tau D^T p, step*l1).  -D^T p is the
 // backward-difference divergence: div p(i) = sum_a p_a(i) - p_a(i - e_a), with
 // p_a(i - e_a) = 0 on the first index and p_a = 0 on the last index of axis a.
+//
+// Temporal blocking.  A dual step at voxel i reads the previous dual at
+// offsets in {-1, 0, 1} per axis, so L fused steps need an L-voxel halo.  A
+// block owns a 64 x (8 Q) tile in (x, y) -- one wavefront lane per x, Q rows of
+// y per lane, 8 wavefronts stacked in y -- and streams through z.  The L steps
+// form a pipeline along z: step l consumes the dual of step l-1 one plane
+// behind it and keeps in registers, per point, the previous plane's dual and
+// primal values.  Neighbours along x move with DPP wave shifts, along y through
+// registers within a lane and through double-buffered LDS rows between
+// wavefronts (one barrier per step and plane).  Points within L of the tile
+// edge are computed but not stored; tiles overlap by 2L.  The z-range is cut
+// into chunks with an L+1 plane margin so that the grid fills the device.
+//
+// One pass fuses up to H steps; a prox is a sequence of passes ping-ponging the
+// dual between two buffers.  The last pass adds a half step (primal recovery),
+// the soft threshold, the occupancy flags of the result and the store of x.
+#include <algorithm>
+
 #include "rihvr_internal.h"
 
 namespace rihvr {
 
-constexpr int kTvBX = 64, kTvBY = 4;
+constexpr int kTvWaves = 8;
+constexpr int kTvQ = 4;                 // rows per lane
+constexpr int kTvRX = 64;               // tile width (lanes)
+constexpr int kTvRY = kTvWaves * kTvQ;  // tile height
 
-struct TvDims {
+struct TvPassArgs {
+  const float* v;                 // nullptr: vol[st->prev]
+  float* x;                       // nullptr: vol[st->next]
+  float* vol[3];
+  const float* pin[3];            // dual read by the first step (ignored when first)
+  float* pout[3];                 // dual written by the last step (unless final)
+  uint8_t* rowflag; uint8_t* planeflag;  // final pass: set where x != 0 (nullable)
+  const SolveState* st;
   int nx, ny, nz;
-  size_t sy, sz;  // strides of y and z in elements
+  int levels;                     // fused dual steps in this pass (<= H, <= H-1 when final)
+  int first, final_, nonneg;
+  int zchunk;                     // output planes per block
+  float tau, c, thr;
 };
 
-__device__ __forceinline__ float div_p(const float* __restrict__ px, const float* __restrict__ py,
-                                       const float* __restrict__ pz, size_t i, int x, int y, int z,
-                                       const TvDims& d) {
-  float r = 0.f;
-  if (x + 1 < d.nx) r += px[i];
-  if (x > 0) r -= px[i - 1];
-  if (y + 1 < d.ny) r += py[i];
-  if (y > 0) r -= py[i - d.sy];
-  if (z + 1 < d.nz) r += pz[i];
-  if (z > 0) r -= pz[i - d.sz];
-  return r;
+__device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1 (0 at lane 0)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+1 (0 at lane 63)
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
 }
 
-struct TvStepArgs {
-  const float* v;      // resolved input (or nullptr: take vol[st->prev])
-  float* vol[3];
-  float* px; float* py; float* pz;
-  float* u;
-  const SolveState* st;
-  TvDims d;
-  float tau, c;        // tau, 1/(12 tau)
-};
+template <int H>
+__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
+  constexpr int Q = kTvQ, NW = kTvWaves;
+  constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
+  __shared__ float s_py[H + 1][2][NW][64];  // bottom-row p_y per wave, per step, parity
+  __shared__ float s_ut[H][2][NW][64];      // top-row u per wave, per step, parity
+  if (A.st != nullptr && A.st->done) return;
+  const float* __restrict__ v = A.v ? A.v : A.vol[A.st->prev];
+  float* __restrict__ xo = A.x ? A.x : A.vol[A.st->next];
+  const int nx = A.nx, ny = A.ny, nz = A.nz;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = blockIdx.x * IX - H + lane;
+  const int ybase = blockIdx.y * IY - H + wv * Q;
+  const bool inx = x >= 0 && x < nx;
+  const bool xlo = x > 0, xhi = x + 1 < nx;
+  const bool ix_store = inx && lane >= H && lane < kTvRX - H;
+  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const int L = A.levels;
+  const int zb = blockIdx.z * A.zchunk, ze = min(nz, zb + A.zchunk);
+  const int M = L + 1;
+  const int zs = max(0, zb - M), zl = min(nz, ze + M);
+  const float tau = A.tau, cc = A.c;
 
-// u = v - tau D^T p = v + tau div p
-__global__ void __launch_bounds__(kTvBX * kTvBY) k_tv_u(TvStepArgs a) {
-  if (a.st != nullptr && a.st->done) return;
-  const int x = blockIdx.x * kTvBX + threadIdx.x, y = blockIdx.y * kTvBY + threadIdx.y, z = blockIdx.z;
-  if (x >= a.d.nx || y >= a.d.ny) return;
-  const float* v = a.v ? a.v : a.vol[a.st->prev];
-  const size_t i = (size_t)z * a.d.sz + (size_t)y * a.d.sy + x;
-  a.u[i] = v[i] + a.tau * div_p(a.px, a.py, a.pz, i, x, y, z, a.d);
-}
-
-// p = proj(p + c D u); FIRST: p = 0 and u = v.
-template <bool FIRST>
-__global__ void __launch_bounds__(kTvBX * kTvBY) k_tv_p(TvStepArgs a) {
-  if (a.st != nullptr && a.st->done) return;
-  const int x = blockIdx.x * kTvBX + threadIdx.x, y = blockIdx.y * kTvBY + threadIdx.y, z = blockIdx.z;
-  if (x >= a.d.nx || y >= a.d.ny) return;
-  const float* u = FIRST ? (a.v ? a.v : a.vol[a.st->prev]) : a.u;
-  const size_t i = (size_t)z * a.d.sz + (size_t)y * a.d.sy + x;
-  const float u0 = u[i];
-  const float gx = (x + 1 < a.d.nx) ? u[i + 1] - u0 : 0.f;
-  const float gy = (y + 1 < a.d.ny) ? u[i + a.d.sy] - u0 : 0.f;
-  const float gz = (z + 1 < a.d.nz) ? u[i + a.d.sz] - u0 : 0.f;
-  float qx = a.c * gx, qy = a.c * gy, qz = a.c * gz;
-  if (!FIRST) {
-    qx += a.px[i];
-    qy += a.py[i];
-    qz += a.pz[i];
+  bool iny[Q], ylo[Q], yhi[Q], ys[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int y = ybase + q;
+    iny[q] = y >= 0 && y < ny;
+    ylo[q] = y > 0;
+    yhi[q] = y + 1 < ny;
+    const int r = wv * Q + q;
+    ys[q] = iny[q] && r >= H && r < kTvRY - H;
   }
-  const float n2 = qx * qx + qy * qy + qz * qz;
-  const float sc = n2 > 1.f ? rsqrtf(n2) : 1.f;
-  a.px[i] = qx * sc;
-  a.py[i] = qy * sc;
-  a.pz[i] = qz * sc;
-}
+  // per step: previous plane's dual (3) and primal (1); final stage: previous p_z
+  float Pp[H][Q][3], Up[H][Q], PzF[Q];
+#pragma unroll
+  for (int l = 0; l < H; ++l)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      Pp[l][q][0] = Pp[l][q][1] = Pp[l][q][2] = 0.f;
+      Up[l][q] = 0.f;
+    }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) PzF[q] = 0.f;
 
-struct TvFinalArgs {
-  const float* v; float* x;
-  float* vol[3];
-  const float* px; const float* py; const float* pz;
-  uint8_t* rowflag; uint8_t* planeflag;
-  const SolveState* st;
-  TvDims d;
-  float tau, thr;
-  int use_p, nonneg;
-};
+  // v of the planes the steps work on this iteration: vQ[l] = v[zs + s - l];
+  // the next plane's v and dual are prefetched one iteration ahead.
+  float vQ[H + 1][Q], vN[Q], pN[Q][3];
+#pragma unroll
+  for (int l = 0; l <= H; ++l)
+#pragma unroll
+    for (int q = 0; q < Q; ++q) vQ[l][q] = 0.f;
+  auto load_plane = [&](int a, float (&vv)[Q], float (&pp)[Q][3]) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const bool in = inx && iny[q] && a < zl;
+      const size_t i = (size_t)a * sz + (size_t)(ybase + q) * sy + x;
+      vv[q] = in ? v[i] : 0.f;
+      if (!A.first) {
+        pp[q][0] = in ? A.pin[0][i] : 0.f;
+        pp[q][1] = in ? A.pin[1][i] : 0.f;
+        pp[q][2] = in ? A.pin[2][i] : 0.f;
+      } else {
+        pp[q][0] = pp[q][1] = pp[q][2] = 0.f;
+      }
+    }
+  };
+  load_plane(zs, vN, pN);
 
-// x = soft(v + tau div p, thr); marks rows / planes that hold a non-zero.
-__global__ void __launch_bounds__(kTvBX * kTvBY) k_tv_final(TvFinalArgs a) {
-  if (a.st != nullptr && a.st->done) return;
-  const int x = blockIdx.x * kTvBX + threadIdx.x, y = blockIdx.y * kTvBY + threadIdx.y, z = blockIdx.z;
-  const bool in = x < a.d.nx && y < a.d.ny;
-  const float* v = a.v ? a.v : a.vol[a.st->prev];
-  float* xo = a.x ? a.x : a.vol[a.st->next];
-  float out = 0.f;
-  if (in) {
-    const size_t i = (size_t)z * a.d.sz + (size_t)y * a.d.sy + x;
-    float u = v[i];
-    if (a.use_p) u += a.tau * div_p(a.px, a.py, a.pz, i, x, y, z, a.d);
-    if (a.nonneg) {
-      out = fmaxf(u - a.thr, 0.f);
+  const int nsteps = (zl - zs) + L;
+  for (int s = 0; s < nsteps; ++s) {
+    const int par = s & 1;
+    // carry: dual of the previous step at the arrival plane of the current step
+    float c3[Q][3];
+#pragma unroll
+    for (int l = H; l > 0; --l)
+#pragma unroll
+      for (int q = 0; q < Q; ++q) vQ[l][q] = vQ[l - 1][q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      vQ[0][q] = vN[q];
+      c3[q][0] = pN[q][0];
+      c3[q][1] = pN[q][1];
+      c3[q][2] = pN[q][2];
+    }
+    if (zs + s + 1 < zl) load_plane(zs + s + 1, vN, pN);
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+      if (l >= L) break;
+      const int a = zs + s - l;          // arrival plane of step l
+      if (a < zs || a > zl) continue;    // idle (uniform across the block)
+      if (a < zl) {
+        // ---- arrival of the previous dual at plane a ----
+        s_py[l][par][wv][lane] = c3[Q - 1][1];
+        __syncthreads();
+        float un[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const float pxm = dpp_from_left(c3[q][0]);
+          const float pym = (q > 0) ? c3[q - 1][1] : (wv > 0 ? s_py[l][par][wv - 1][lane] : 0.f);
+          float d = 0.f;
+          d += xhi ? c3[q][0] : 0.f;
+          d -= xlo ? pxm : 0.f;
+          d += yhi[q] ? c3[q][1] : 0.f;
+          d -= ylo[q] ? pym : 0.f;
+          d += (a + 1 < nz) ? c3[q][2] : 0.f;
+          d -= (a > 0) ? Pp[l][q][2] : 0.f;
+          un[q] = fmaf(tau, d, vQ[l][q]);
+        }
+        if (a > zs) {
+          // ---- dual step at plane m = a - 1 ----
+          const int m = a - 1;
+          float out[Q][3];
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            const float u0 = Up[l][q];
+            const float uxp = dpp_from_right(u0);
+            const float uyp = (q < Q - 1) ? Up[l][q + 1] : (wv < NW - 1 ? s_ut[l][par ^ 1][wv + 1][lane] : 0.f);
+            const float gx = xhi ? uxp - u0 : 0.f;
+            const float gy = yhi[q] ? uyp - u0 : 0.f;
+            const float gz = (m + 1 < nz) ? un[q] - u0 : 0.f;
+            const float qx = fmaf(cc, gx, Pp[l][q][0]);
+            const float qy = fmaf(cc, gy, Pp[l][q][1]);
+            const float qz = fmaf(cc, gz, Pp[l][q][2]);
+            const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+            const float sc = n2 > 1.f ? __frsqrt_rn(n2) : 1.f;
+            out[q][0] = qx * sc;
+            out[q][1] = qy * sc;
+            out[q][2] = qz * sc;
+          }
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            Pp[l][q][0] = c3[q][0];
+            Pp[l][q][1] = c3[q][1];
+            Pp[l][q][2] = c3[q][2];
+            Up[l][q] = un[q];
+            c3[q][0] = out[q][0];
+            c3[q][1] = out[q][1];
+            c3[q][2] = out[q][2];
+          }
+        } else {
+#pragma unroll
+          for (int q = 0; q < Q; ++q) {
+            Pp[l][q][0] = c3[q][0];
+            Pp[l][q][1] = c3[q][1];
+            Pp[l][q][2] = c3[q][2];
+            Up[l][q] = un[q];
+          }
+        }
+        s_ut[l][par][wv][lane] = un[0];
+      } else {
+        // ---- flush: dual step at the last plane m = zl - 1 (no plane above) ----
+        __syncthreads();
+        const int m = zl - 1;
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          const float u0 = Up[l][q];
+          const float uxp = dpp_from_right(u0);
+          const float uyp = (q < Q - 1) ? Up[l][q + 1] : (wv < NW - 1 ? s_ut[l][par ^ 1][wv + 1][lane] : 0.f);
+          const float gx = xhi ? uxp - u0 : 0.f;
+          const float gy = yhi[q] ? uyp - u0 : 0.f;
+          (void)m;
+          const float qx = fmaf(cc, gx, Pp[l][q][0]);
+          const float qy = fmaf(cc, gy, Pp[l][q][1]);
+          const float qz = Pp[l][q][2];
+          const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+          const float sc = n2 > 1.f ? __frsqrt_rn(n2) : 1.f;
+          c3[q][0] = qx * sc;
+          c3[q][1] = qy * sc;
+          c3[q][2] = qz * sc;
+        }
+      }
+    }
+    // ---- output stage: dual of the last step at plane m = zs + s - L ----
+    const int m = zs + s - L;
+    if (m < zs || m >= zl) continue;
+    const bool zstore = m >= zb && m < ze;
+    if (!A.final_) {
+      if (zstore && ix_store) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          if (!ys[q]) continue;
+          const size_t i = (size_t)m * sz + (size_t)(ybase + q) * sy + x;
+          A.pout[0][i] = c3[q][0];
+          A.pout[1][i] = c3[q][1];
+          A.pout[2][i] = c3[q][2];
+        }
+      }
     } else {
-      const float m = fmaxf(fabsf(u) - a.thr, 0.f);
-      out = copysignf(m, u);
+      // primal recovery u = v + tau div p, soft threshold, store, flags
+      s_py[H][par][wv][lane] = c3[Q - 1][1];
+      __syncthreads();
+      const bool any_tv = tau != 0.f;
+      float vF[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) vF[q] = vQ[0][q];
+#pragma unroll
+      for (int l = 1; l <= H; ++l)
+        if (l == L)
+#pragma unroll
+          for (int q = 0; q < Q; ++q) vF[q] = vQ[l][q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) {
+        const size_t i = (size_t)m * sz + (size_t)(ybase + q) * sy + x;
+        float u = vF[q];
+        if (any_tv) {
+          const float pxm = dpp_from_left(c3[q][0]);
+          const float pym = (q > 0) ? c3[q - 1][1] : (wv > 0 ? s_py[H][par][wv - 1][lane] : 0.f);
+          float d = 0.f;
+          d += xhi ? c3[q][0] : 0.f;
+          d -= xlo ? pxm : 0.f;
+          d += yhi[q] ? c3[q][1] : 0.f;
+          d -= ylo[q] ? pym : 0.f;
+          d += (m + 1 < nz) ? c3[q][2] : 0.f;
+          d -= (m > 0) ? PzF[q] : 0.f;
+          u = fmaf(tau, d, u);
+        }
+        PzF[q] = c3[q][2];
+        float xv;
+        if (A.nonneg) {
+          xv = fmaxf(u - A.thr, 0.f);
+        } else {
+          xv = copysignf(fmaxf(fabsf(u) - A.thr, 0.f), u);
+        }
+        const bool st = zstore && ix_store && ys[q];
+        if (st) xo[i] = xv;
+        if (A.rowflag != nullptr) {
+          const bool nzr = __ballot(st && xv != 0.f) != 0;
+          if (nzr && lane == 0) {
+            A.rowflag[(size_t)m * ny + ybase + q] = 1;
+            A.planeflag[m] = 1;
+          }
+        }
+      }
     }
-    xo[i] = out;
   }
-  if (a.rowflag != nullptr) {
-    // one wavefront = 64 consecutive x of one row
-    const bool nz = __ballot(in && out != 0.f) != 0;
-    if (nz && threadIdx.x == 0) {
-      a.rowflag[(size_t)z * a.d.ny + y] = 1;
-      a.planeflag[z] = 1;
-    }
-  }
+}
+
+// Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut so that
+// the grid holds at least ~3 blocks per CU where the volume allows it.
+static void pass_grid(int nx, int ny, int nz, int H, dim3* grid, int* zchunk) {
+  const int tx = (nx + (kTvRX - 2 * H) - 1) / (kTvRX - 2 * H);
+  const int ty = (ny + (kTvRY - 2 * H) - 1) / (kTvRY - 2 * H);
+  const int want = 1536;
+  int nzc = std::max(1, std::min(nz / 16, (want + tx * ty - 1) / (tx * ty)));
+  if (nzc < 1) nzc = 1;
+  const int zc = (nz + nzc - 1) / nzc;
+  *zchunk = zc;
+  *grid = dim3(tx, ty, (nz + zc - 1) / zc);
+}
+
+constexpr int kTvH = 4;
+
+int prox_passes(int inner_iters, double tau) {
+  if (!(tau > 0.0) || inner_iters <= 0) return 1;
+  return (inner_iters + 1 + kTvH - 1) / kTvH;   // K dual steps + one primal half step
 }
 
 hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
-  TvDims d{pa.nx, pa.ny, pa.nz, (size_t)pa.nx, (size_t)pa.nx * pa.ny};
-  const dim3 blk(kTvBX, kTvBY);
-  const dim3 grd((pa.nx + kTvBX - 1) / kTvBX, (pa.ny + kTvBY - 1) / kTvBY, pa.nz);
-  // The weights come from the host for a plain prox call, and from the same
-  // host values for the solver (they are constant over a solve).
   const double tau = pa.step * pa.tv;
   const double thr = pa.step * pa.l1;
   const bool use_tv = tau > 0.0 && pa.inner_iters > 0;
-  int n = 0;
-  TvStepArgs sa{};
-  sa.v = pa.v;
-  for (int k = 0; k < 3; ++k) sa.vol[k] = pa.vol[k];
-  sa.px = pa.p[0]; sa.py = pa.p[1]; sa.pz = pa.p[2];
-  sa.u = pa.u;
-  sa.st = pa.st;
-  sa.d = d;
-  sa.tau = (float)tau;
-  sa.c = use_tv ? (float)(1.0 / (12.0 * tau)) : 0.f;
-  if (use_tv) {
-    hipLaunchKernelGGL(k_tv_p<true>, grd, blk, 0, s, sa);
-    ++n;
-    for (int k = 1; k < pa.inner_iters; ++k) {
-      hipLaunchKernelGGL(k_tv_u, grd, blk, 0, s, sa);
-      hipLaunchKernelGGL(k_tv_p<false>, grd, blk, 0, s, sa);
-      n += 2;
+  const int K = use_tv ? pa.inner_iters : 0;
+  const int npass = prox_passes(K, tau);
+  TvPassArgs a{};
+  a.v = pa.v;
+  a.x = pa.x;
+  for (int k = 0; k < 3; ++k) a.vol[k] = pa.vol[k];
+  a.rowflag = pa.rowflag;
+  a.planeflag = pa.planeflag;
+  a.st = pa.st;
+  a.nx = pa.nx; a.ny = pa.ny; a.nz = pa.nz;
+  a.nonneg = pa.nonneg;
+  a.tau = (float)tau;
+  a.c = use_tv ? (float)(1.0 / (12.0 * tau)) : 0.f;
+  a.thr = (float)thr;
+  dim3 grid;
+  pass_grid(pa.nx, pa.ny, pa.nz, kTvH, &grid, &a.zchunk);
+  // dual steps per pass: non-final passes take kTvH, the final pass the rest
+  // (at most kTvH - 1, leaving room for the primal half step in its halo)
+  int done = 0;
+  for (int p = 0; p < npass; ++p) {
+    const bool fin = p == npass - 1;
+    const int lv = fin ? K - done : std::min(kTvH, K - done);
+    a.levels = lv;
+    a.first = (done == 0) ? 1 : 0;
+    a.final_ = fin ? 1 : 0;
+    float* const* src = (p & 1) ? pa.pb : pa.pa;
+    float* const* dst = (p & 1) ? pa.pa : pa.pb;
+    for (int k = 0; k < 3; ++k) {
+      a.pin[k] = src[k];
+      a.pout[k] = dst[k];
     }
+    hipLaunchKernelGGL(k_tv_pass<kTvH>, grid, dim3(kTvWaves * 64), 0, s, a);
+    done += lv;
   }
-  TvFinalArgs fa{};
-  fa.v = pa.v;
-  fa.x = pa.x;
-  for (int k = 0; k < 3; ++k) fa.vol[k] = pa.vol[k];
-  fa.px = pa.p[0]; fa.py = pa.p[1]; fa.pz = pa.p[2];
-  fa.rowflag = pa.rowflag;
-  fa.planeflag = pa.planeflag;
-  fa.st = pa.st;
-  fa.d = d;
-  fa.tau = (float)tau;
-  fa.thr = (float)thr;
-  fa.use_p = use_tv ? 1 : 0;
-  fa.nonneg = pa.nonneg;
-  hipLaunchKernelGGL(k_tv_final, grd, blk, 0, s, fa);
-  ++n;
-  if (launches) *launches = n;
+  if (launches) *launches = npass;
   return hipGetLastError();
 }
 

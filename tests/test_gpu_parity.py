@@ -140,6 +140,20 @@ def test_prox_parity(torch_cuda, plans, shape, nonneg):
     assert rel_l2(out, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8, 20])
+def test_prox_pass_schedules(torch_cuda, plans, k):
+    """Dual-step counts that split differently over fused passes, on a volume
+    with several x / y tiles and z chunks."""
+    torch = torch_cuda
+    g = geom(192, 96, 40)
+    rng = np.random.default_rng(100 + k)
+    v = (0.3 * rng.standard_normal(g.shape)).astype(np.float32)
+    step, l1, tv = 0.5, 0.05, 0.3
+    ref = prox.prox_fused_lasso(v.astype(np.float64), step, l1, tv, k)
+    out = to_host(plans(g).prox(to_dev(torch, v), step, l1, tv, k))
+    assert rel_l2(out, ref) <= 1e-5
+
+
 def test_prox_without_tv_is_exact_soft_threshold(torch_cuda, plans):
     torch = torch_cuda
     g = geom(64, 32, 5)
