@@ -20,6 +20,11 @@
 // edge are computed but not stored; tiles overlap by 2L.  The z-range is cut
 // into chunks with an L+1 plane margin so that the grid fills the device.
 //
+// Boundaries: the z-component of the dual is exactly zero on the last plane
+// (its z-difference is zero there, from p = 0 on) and the state below the first
+// plane starts at zero, so the divergence carries no z masks; x / y masks are
+// compiled only into the blocks whose tile touches the volume edge.
+//
 // One pass fuses up to H steps; a prox is a sequence of passes ping-ponging the
 // dual between two buffers.  The last pass adds a half step (primal recovery),
 // the soft threshold, the occupancy flags of the result and the store of x.
@@ -50,29 +55,39 @@ struct TvPassArgs {
 };
 
 __device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1 (0 at lane 0)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x138, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
 __device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+1 (0 at lane 63)
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x130, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
-template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
-  constexpr int Q = kTvQ, NW = kTvWaves;
+// Pass body.  EDGE: the tile touches the volume boundary, so every access and
+// every difference is masked; interior tiles (most of them) skip the masks.
+// FIRST: the incoming dual is zero (nothing is read).
+// A pointer known to be the same in every lane (keeps address bases in SGPRs).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+template <int H, bool EDGE, bool FIRST>
+__device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, float (*s_py)[2][kTvWaves][64],
+                                             float (*s_ut)[2][kTvWaves][64], float* s_v) {
+  constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
-  __shared__ float s_py[H + 1][2][NW][64];  // bottom-row p_y per wave, per step, parity
-  __shared__ float s_ut[H][2][NW][64];      // top-row u per wave, per step, parity
-  if (A.st != nullptr && A.st->done) return;
-  const float* __restrict__ v = A.v ? A.v : A.vol[A.st->prev];
-  float* __restrict__ xo = A.x ? A.x : A.vol[A.st->next];
+  const float* __restrict__ v = uniform_ptr(A.v ? A.v : A.vol[A.st->prev]);
+  float* __restrict__ xo = uniform_ptr(A.x ? A.x : A.vol[A.st->next]);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = blockIdx.x * IX - H + lane;
   const int ybase = blockIdx.y * IY - H + wv * Q;
-  const bool inx = x >= 0 && x < nx;
-  const bool xlo = x > 0, xhi = x + 1 < nx;
+  const bool inx = !EDGE || (x >= 0 && x < nx);
+  const bool xlo = !EDGE || x > 0, xhi = !EDGE || x + 1 < nx;
   const bool ix_store = inx && lane >= H && lane < kTvRX - H;
-  const size_t sy = (size_t)nx, sz = (size_t)nx * ny;
+  const size_t sz = (size_t)nx * ny;
   const int L = A.levels;
   const int zb = blockIdx.z * A.zchunk, ze = min(nz, zb + A.zchunk);
   const int M = L + 1;
@@ -80,16 +95,18 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
   const float tau = A.tau, cc = A.c;
 
   bool iny[Q], ylo[Q], yhi[Q], ys[Q];
+  unsigned off[Q];  // in-plane byte offset (32 bit, so loads use a scalar base + vector offset)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int y = ybase + q;
-    iny[q] = y >= 0 && y < ny;
-    ylo[q] = y > 0;
-    yhi[q] = y + 1 < ny;
+    iny[q] = !EDGE || (y >= 0 && y < ny);
+    ylo[q] = !EDGE || y > 0;
+    yhi[q] = !EDGE || y + 1 < ny;
     const int r = wv * Q + q;
     ys[q] = iny[q] && r >= H && r < kTvRY - H;
+    off[q] = (inx && iny[q]) ? (unsigned)(y * nx + x) * 4u : 0u;
   }
-  // per step: previous plane's dual (3) and primal (1); final stage: previous p_z
+  // per fused step: previous plane's dual (3) and primal (1); final stage: previous p_z
   float Pp[H][Q][3], Up[H][Q], PzF[Q];
 #pragma unroll
   for (int l = 0; l < H; ++l)
@@ -101,51 +118,56 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
 #pragma unroll
   for (int q = 0; q < Q; ++q) PzF[q] = 0.f;
 
-  // v of the planes the steps work on this iteration: vQ[l] = v[zs + s - l];
-  // the next plane's v and dual are prefetched one iteration ahead.
-  float vQ[H + 1][Q], vN[Q], pN[Q][3];
+  // v of recent planes lives in a thread-private LDS ring (slot = plane mod H+1);
+  // the next plane's v and dual are prefetched into registers one step ahead.
+  float vN[Q], pN[Q][3];
+  auto ld = [](const float* base, unsigned ob) -> float {
+    return *(const __attribute__((address_space(1))) float*)(reinterpret_cast<const char*>(base) + ob);
+  };
+  auto load_plane = [&](int a) {
+    const float* vp = v + (size_t)a * sz;
 #pragma unroll
-  for (int l = 0; l <= H; ++l)
+    for (int q = 0; q < Q; ++q) vN[q] = (inx && iny[q]) ? ld(vp, off[q]) : 0.f;
+    if constexpr (!FIRST) {
+      const float* p0 = A.pin[0] + (size_t)a * sz;
+      const float* p1 = A.pin[1] + (size_t)a * sz;
+      const float* p2 = A.pin[2] + (size_t)a * sz;
 #pragma unroll
-    for (int q = 0; q < Q; ++q) vQ[l][q] = 0.f;
-  auto load_plane = [&](int a, float (&vv)[Q], float (&pp)[Q][3]) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) {
-      const bool in = inx && iny[q] && a < zl;
-      const size_t i = (size_t)a * sz + (size_t)(ybase + q) * sy + x;
-      vv[q] = in ? v[i] : 0.f;
-      if (!A.first) {
-        pp[q][0] = in ? A.pin[0][i] : 0.f;
-        pp[q][1] = in ? A.pin[1][i] : 0.f;
-        pp[q][2] = in ? A.pin[2][i] : 0.f;
-      } else {
-        pp[q][0] = pp[q][1] = pp[q][2] = 0.f;
+      for (int q = 0; q < Q; ++q) {
+        const bool in = inx && iny[q];
+        pN[q][0] = in ? ld(p0, off[q]) : 0.f;
+        pN[q][1] = in ? ld(p1, off[q]) : 0.f;
+        pN[q][2] = in ? ld(p2, off[q]) : 0.f;
       }
     }
   };
-  load_plane(zs, vN, pN);
+  auto st_ = [](float* base, unsigned ob, float val) {
+    *(__attribute__((address_space(1))) float*)(reinterpret_cast<char*>(base) + ob) = val;
+  };
+  if constexpr (FIRST) {
+#pragma unroll
+    for (int q = 0; q < Q; ++q) pN[q][0] = pN[q][1] = pN[q][2] = 0.f;
+  }
+  auto vring = [&](int a, int q) -> float& { return s_v[((a % (H + 1)) * Q + q) * NT + threadIdx.x]; };
+  load_plane(zs);
 
   const int nsteps = (zl - zs) + L;
   for (int s = 0; s < nsteps; ++s) {
     const int par = s & 1;
-    // carry: dual of the previous step at the arrival plane of the current step
+    const int a1 = zs + s;
     float c3[Q][3];
 #pragma unroll
-    for (int l = H; l > 0; --l)
-#pragma unroll
-      for (int q = 0; q < Q; ++q) vQ[l][q] = vQ[l - 1][q];
-#pragma unroll
     for (int q = 0; q < Q; ++q) {
-      vQ[0][q] = vN[q];
+      if (a1 < zl) vring(a1, q) = vN[q];
       c3[q][0] = pN[q][0];
       c3[q][1] = pN[q][1];
       c3[q][2] = pN[q][2];
     }
-    if (zs + s + 1 < zl) load_plane(zs + s + 1, vN, pN);
+    if (a1 + 1 < zl) load_plane(a1 + 1);
 #pragma unroll
     for (int l = 0; l < H; ++l) {
       if (l >= L) break;
-      const int a = zs + s - l;          // arrival plane of step l
+      const int a = zs + s - l;          // arrival plane of fused step l
       if (a < zs || a > zl) continue;    // idle (uniform across the block)
       if (a < zl) {
         // ---- arrival of the previous dual at plane a ----
@@ -155,47 +177,37 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const float pxm = dpp_from_left(c3[q][0]);
-          const float pym = (q > 0) ? c3[q - 1][1] : (wv > 0 ? s_py[l][par][wv - 1][lane] : 0.f);
-          float d = 0.f;
-          d += xhi ? c3[q][0] : 0.f;
-          d -= xlo ? pxm : 0.f;
-          d += yhi[q] ? c3[q][1] : 0.f;
-          d -= ylo[q] ? pym : 0.f;
-          d += (a + 1 < nz) ? c3[q][2] : 0.f;
-          d -= (a > 0) ? Pp[l][q][2] : 0.f;
-          un[q] = fmaf(tau, d, vQ[l][q]);
+          const float pym = (q > 0) ? c3[q - 1][1] : s_py[l][par][wv > 0 ? wv - 1 : 0][lane];
+          float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
+          d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
+          d += c3[q][2] - Pp[l][q][2];
+          un[q] = fmaf(tau, d, vring(a, q));
         }
         if (a > zs) {
-          // ---- dual step at plane m = a - 1 ----
-          const int m = a - 1;
-          float out[Q][3];
+          // ---- dual step at plane a - 1 ----
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
             const float u0 = Up[l][q];
             const float uxp = dpp_from_right(u0);
-            const float uyp = (q < Q - 1) ? Up[l][q + 1] : (wv < NW - 1 ? s_ut[l][par ^ 1][wv + 1][lane] : 0.f);
+            const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
             const float gx = xhi ? uxp - u0 : 0.f;
             const float gy = yhi[q] ? uyp - u0 : 0.f;
-            const float gz = (m + 1 < nz) ? un[q] - u0 : 0.f;
+            const float gz = un[q] - u0;       // plane a exists
             const float qx = fmaf(cc, gx, Pp[l][q][0]);
             const float qy = fmaf(cc, gy, Pp[l][q][1]);
             const float qz = fmaf(cc, gz, Pp[l][q][2]);
             const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-            const float sc = n2 > 1.f ? __frsqrt_rn(n2) : 1.f;
-            out[q][0] = qx * sc;
-            out[q][1] = qy * sc;
-            out[q][2] = qz * sc;
-          }
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
+            const float sc = fminf(1.f, __frsqrt_rn(n2));   // 1 / max(1, |q|)
             Pp[l][q][0] = c3[q][0];
             Pp[l][q][1] = c3[q][1];
             Pp[l][q][2] = c3[q][2];
-            Up[l][q] = un[q];
-            c3[q][0] = out[q][0];
-            c3[q][1] = out[q][1];
-            c3[q][2] = out[q][2];
+            c3[q][0] = qx * sc;
+            c3[q][1] = qy * sc;
+            c3[q][2] = qz * sc;
           }
+          // Up is read by the neighbours above (q+1) before it is replaced
+#pragma unroll
+          for (int q = 0; q < Q; ++q) Up[l][q] = un[q];
         } else {
 #pragma unroll
           for (int q = 0; q < Q; ++q) {
@@ -207,70 +219,57 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
         }
         s_ut[l][par][wv][lane] = un[0];
       } else {
-        // ---- flush: dual step at the last plane m = zl - 1 (no plane above) ----
+        // ---- flush: dual step at the last plane zl - 1 (no plane above) ----
         __syncthreads();
-        const int m = zl - 1;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           const float u0 = Up[l][q];
           const float uxp = dpp_from_right(u0);
-          const float uyp = (q < Q - 1) ? Up[l][q + 1] : (wv < NW - 1 ? s_ut[l][par ^ 1][wv + 1][lane] : 0.f);
+          const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
           const float gx = xhi ? uxp - u0 : 0.f;
           const float gy = yhi[q] ? uyp - u0 : 0.f;
-          (void)m;
           const float qx = fmaf(cc, gx, Pp[l][q][0]);
           const float qy = fmaf(cc, gy, Pp[l][q][1]);
           const float qz = Pp[l][q][2];
           const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-          const float sc = n2 > 1.f ? __frsqrt_rn(n2) : 1.f;
+          const float sc = fminf(1.f, __frsqrt_rn(n2));
           c3[q][0] = qx * sc;
           c3[q][1] = qy * sc;
           c3[q][2] = qz * sc;
         }
       }
     }
-    // ---- output stage: dual of the last step at plane m = zs + s - L ----
+    // ---- output stage: dual of the last fused step at plane m = zs + s - L ----
     const int m = zs + s - L;
     if (m < zs || m >= zl) continue;
     const bool zstore = m >= zb && m < ze;
     if (!A.final_) {
       if (zstore && ix_store) {
+        float* o0 = A.pout[0] + (size_t)m * sz;
+        float* o1 = A.pout[1] + (size_t)m * sz;
+        float* o2 = A.pout[2] + (size_t)m * sz;
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
           if (!ys[q]) continue;
-          const size_t i = (size_t)m * sz + (size_t)(ybase + q) * sy + x;
-          A.pout[0][i] = c3[q][0];
-          A.pout[1][i] = c3[q][1];
-          A.pout[2][i] = c3[q][2];
+          st_(o0, off[q], c3[q][0]);
+          st_(o1, off[q], c3[q][1]);
+          st_(o2, off[q], c3[q][2]);
         }
       }
     } else {
       // primal recovery u = v + tau div p, soft threshold, store, flags
       s_py[H][par][wv][lane] = c3[Q - 1][1];
       __syncthreads();
-      const bool any_tv = tau != 0.f;
-      float vF[Q];
-#pragma unroll
-      for (int q = 0; q < Q; ++q) vF[q] = vQ[0][q];
-#pragma unroll
-      for (int l = 1; l <= H; ++l)
-        if (l == L)
-#pragma unroll
-          for (int q = 0; q < Q; ++q) vF[q] = vQ[l][q];
+      float* xp = xo + (size_t)m * sz;
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const size_t i = (size_t)m * sz + (size_t)(ybase + q) * sy + x;
-        float u = vF[q];
-        if (any_tv) {
+        float u = vring(m, q);
+        if (tau != 0.f) {
           const float pxm = dpp_from_left(c3[q][0]);
-          const float pym = (q > 0) ? c3[q - 1][1] : (wv > 0 ? s_py[H][par][wv - 1][lane] : 0.f);
-          float d = 0.f;
-          d += xhi ? c3[q][0] : 0.f;
-          d -= xlo ? pxm : 0.f;
-          d += yhi[q] ? c3[q][1] : 0.f;
-          d -= ylo[q] ? pym : 0.f;
-          d += (m + 1 < nz) ? c3[q][2] : 0.f;
-          d -= (m > 0) ? PzF[q] : 0.f;
+          const float pym = (q > 0) ? c3[q - 1][1] : s_py[H][par][wv > 0 ? wv - 1 : 0][lane];
+          float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
+          d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
+          d += c3[q][2] - PzF[q];
           u = fmaf(tau, d, u);
         }
         PzF[q] = c3[q][2];
@@ -281,7 +280,7 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
           xv = copysignf(fmaxf(fabsf(u) - A.thr, 0.f), u);
         }
         const bool st = zstore && ix_store && ys[q];
-        if (st) xo[i] = xv;
+        if (st) st_(xp, off[q], xv);
         if (A.rowflag != nullptr) {
           const bool nzr = __ballot(st && xv != 0.f) != 0;
           if (nzr && lane == 0) {
@@ -291,6 +290,25 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
         }
       }
     }
+  }
+}
+
+template <int H>
+__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
+  __shared__ float s_py[H + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step, parity
+  __shared__ float s_ut[H][2][kTvWaves][64];      // top-row u per wave, per step, parity
+  __shared__ float s_v[(H + 1) * kTvQ * kTvWaves * 64];  // v ring, thread-private
+  if (A.st != nullptr && A.st->done) return;
+  constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;
+  const int x0 = blockIdx.x * IX - H, y0 = blockIdx.y * IY - H;
+  // interior tile: every point of the region and its +-1 neighbours lie inside
+  const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
+  if (A.first) {
+    if (interior) tv_pass_body<H, false, true>(A, s_py, s_ut, s_v);
+    else tv_pass_body<H, true, true>(A, s_py, s_ut, s_v);
+  } else {
+    if (interior) tv_pass_body<H, false, false>(A, s_py, s_ut, s_v);
+    else tv_pass_body<H, true, false>(A, s_py, s_ut, s_v);
   }
 }
 
