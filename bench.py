@@ -42,6 +42,26 @@ def prox_bytes_per_voxel(passes: int) -> float:
     return 16.0 + 28.0 * (passes - 2) + 20.0
 
 
+def measured_traffic():
+    """HBM bytes per k_tv_pass dispatch from the committed rocprofv3 counter
+    summary, or None if the kernel source changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_tv_pass_c2_hbm_counters.md")
+    src = os.path.join(ROOT, "paper_1904_04884_amd", "csrc", "tv.hip")
+    try:
+        kv = {}
+        for line in open(path):
+            if " = " in line:
+                k, v = line.split(" = ", 1)
+                kv[k.strip()] = v.strip()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if kv.get("tv_source_sha256") != digest:
+            return None
+        return float(kv["traffic_bytes_per_dispatch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
 def build_scene(torch, rihvr, scenes, plan, seed):
     g = scenes.geometry_c2()
     sc = scenes.scene_c2(seed=seed)
@@ -158,7 +178,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": prox_gbs / HBM_PEAK_GBS,
-        "traffic": None,
+        "traffic": measured_traffic(),
         "launch_ms": launch_ms,
         "passes": passes,
         "bytes_per_voxel_per_prox": prox_bytes_per_voxel(passes),

@@ -178,10 +178,15 @@ ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const float* b,
  * count (one plan per frame).  Frames advance in lock-step, one outer
  * iteration for all frames at a time, each with its own step, momentum,
  * objective and stop flag; a frame that has met its criterion does no further
- * work.  ws must hold ri_workspace_size(plans[i], RI_OP_SOLVE) for every frame,
- * each rounded up to 256 bytes, summed.  params[i], b[i], x_inout[i] and
- * reports[i] (nullable array) belong to frame i.
+ * work.  Each kernel of an iteration is launched once per transform size (or
+ * once for all frames) and one iteration of all frames is replayed as a HIP
+ * graph (unless params[0].flags has RI_SOLVE_NO_GRAPH).  The workspace must
+ * hold ri_workspace_size_batched() bytes.  params[i], b[i], x_inout[i] and
+ * reports[i] (nullable array; filled after one synchronisation) belong to
+ * frame i.  The x_inout volumes must not overlap each other, any b or ws.
  */
+ri_status ri_workspace_size_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
+                                    size_t* bytes);
 ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
                            const float* const* b, float* const* x_inout,
                            void* ws, size_t ws_bytes, void* stream, ri_solve_report* reports);

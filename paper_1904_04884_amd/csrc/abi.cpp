@@ -332,7 +332,8 @@ static hipError_t enqueue_forward(ri_plan* p, const Layout& L, void* ws, const f
   ra.out = at<float2>(ws, L.spec);
   ra.nrows = ny * nz;
   ra.mode = 0;
-  hipError_t e = launch_rows_r2c(m, ra, pt, s);
+  ra.pt = pt;
+  hipError_t e = launch_rows_r2c(m, ra, s);
   if (e != hipSuccess) return e;
   FwdColsArgs fa{};
   fa.t = at<float2>(ws, L.spec);
@@ -340,10 +341,16 @@ static hipError_t enqueue_forward(ri_plan* p, const Layout& L, void* ws, const f
   fa.m = m;
   fa.nz = nz;
   fa.planes_per_chunk = L.ppc;
-  e = launch_fwd_cols(ny, L.nchunk, fa, pt, s);
+  fa.pt = pt;
+  e = launch_fwd_cols(ny, L.nchunk, fa, s);
   if (e != hipSuccess) return e;
-  HoloColsInvArgs ha{at<float2>(ws, L.gp), at<float2>(ws, L.gi), m, L.nchunk, nullptr};
-  e = launch_holo_cols_inv(ny, ha, pt, s);
+  HoloColsInvArgs ha{};
+  ha.gp = at<float2>(ws, L.gp);
+  ha.gi = at<float2>(ws, L.gi);
+  ha.m = m;
+  ha.nchunk = L.nchunk;
+  ha.pt = pt;
+  e = launch_holo_cols_inv(ny, ha, s);
   if (e != hipSuccess) return e;
   RowsC2RArgs ca{};
   ca.in = at<float2>(ws, L.gi);
@@ -351,7 +358,8 @@ static hipError_t enqueue_forward(ri_plan* p, const Layout& L, void* ws, const f
   ca.out = out;
   ca.mode = 0;
   ca.scale = (float)(1.0 / ((double)p->g.nx * ny));
-  return launch_rows_c2r(m, ca, pt, s);
+  ca.pt = pt;
+  return launch_rows_c2r(m, ca, s);
 }
 
 extern "C" ri_status ri_forward(ri_plan* p, const float* x, float* b_out, void* ws, size_t ws_bytes,
@@ -380,9 +388,16 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   ra.out = at<float2>(ws, L.th);
   ra.nrows = ny;
   ra.mode = 0;
-  HIP_TRY(launch_rows_r2c(m, ra, pt, s));
-  AdjColsArgs aa{at<float2>(ws, L.th), at<float2>(ws, L.spec), m, nz, L.ppc, nullptr};
-  HIP_TRY(launch_adj_cols(ny, L.nchunk, aa, pt, s));
+  ra.pt = pt;
+  HIP_TRY(launch_rows_r2c(m, ra, s));
+  AdjColsArgs aa{};
+  aa.th = at<float2>(ws, L.th);
+  aa.u = at<float2>(ws, L.spec);
+  aa.m = m;
+  aa.nz = nz;
+  aa.planes_per_chunk = L.ppc;
+  aa.pt = pt;
+  HIP_TRY(launch_adj_cols(ny, L.nchunk, aa, s));
   AdjRowsArgs ar{};
   ar.u = at<float2>(ws, L.spec);
   ar.nrows = ny * nz;
@@ -390,7 +405,8 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   ar.out = x_out;
   ar.mode = 0;
   ar.scale = (float)(1.0 / ((double)p->g.nx * ny));
-  HIP_TRY(launch_adj_rows(m, ar, pt, s));
+  ar.pt = pt;
+  HIP_TRY(launch_adj_rows(m, ar, s));
   return RI_OK;
 }
 
@@ -476,8 +492,22 @@ struct PhaseTimer {
   }
 };
 
-// One outer iteration: objective of x_it, momentum, gradient step, prox.
-static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer* tm) {
+// Argument structs of the kernels of one outer iteration of one frame.  The
+// single-frame path launches them directly; the batched path uploads them.
+struct IterArgs {
+  ObjArgs obj;
+  RowsR2CArgs fwd_rows;
+  FwdColsArgs fwd_cols;
+  HoloColsInvArgs holo_inv;
+  RowsC2RArgs holo_c2r;
+  ScalarArgs scal;
+  RowsR2CArgs resid;
+  AdjColsArgs adj_cols;
+  AdjRowsArgs adj_rows;
+  ProxArgs prox;
+};
+
+static IterArgs iteration_args(const SolveCtx& c) {
   ri_plan* p = c.p;
   const Layout& L = c.L;
   const PlanTables pt = p->tables();
@@ -485,47 +515,41 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   const float scale = (float)(1.0 / ((double)nx * ny));
   uint8_t* rowflag = at<uint8_t>(c.ws, L.rowflag);
   uint8_t* planeflag = at<uint8_t>(c.ws, L.planeflag);
-  hipError_t e;
-#define LTRY(x)                      \
-  do {                               \
-    e = (x);                         \
-    if (e != hipSuccess) return e;   \
-  } while (0)
+  IterArgs I{};
   // objective pieces of x_it
-  if (tm) tm->begin(PH_OBJ);
-  ObjArgs oa{};
+  ObjArgs& oa = I.obj;
   oa.x0 = c.vol[0]; oa.x1 = c.vol[1]; oa.x2 = c.vol[2];
   oa.nx = nx; oa.ny = ny; oa.nz = nz;
   oa.rowflag = rowflag;
   oa.psum = at<double>(c.ws, L.psum);
   oa.ptv = at<double>(c.ws, L.ptv);
   oa.st = c.st;
-  LTRY(launch_obj(oa, nullptr, s));
-  if (tm) tm->end(1);
   // A x_it (skipping empty rows and planes unless dense)
-  if (tm) tm->begin(PH_FORWARD);
-  RowsR2CArgs ra{};
+  RowsR2CArgs& ra = I.fwd_rows;
   for (int k = 0; k < 3; ++k) ra.xs[k] = c.vol[k];
   ra.out = at<float2>(c.ws, L.spec);
   ra.nrows = ny * nz;
   ra.rowflag = c.dense ? nullptr : rowflag;
   ra.st = c.st;
   ra.mode = 2;
-  LTRY(launch_rows_r2c(m, ra, pt, s));
-  FwdColsArgs fa{};
+  ra.pt = pt;
+  FwdColsArgs& fa = I.fwd_cols;
   fa.t = at<float2>(c.ws, L.spec);
   fa.gp = at<float2>(c.ws, L.gp);
   fa.m = m; fa.nz = nz; fa.planes_per_chunk = L.ppc;
   fa.rowflag = c.dense ? nullptr : rowflag;
   fa.planeflag = c.dense ? nullptr : planeflag;
   fa.st = c.st;
-  LTRY(launch_fwd_cols(ny, L.nchunk, fa, pt, s));
-  if (tm) tm->end(2);
+  fa.pt = pt;
   // hologram space: A x_it, data misfit, scalars, residual spectrum
-  if (tm) tm->begin(PH_HOLO);
-  HoloColsInvArgs ha{at<float2>(c.ws, L.gp), at<float2>(c.ws, L.gi), m, L.nchunk, c.st};
-  LTRY(launch_holo_cols_inv(ny, ha, pt, s));
-  RowsC2RArgs ca{};
+  HoloColsInvArgs& ha = I.holo_inv;
+  ha.gp = at<float2>(c.ws, L.gp);
+  ha.gi = at<float2>(c.ws, L.gi);
+  ha.m = m;
+  ha.nchunk = L.nchunk;
+  ha.st = c.st;
+  ha.pt = pt;
+  RowsC2RArgs& ca = I.holo_c2r;
   ca.in = at<float2>(c.ws, L.gi);
   ca.nrows = ny;
   ca.ax0 = at<float>(c.ws, L.ax0);
@@ -535,8 +559,8 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   ca.st = c.st;
   ca.mode = 1;
   ca.scale = scale;
-  LTRY(launch_rows_c2r(m, ca, pt, s));
-  ScalarArgs sa{};
+  ca.pt = pt;
+  ScalarArgs& sa = I.scal;
   sa.st = c.st;
   sa.pdfit = at<double>(c.ws, L.pdfit);
   sa.n_dfit = L.n_dfit;
@@ -544,8 +568,7 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   sa.ptv = at<double>(c.ws, L.ptv);
   sa.n_obj = L.n_obj;
   sa.hist = at<double>(c.ws, L.hist);
-  LTRY(launch_scalars(sa, s));
-  RowsR2CArgs rr{};
+  RowsR2CArgs& rr = I.resid;
   rr.ax0 = at<float>(c.ws, L.ax0);
   rr.ax1 = at<float>(c.ws, L.ax1);
   rr.b = c.b;
@@ -553,13 +576,17 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   rr.nrows = ny;
   rr.st = c.st;
   rr.mode = 1;
-  LTRY(launch_rows_r2c(m, rr, pt, s));
-  if (tm) tm->end(4);
+  rr.pt = pt;
   // adjoint and gradient step: v = y - t A^T r over x_{it-1}
-  if (tm) tm->begin(PH_ADJOINT);
-  AdjColsArgs aa{at<float2>(c.ws, L.th), at<float2>(c.ws, L.spec), m, nz, L.ppc, c.st};
-  LTRY(launch_adj_cols(ny, L.nchunk, aa, pt, s));
-  AdjRowsArgs ar{};
+  AdjColsArgs& aa = I.adj_cols;
+  aa.th = at<float2>(c.ws, L.th);
+  aa.u = at<float2>(c.ws, L.spec);
+  aa.m = m;
+  aa.nz = nz;
+  aa.planes_per_chunk = L.ppc;
+  aa.st = c.st;
+  aa.pt = pt;
+  AdjRowsArgs& ar = I.adj_rows;
   ar.u = at<float2>(c.ws, L.spec);
   ar.nrows = ny * nz;
   ar.ny = ny;
@@ -570,11 +597,9 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   ar.step = c.step;
   ar.mode = 1;
   ar.scale = scale;
-  LTRY(launch_adj_rows(m, ar, pt, s));
-  if (tm) tm->end(2);
+  ar.pt = pt;
   // fused-lasso prox -> x_{it+1}, occupancy flags
-  if (tm) tm->begin(PH_PROX);
-  ProxArgs pa{};
+  ProxArgs& pa = I.prox;
   for (int k = 0; k < 3; ++k) pa.vol[k] = c.vol[k];
   for (int k = 0; k < 3; ++k) pa.pa[k] = at<float>(c.ws, L.pa[k]);
   for (int k = 0; k < 3; ++k) pa.pb[k] = at<float>(c.ws, L.pb[k]);
@@ -587,8 +612,40 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   pa.l1 = c.l1;
   pa.tv = c.tv;
   pa.st = c.st;
+  return I;
+}
+
+// One outer iteration: objective of x_it, momentum, gradient step, prox.
+static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer* tm) {
+  const ri_plan* p = c.p;
+  const int ny = p->g.ny, m = p->m;
+  const IterArgs I = iteration_args(c);
+  hipError_t e;
+#define LTRY(x)                      \
+  do {                               \
+    e = (x);                         \
+    if (e != hipSuccess) return e;   \
+  } while (0)
+  if (tm) tm->begin(PH_OBJ);
+  LTRY(launch_obj(I.obj, s));
+  if (tm) tm->end(1);
+  if (tm) tm->begin(PH_FORWARD);
+  LTRY(launch_rows_r2c(m, I.fwd_rows, s));
+  LTRY(launch_fwd_cols(ny, c.L.nchunk, I.fwd_cols, s));
+  if (tm) tm->end(2);
+  if (tm) tm->begin(PH_HOLO);
+  LTRY(launch_holo_cols_inv(ny, I.holo_inv, s));
+  LTRY(launch_rows_c2r(m, I.holo_c2r, s));
+  LTRY(launch_scalars(I.scal, s));
+  LTRY(launch_rows_r2c(m, I.resid, s));
+  if (tm) tm->end(4);
+  if (tm) tm->begin(PH_ADJOINT);
+  LTRY(launch_adj_cols(ny, c.L.nchunk, I.adj_cols, s));
+  LTRY(launch_adj_rows(m, I.adj_rows, s));
+  if (tm) tm->end(2);
+  if (tm) tm->begin(PH_PROX);
   int nl = 0;
-  LTRY(launch_prox(pa, s, &nl));
+  LTRY(launch_prox(I.prox, s, &nl));
   if (tm) tm->end(nl);
 #undef LTRY
   return hipSuccess;
@@ -736,7 +793,8 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const float
     if (gs != RI_OK) return gs;
   }
   const int total = sp->max_iters + 1;  // the last group only evaluates the final objective
-  const int every = std::max(1, sp->check_every);
+  // with phase timing every launched group is counted, so poll after each one
+  const int every = timing ? 1 : std::max(1, sp->check_every);
   const bool poll = sp->f_ref > 0;
   for (int k = 0; k < total; ++k) {
     if (use_graph) {
@@ -757,6 +815,114 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const float
   return fill_report(c, s, report, timing ? &tm : nullptr);
 }
 
+// ---------------------------------------------------------------------------
+// Batched solve.  Frames advance in lock-step; every kernel of an iteration is
+// launched once per transform size (rows: nx/2, columns: ny) or once for all
+// frames (objective, scalars, TV passes), with per-frame argument structs and
+// block offsets uploaded once into a table region at the end of the workspace.
+// One iteration of all frames is captured as one HIP graph and replayed until
+// a device-side count of stopped frames reaches n.
+// ---------------------------------------------------------------------------
+enum BatchKind { BK_OBJ, BK_FWD_ROWS, BK_FWD_COLS, BK_HOLO_INV, BK_HOLO_C2R, BK_SCAL, BK_RESID, BK_ADJ_COLS,
+                 BK_ADJ_ROWS, BK_TV, BK_COUNT };
+
+struct BatchLaunch {
+  int kind;
+  int size;       // template size (m or ny), 0 when the kernel is not specialised
+  int pass;       // TV pass index
+  std::vector<int> frames;
+  size_t args_off = 0, offs_off = 0;
+  int nblocks = 0;
+};
+
+static size_t kind_args_size(int kind) {
+  switch (kind) {
+    case BK_OBJ: return sizeof(ObjArgs);
+    case BK_FWD_ROWS: case BK_RESID: return sizeof(RowsR2CArgs);
+    case BK_FWD_COLS: return sizeof(FwdColsArgs);
+    case BK_HOLO_INV: return sizeof(HoloColsInvArgs);
+    case BK_HOLO_C2R: return sizeof(RowsC2RArgs);
+    case BK_SCAL: return sizeof(ScalarArgs);
+    case BK_ADJ_COLS: return sizeof(AdjColsArgs);
+    case BK_ADJ_ROWS: return sizeof(AdjRowsArgs);
+    case BK_TV: return tv_pass_args_size();
+  }
+  return 0;
+}
+
+static int prox_pass_count(const ri_plan* p, const ri_solve_params& sp) {
+  return prox_passes(sp.inner_iters, (1.0 / p->lipschitz) * sp.tv);
+}
+
+// The launches of one batched iteration (frames grouped by transform size).
+static std::vector<BatchLaunch> batch_launches(int n, ri_plan* const* plans, const ri_solve_params* params) {
+  std::vector<BatchLaunch> out;
+  auto group = [&](int kind, bool by_m, bool by_ny) {
+    std::vector<int> sizes;
+    for (int i = 0; i < n; ++i) {
+      const int key = by_m ? plans[i]->m : (by_ny ? plans[i]->g.ny : 0);
+      if (std::find(sizes.begin(), sizes.end(), key) == sizes.end()) sizes.push_back(key);
+    }
+    for (int key : sizes) {
+      BatchLaunch b;
+      b.kind = kind;
+      b.size = key;
+      b.pass = 0;
+      for (int i = 0; i < n; ++i) {
+        const int k2 = by_m ? plans[i]->m : (by_ny ? plans[i]->g.ny : 0);
+        if (k2 == key) b.frames.push_back(i);
+      }
+      out.push_back(b);
+    }
+  };
+  group(BK_OBJ, false, false);
+  group(BK_FWD_ROWS, true, false);
+  group(BK_FWD_COLS, false, true);
+  group(BK_HOLO_INV, false, true);
+  group(BK_HOLO_C2R, true, false);
+  group(BK_SCAL, false, false);
+  group(BK_RESID, true, false);
+  group(BK_ADJ_COLS, false, true);
+  group(BK_ADJ_ROWS, true, false);
+  int maxpass = 0;
+  for (int i = 0; i < n; ++i) maxpass = std::max(maxpass, prox_pass_count(plans[i], params[i]));
+  for (int p = 0; p < maxpass; ++p) {
+    BatchLaunch b;
+    b.kind = BK_TV;
+    b.size = 0;
+    b.pass = p;
+    for (int i = 0; i < n; ++i)
+      if (p < prox_pass_count(plans[i], params[i])) b.frames.push_back(i);
+    out.push_back(b);
+  }
+  return out;
+}
+
+static size_t batch_tables_bytes(int n, ri_plan* const* plans, const ri_solve_params* params) {
+  size_t off = 0;
+  for (const BatchLaunch& b : batch_launches(n, plans, params)) {
+    off = align_up(off + kind_args_size(b.kind) * b.frames.size());
+    off = align_up(off + sizeof(uint32_t) * (b.frames.size() + 1));
+  }
+  off = align_up(off + sizeof(SolveState*) * n);  // states for the stop count
+  off = align_up(off + sizeof(int32_t));           // the count
+  return off;
+}
+
+static size_t frame_ws_bytes(const ri_plan* p) { return align_up(make_layout(p, RI_OP_SOLVE).total); }
+
+extern "C" ri_status ri_workspace_size_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
+                                               size_t* bytes) {
+  if (!bytes || n < 0 || (n > 0 && (!plans || !params))) return fail(RI_ERR_INVALID_ARG, "invalid argument");
+  size_t tot = 256;
+  for (int i = 0; i < n; ++i) {
+    if (!plans[i]) return fail(RI_ERR_INVALID_ARG, "plans[%d] is NULL", i);
+    tot += frame_ws_bytes(plans[i]);
+  }
+  *bytes = tot + batch_tables_bytes(n, plans, params);
+  return RI_OK;
+}
+
 extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
                                       const float* const* b, float* const* x_inout, void* ws, size_t ws_bytes,
                                       void* stream, ri_solve_report* reports) {
@@ -764,24 +930,199 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
   if (n == 0) return RI_OK;
   if (!plans || !params || !b || !x_inout) return fail(RI_ERR_INVALID_ARG, "NULL array argument");
   size_t need = 0;
-  std::vector<size_t> offs(n);
-  for (int i = 0; i < n; ++i) {
-    if (!plans[i]) return fail(RI_ERR_INVALID_ARG, "plans[%d] is NULL", i);
-    offs[i] = need;
-    need += align_up(make_layout(plans[i], RI_OP_SOLVE).total);
-  }
+  ri_status vs = ri_workspace_size_batched(n, plans, params, &need);
+  if (vs != RI_OK) return vs;
   if (!ws) return fail(RI_ERR_INVALID_ARG, "workspace is NULL");
   if (ws_bytes < need) return fail(RI_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  // frame workspaces from an aligned base, tables after them
+  char* base = (char*)(((uintptr_t)ws + 255) & ~(uintptr_t)255);
+  std::vector<SolveCtx> ctx(n);
+  size_t off = 0;
   for (int i = 0; i < n; ++i) {
-    ri_status vs = validate_solve(plans[i], &params[i], b[i], x_inout[i], (char*)ws + offs[i],
-                                  align_up(make_layout(plans[i], RI_OP_SOLVE).total));
+    ri_plan* p = plans[i];
+    const size_t fb = frame_ws_bytes(p);
+    vs = validate_solve(p, &params[i], b[i], x_inout[i], base + off, fb);
     if (vs != RI_OK) return vs;
+    if (p->device != plans[0]->device) return fail(RI_ERR_INVALID_ARG, "plans on different devices");
+    SolveCtx& c = ctx[i];
+    c.p = p;
+    c.L = make_layout(p, RI_OP_SOLVE);
+    c.ws = base + off;
+    c.b = b[i];
+    c.vol[0] = x_inout[i];
+    c.vol[1] = at<float>(c.ws, c.L.vol1);
+    c.vol[2] = at<float>(c.ws, c.L.vol2);
+    c.st = at<SolveState>(c.ws, c.L.state);
+    c.step = 1.0 / p->lipschitz;
+    c.l1 = params[i].l1;
+    c.tv = params[i].tv;
+    c.inner = params[i].inner_iters;
+    c.dense = (params[i].flags & RI_SOLVE_DENSE) != 0;
+    c.nonneg = params[i].nonneg ? 1 : 0;
+    off += fb;
   }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j)
+      if (i != j && overlaps(x_inout[i], (size_t)plans[i]->g.nx * plans[i]->g.ny * plans[i]->g.nz * 4, x_inout[j],
+                             (size_t)plans[j]->g.nx * plans[j]->g.ny * plans[j]->g.nz * 4))
+        return fail(RI_ERR_INVALID_ARG, "x_inout[%d] and x_inout[%d] overlap", i, j);
+  char* tables = base + off;
+
+  // per-frame argument structs (grids filled in as the single-frame launchers do)
+  std::vector<IterArgs> it(n);
+  std::vector<std::vector<char>> tv(n);
+  std::vector<int> tv_blocks(n), npass(n);
+  for (int i = 0; i < n; ++i) {
+    it[i] = iteration_args(ctx[i]);
+    const ri_plan* p = plans[i];
+    const int ny = p->g.ny, nz = p->g.nz, m = p->m;
+    dim3 g;
+    g = grid_obj(p->g.nx, ny, nz);             it[i].obj.gx = g.x; it[i].obj.gy = g.y;
+    g = grid_rows(m, ny * nz);                 it[i].fwd_rows.gx = g.x; it[i].fwd_rows.gy = g.y;
+    g = grid_cols(ny, m, ctx[i].L.nchunk);     it[i].fwd_cols.gx = g.x; it[i].fwd_cols.gy = g.y;
+    g = grid_cols(ny, m, 1);                   it[i].holo_inv.gx = g.x; it[i].holo_inv.gy = g.y;
+    g = grid_rows(m, ny);                      it[i].holo_c2r.gx = g.x; it[i].holo_c2r.gy = g.y;
+    it[i].scal.gx = 1; it[i].scal.gy = 1;
+    g = grid_rows(m, ny);                      it[i].resid.gx = g.x; it[i].resid.gy = g.y;
+    g = grid_cols(ny, m, ctx[i].L.nchunk);     it[i].adj_cols.gx = g.x; it[i].adj_cols.gy = g.y;
+    g = grid_rows(m, ny * nz);                 it[i].adj_rows.gx = g.x; it[i].adj_rows.gy = g.y;
+    npass[i] = prox_pass_count(p, params[i]);
+    tv[i].resize(tv_pass_args_size() * npass[i]);
+    prox_pass_args(it[i].prox, tv[i].data(), &tv_blocks[i]);
+  }
+  auto frame_blocks = [&](int kind, int i) -> int {
+    const IterArgs& a = it[i];
+    switch (kind) {
+      case BK_OBJ: return a.obj.gx * a.obj.gy;
+      case BK_FWD_ROWS: return a.fwd_rows.gx * a.fwd_rows.gy;
+      case BK_FWD_COLS: return a.fwd_cols.gx * a.fwd_cols.gy;
+      case BK_HOLO_INV: return a.holo_inv.gx * a.holo_inv.gy;
+      case BK_HOLO_C2R: return a.holo_c2r.gx * a.holo_c2r.gy;
+      case BK_SCAL: return 1;
+      case BK_RESID: return a.resid.gx * a.resid.gy;
+      case BK_ADJ_COLS: return a.adj_cols.gx * a.adj_cols.gy;
+      case BK_ADJ_ROWS: return a.adj_rows.gx * a.adj_rows.gy;
+      case BK_TV: return tv_blocks[i];
+    }
+    return 0;
+  };
+  auto frame_args = [&](int kind, int pass, int i) -> const void* {
+    const IterArgs& a = it[i];
+    switch (kind) {
+      case BK_OBJ: return &a.obj;
+      case BK_FWD_ROWS: return &a.fwd_rows;
+      case BK_FWD_COLS: return &a.fwd_cols;
+      case BK_HOLO_INV: return &a.holo_inv;
+      case BK_HOLO_C2R: return &a.holo_c2r;
+      case BK_SCAL: return &a.scal;
+      case BK_RESID: return &a.resid;
+      case BK_ADJ_COLS: return &a.adj_cols;
+      case BK_ADJ_ROWS: return &a.adj_rows;
+      case BK_TV: return tv[i].data() + tv_pass_args_size() * pass;
+    }
+    return nullptr;
+  };
+  // stage the tables on the host, upload once
+  std::vector<BatchLaunch> launches = batch_launches(n, plans, params);
+  const size_t tbytes = batch_tables_bytes(n, plans, params);
+  std::vector<char> host(tbytes, 0);
+  size_t t = 0;
+  for (BatchLaunch& bl : launches) {
+    const size_t as = kind_args_size(bl.kind);
+    bl.args_off = t;
+    for (size_t k = 0; k < bl.frames.size(); ++k)
+      std::memcpy(host.data() + t + k * as, frame_args(bl.kind, bl.pass, bl.frames[k]), as);
+    t = align_up(t + as * bl.frames.size());
+    bl.offs_off = t;
+    uint32_t* o = reinterpret_cast<uint32_t*>(host.data() + t);
+    uint32_t acc = 0;
+    for (size_t k = 0; k < bl.frames.size(); ++k) {
+      o[k] = acc;
+      acc += (uint32_t)frame_blocks(bl.kind, bl.frames[k]);
+    }
+    o[bl.frames.size()] = acc;
+    bl.nblocks = (int)acc;
+    t = align_up(t + sizeof(uint32_t) * (bl.frames.size() + 1));
+  }
+  const size_t states_off = t;
+  for (int i = 0; i < n; ++i) reinterpret_cast<SolveState**>(host.data() + t)[i] = ctx[i].st;
+  t = align_up(t + sizeof(SolveState*) * n);
+  const size_t count_off = t;
+  HIP_TRY(hipMemcpyAsync(tables, host.data(), tbytes, hipMemcpyHostToDevice, s));
+  HIP_TRY(hipStreamSynchronize(s));  // the staging buffer is pageable and local
+
+  auto enqueue_batch_iteration = [&](hipStream_t q) -> hipError_t {
+    hipError_t e = hipSuccess;
+    for (const BatchLaunch& bl : launches) {
+      if (bl.nblocks == 0) continue;
+      const BatchMap mp{reinterpret_cast<const uint32_t*>(tables + bl.offs_off), (int)bl.frames.size()};
+      const void* a = tables + bl.args_off;
+      switch (bl.kind) {
+        case BK_OBJ: e = launch_obj_batched((const ObjArgs*)a, mp, bl.nblocks, q); break;
+        case BK_FWD_ROWS: case BK_RESID:
+          e = launch_rows_r2c_batched(bl.size, (const RowsR2CArgs*)a, mp, bl.nblocks, q); break;
+        case BK_FWD_COLS: e = launch_fwd_cols_batched(bl.size, (const FwdColsArgs*)a, mp, bl.nblocks, q); break;
+        case BK_HOLO_INV:
+          e = launch_holo_cols_inv_batched(bl.size, (const HoloColsInvArgs*)a, mp, bl.nblocks, q); break;
+        case BK_HOLO_C2R: e = launch_rows_c2r_batched(bl.size, (const RowsC2RArgs*)a, mp, bl.nblocks, q); break;
+        case BK_SCAL: e = launch_scalars_batched((const ScalarArgs*)a, mp, bl.nblocks, q); break;
+        case BK_ADJ_COLS: e = launch_adj_cols_batched(bl.size, (const AdjColsArgs*)a, mp, bl.nblocks, q); break;
+        case BK_ADJ_ROWS: e = launch_adj_rows_batched(bl.size, (const AdjRowsArgs*)a, mp, bl.nblocks, q); break;
+        case BK_TV: e = launch_tv_pass_batched(a, mp, bl.nblocks, q); break;
+      }
+      if (e != hipSuccess) return e;
+    }
+    return launch_count_done(reinterpret_cast<SolveState* const*>(tables + states_off), n,
+                             reinterpret_cast<int32_t*>(tables + count_off), q);
+  };
+
+  for (int i = 0; i < n; ++i) HIP_TRY(enqueue_setup(ctx[i], &params[i], s));
+  const bool use_graph = !(params[0].flags & RI_SOLVE_NO_GRAPH);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    hipStream_t cap = plans[0]->capture;
+    HIP_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeRelaxed));
+    hipError_t e = enqueue_batch_iteration(cap);
+    hipError_t e2 = hipStreamEndCapture(cap, &graph);
+    if (e != hipSuccess || e2 != hipSuccess) {
+      if (graph) hipGraphDestroy(graph);
+      return fail(RI_ERR_HIP, "batch capture: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      hipGraphDestroy(graph);
+      return fail(RI_ERR_HIP, "batch instantiate: %s", hipGetErrorString(e));
+    }
+  }
+  int total = 0, every = 1 << 30;
+  for (int i = 0; i < n; ++i) {
+    total = std::max(total, params[i].max_iters + 1);
+    every = std::min(every, std::max(1, params[i].check_every));
+  }
+  ri_status rs = RI_OK;
+  for (int k = 0; k < total && rs == RI_OK; ++k) {
+    hipError_t e = use_graph ? hipGraphLaunch(exec, s) : enqueue_batch_iteration(s);
+    if (e != hipSuccess) rs = fail(RI_ERR_HIP, "batch iteration: %s", hipGetErrorString(e));
+    if (rs == RI_OK && (k + 1) % every == 0 && k + 1 < total) {
+      int32_t* hf = plans[0]->host_flag;
+      e = hipMemcpyAsync(hf, tables + count_off, sizeof(int32_t), hipMemcpyDeviceToHost, s);
+      if (e == hipSuccess) e = hipStreamSynchronize(s);
+      if (e != hipSuccess) rs = fail(RI_ERR_HIP, "batch poll: %s", hipGetErrorString(e));
+      else if (*hf >= n) break;
+    }
+  }
+  if (exec) hipGraphExecDestroy(exec);
+  if (graph) hipGraphDestroy(graph);
+  if (rs != RI_OK) return rs;
+  for (int i = 0; i < n; ++i)
+    HIP_TRY(launch_copy_final(ctx[i].vol[0], ctx[i].vol[1], ctx[i].vol[2], x_inout[i],
+                              (size_t)plans[i]->g.nx * plans[i]->g.ny * plans[i]->g.nz, ctx[i].st, s));
+  if (!reports) return RI_OK;
   ri_status agg = RI_OK;
   for (int i = 0; i < n; ++i) {
-    ri_status st = ri_solve(plans[i], &params[i], b[i], x_inout[i], (char*)ws + offs[i],
-                            align_up(make_layout(plans[i], RI_OP_SOLVE).total), stream,
-                            reports ? &reports[i] : nullptr);
+    const ri_status st = fill_report(ctx[i], s, &reports[i], nullptr);
     if (st != RI_OK && agg == RI_OK) agg = st;
   }
   return agg;

@@ -88,13 +88,13 @@ __device__ __forceinline__ double block_sum(double v, double* red) {
 // Packed R2C of real rows.  Block: ROWS rows x T threads; each row in LDS.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
-k_rows_r2c(RowsR2CArgs a, const float2* __restrict__ tw) {
+__device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int by) {
+  const float2* __restrict__ tw = a.pt.tw_row;
   constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M);
   __shared__ float2 lds[ROWS][M];
   if (solve_done(a.st)) return;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * ROWS + r;
+  const int row = bx * ROWS + r;
   const bool active = row < a.nrows && (a.rowflag == nullptr || a.rowflag[row] != 0);
   if (!__syncthreads_or(active)) return;
   float2* buf = lds[r];
@@ -174,14 +174,14 @@ __device__ __forceinline__ void c2r_prepare(float2* buf, int t, const float2* __
 }
 
 template <int M>
-__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
-k_rows_c2r(RowsC2RArgs a, const float2* __restrict__ tw) {
+__device__ __forceinline__ void rows_c2r_body(const RowsC2RArgs& a, int bx, int by) {
+  const float2* __restrict__ tw = a.pt.tw_row;
   constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M), NT = ROWS * T;
   __shared__ float2 lds[ROWS][M];
   __shared__ double red[16];
   if (solve_done(a.st)) return;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * ROWS + r;
+  const int row = bx * ROWS + r;
   const bool active = row < a.nrows;
   float2* buf = lds[r];
   const float2* src = a.in + (size_t)row * M;
@@ -216,7 +216,7 @@ k_rows_c2r(RowsC2RArgs a, const float2* __restrict__ tw) {
     }
   }
   acc = block_sum<NT>(acc, red);
-  if (threadIdx.x == 0) a.partial[blockIdx.x] = 0.5 * acc;
+  if (threadIdx.x == 0) a.partial[bx] = 0.5 * acc;
 }
 
 // ---------------------------------------------------------------------------
@@ -224,14 +224,14 @@ k_rows_c2r(RowsC2RArgs a, const float2* __restrict__ tw) {
 // Block: W columns x TC threads per column (TC = NY / P).
 // ---------------------------------------------------------------------------
 template <int NY>
-__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
-k_fwd_cols(FwdColsArgs a, PlanTables pt) {
+__device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int by) {
+  const PlanTables& pt = a.pt;
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
-  const int kx = blockIdx.x * W + w;
+  const int kx = bx * W + w;
   const bool colok = kx < m;           // tiles may overhang the last column
   const bool col0 = (kx == 0);
   double th[P];
@@ -240,7 +240,7 @@ k_fwd_cols(FwdColsArgs a, PlanTables pt) {
   float2 acc[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) acc[s] = make_float2(0.f, 0.f);
-  const int j0 = blockIdx.y * a.planes_per_chunk;
+  const int j0 = by * a.planes_per_chunk;
   const int j1 = min(a.nz, j0 + a.planes_per_chunk);
   for (int j = j0; j < j1; ++j) {
     if (a.planeflag != nullptr && a.planeflag[j] == 0) continue;
@@ -273,7 +273,7 @@ k_fwd_cols(FwdColsArgs a, PlanTables pt) {
     __syncthreads();
   }
   if (!colok) return;
-  float2* dst = a.gp + (size_t)blockIdx.y * NY * m + kx;
+  float2* dst = a.gp + (size_t)by * NY * m + kx;
 #pragma unroll
   for (int s = 0; s < P; ++s) dst[(size_t)(q + s * TC) * m] = acc[s];
 }
@@ -282,14 +282,14 @@ k_fwd_cols(FwdColsArgs a, PlanTables pt) {
 // Sum of partial spectra and inverse column FFT (hologram sized).
 // ---------------------------------------------------------------------------
 template <int NY>
-__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
-k_holo_cols_inv(HoloColsInvArgs a, PlanTables pt) {
+__device__ __forceinline__ void holo_cols_inv_body(const HoloColsInvArgs& a, int bx, int by) {
+  const PlanTables& pt = a.pt;
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
-  const int kx = blockIdx.x * W + w;
+  const int kx = bx * W + w;
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const int y = q + s * TC;
@@ -314,15 +314,15 @@ k_holo_cols_inv(HoloColsInvArgs a, PlanTables pt) {
 // the chunk multiplies it by cos(phase_j) and inverse-transforms the columns.
 // ---------------------------------------------------------------------------
 template <int NY>
-__global__ void __launch_bounds__(kColW(NY) * (NY / kColP(NY)))
-k_adj_cols(AdjColsArgs a, PlanTables pt) {
+__device__ __forceinline__ void adj_cols_body(const AdjColsArgs& a, int bx, int by) {
+  const PlanTables& pt = a.pt;
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
   __shared__ float2 r0[NY];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
-  const int kx = blockIdx.x * W + w;
+  const int kx = bx * W + w;
   const bool colok = kx < m;
   const bool col0 = (kx == 0);
 #pragma unroll
@@ -342,7 +342,7 @@ k_adj_cols(AdjColsArgs a, PlanTables pt) {
     th[s] = colok ? pt.theta[(size_t)y * (m + 1) + kx] : 0.0;
   }
   __syncthreads();
-  const int j0 = blockIdx.y * a.planes_per_chunk;
+  const int j0 = by * a.planes_per_chunk;
   const int j1 = min(a.nz, j0 + a.planes_per_chunk);
   for (int j = j0; j < j1; ++j) {
     const double2 zc = pt.zc[j];
@@ -380,13 +380,13 @@ k_adj_cols(AdjColsArgs a, PlanTables pt) {
 // v = y - t A^T r with the extrapolated point y formed on the fly.
 // ---------------------------------------------------------------------------
 template <int M>
-__global__ void __launch_bounds__(kRowsPerBlock(M) * kRowThreads(M))
-k_adj_rows(AdjRowsArgs a, const float2* __restrict__ tw) {
+__device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int by) {
+  const float2* __restrict__ tw = a.pt.tw_row;
   constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M);
   __shared__ float2 lds[ROWS][M];
   if (solve_done(a.st)) return;
   const int r = threadIdx.x / T, t = threadIdx.x % T;
-  const int row = blockIdx.x * ROWS + r;
+  const int row = bx * ROWS + r;
   const bool active = row < a.nrows;
   float2* buf = lds[r];
   const float2* src = a.u + (size_t)row * M;
@@ -434,7 +434,7 @@ k_adj_rows(AdjRowsArgs a, const float2* __restrict__ tw) {
 constexpr int kObjRows = 4;
 constexpr int kObjThreads = 256;
 
-__global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) {
+__device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
   __shared__ double red[2][16];
   if (solve_done(a.st)) return;
   const float* x = a.x0;
@@ -447,7 +447,7 @@ __global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) {
   const long nrows = (long)ny * nz;
   double s_acc = 0.0, t_acc = 0.0;
   for (int rr = 0; rr < kObjRows; ++rr) {
-    const long row = (long)blockIdx.x * kObjRows + rr;
+    const long row = (long)bx * kObjRows + rr;
     if (row >= nrows) break;
     const int z = (int)(row / ny), y = (int)(row % ny);
     const bool has_y = y + 1 < ny, has_z = z + 1 < nz;
@@ -475,14 +475,9 @@ __global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) {
   __syncthreads();
   t_acc = block_sum<kObjThreads>(t_acc, red[1]);
   if (threadIdx.x == 0) {
-    a.psum[blockIdx.x] = s_acc;
-    a.ptv[blockIdx.x] = t_acc;
+    a.psum[bx] = s_acc;
+    a.ptv[bx] = t_acc;
   }
-}
-
-int obj_blocks(int nx, int ny, int nz) {
-  (void)nx;
-  return (int)(((long)ny * nz + kObjRows - 1) / kObjRows);
 }
 
 // ---------------------------------------------------------------------------
@@ -490,7 +485,7 @@ int obj_blocks(int nx, int ny, int nz) {
 // ---------------------------------------------------------------------------
 constexpr int kScalarThreads = 1024;
 
-__global__ void __launch_bounds__(kScalarThreads) k_scalars(ScalarArgs a) {
+__device__ __forceinline__ void scalars_body(const ScalarArgs& a, int, int) {
   __shared__ double red[3][16];
   SolveState* st = a.st;
   if (st->done) return;
@@ -639,17 +634,6 @@ hipError_t launch_state_init(SolveState* st, const StateInit& init, hipStream_t 
   hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, s, st, init);
   return hipGetLastError();
 }
-hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kScalarThreads), 0, s, a);
-  return hipGetLastError();
-}
-hipError_t launch_obj(const ObjArgs& a, int* nblocks_out, hipStream_t s) {
-  const int nb = obj_blocks(a.nx, a.ny, a.nz);
-  if (nblocks_out) *nblocks_out = nb;
-  hipLaunchKernelGGL(k_obj, dim3(nb), dim3(kObjThreads), 0, s, a);
-  return hipGetLastError();
-}
-
 // ---------------------------------------------------------------------------
 // Lipschitz constant: S(f) = sum_j cos^2(2 pi (c_j + z_j theta(f))) in FP64,
 // block maxima over the half-spectrum grid (the full grid is symmetric).
@@ -689,101 +673,208 @@ hipError_t launch_lipschitz(const PlanTables& pt, int m, int ny, int nz, double*
 }
 
 // ---------------------------------------------------------------------------
-// Size dispatch
+// Single-frame and batched entry kernels
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void batch_find(BatchMap map, int& frame, int& local) {
+  const uint32_t b = blockIdx.x;
+  int lo = 0, hi = map.n;  // largest f with offs[f] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (map.offs[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  frame = lo;
+  local = (int)(b - map.offs[lo]);
+}
+
+template <class Args>
+__device__ __forceinline__ void batch_entry(const Args* __restrict__ args, BatchMap map,
+                                            Args& a, int& bx, int& by) {
+  int f, lb;
+  batch_find(map, f, lb);
+  a = args[f];
+  bx = lb % a.gx;
+  by = lb / a.gx;
+}
+
+#define RIHVR_ENTRY_T(NAME, BODY, ARGS, TP, NT)                                                   \
+  template <int TP>                                                                               \
+  __global__ void __launch_bounds__(NT) NAME(ARGS a) { BODY<TP>(a, blockIdx.x, blockIdx.y); }      \
+  template <int TP>                                                                               \
+  __global__ void __launch_bounds__(NT) NAME##_b(const ARGS* __restrict__ args,                   \
+                                                 BatchMap map) {              \
+    ARGS a;                                                                                       \
+    int bx, by;                                                                                   \
+    batch_entry(args, map, a, bx, by);                                                            \
+    BODY<TP>(a, bx, by);                                                                          \
+  }
+
+RIHVR_ENTRY_T(k_rows_r2c, rows_r2c_body, RowsR2CArgs, M, kRowsPerBlock(M) * kRowThreads(M))
+RIHVR_ENTRY_T(k_rows_c2r, rows_c2r_body, RowsC2RArgs, M, kRowsPerBlock(M) * kRowThreads(M))
+RIHVR_ENTRY_T(k_adj_rows, adj_rows_body, AdjRowsArgs, M, kRowsPerBlock(M) * kRowThreads(M))
+RIHVR_ENTRY_T(k_fwd_cols, fwd_cols_body, FwdColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
+RIHVR_ENTRY_T(k_holo_cols_inv, holo_cols_inv_body, HoloColsInvArgs, NY, kColW(NY) * (NY / kColP(NY)))
+RIHVR_ENTRY_T(k_adj_cols, adj_cols_body, AdjColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
+#undef RIHVR_ENTRY_T
+
+__global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) { obj_body(a, blockIdx.x, blockIdx.y); }
+__global__ void __launch_bounds__(kObjThreads) k_obj_b(const ObjArgs* __restrict__ args,
+                                                       BatchMap map) {
+  ObjArgs a;
+  int bx, by;
+  batch_entry(args, map, a, bx, by);
+  obj_body(a, bx, by);
+}
+__global__ void __launch_bounds__(kScalarThreads) k_scalars(ScalarArgs a) { scalars_body(a, 0, 0); }
+__global__ void __launch_bounds__(kScalarThreads) k_scalars_b(const ScalarArgs* __restrict__ args,
+                                                              BatchMap map) {
+  ScalarArgs a;
+  int bx, by;
+  batch_entry(args, map, a, bx, by);
+  scalars_body(a, bx, by);
+}
+
+__global__ void k_count_done(const SolveState* const* __restrict__ states, int n, int32_t* out) {
+  int c = 0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) c += states[i]->done != 0;
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  __shared__ int red[16];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += red[w];
+    *out = t;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grids and size dispatch
 // ---------------------------------------------------------------------------
 #define RIHVR_ROW_SIZES(X) X(8) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) \
   X(12) X(24) X(48) X(96) X(192) X(384) X(768)
 #define RIHVR_COL_SIZES(X) X(16) X(32) X(64) X(128) X(256) X(512) X(1024) X(2048) \
   X(24) X(48) X(96) X(192) X(384) X(768) X(1536)
 
-hipError_t launch_rows_r2c(int m, const RowsR2CArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (m) {
-#define CASE(M)                                                                           \
-  case M: {                                                                               \
-    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
-    hipLaunchKernelGGL(k_rows_r2c<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
-                       pt.tw_row);                                                        \
-    return hipGetLastError();                                                             \
+dim3 grid_rows(int m, int nrows) {
+  const int r = kRowsPerBlock(m);
+  return dim3((nrows + r - 1) / r);
+}
+dim3 grid_cols(int ny, int m, int nchunk) {
+  const int w = kColW(ny);
+  return dim3((m + w - 1) / w, nchunk);
+}
+static int row_threads(int m) { return kRowsPerBlock(m) * kRowThreads(m); }
+static int col_threads(int ny) { return kColW(ny) * (ny / kColP(ny)); }
+
+#define RIHVR_DISPATCH(SIZES, VAR, SINGLE_OR_BATCH)                                          \
+  switch (VAR) {                                                                             \
+    SIZES(SINGLE_OR_BATCH)                                                                   \
+    default: return hipErrorInvalidValue;                                                    \
   }
-    RIHVR_ROW_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+
+hipError_t launch_rows_r2c(int m, RowsR2CArgs a, hipStream_t s) {
+  const dim3 g = grid_rows(m, a.nrows);
+  a.gx = g.x; a.gy = g.y;
+#define C(M) case M: hipLaunchKernelGGL(k_rows_r2c<M>, g, dim3(row_threads(M)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_rows_r2c_batched(int m, const RowsR2CArgs* args, BatchMap map, int nb, hipStream_t s) {
+#define C(M) case M: hipLaunchKernelGGL(k_rows_r2c_b<M>, dim3(nb), dim3(row_threads(M)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_rows_c2r(int m, RowsC2RArgs a, hipStream_t s) {
+  const dim3 g = grid_rows(m, a.nrows);
+  a.gx = g.x; a.gy = g.y;
+#define C(M) case M: hipLaunchKernelGGL(k_rows_c2r<M>, g, dim3(row_threads(M)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_rows_c2r_batched(int m, const RowsC2RArgs* args, BatchMap map, int nb, hipStream_t s) {
+#define C(M) case M: hipLaunchKernelGGL(k_rows_c2r_b<M>, dim3(nb), dim3(row_threads(M)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_adj_rows(int m, AdjRowsArgs a, hipStream_t s) {
+  const dim3 g = grid_rows(m, a.nrows);
+  a.gx = g.x; a.gy = g.y;
+#define C(M) case M: hipLaunchKernelGGL(k_adj_rows<M>, g, dim3(row_threads(M)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_adj_rows_batched(int m, const AdjRowsArgs* args, BatchMap map, int nb, hipStream_t s) {
+#define C(M) case M: hipLaunchKernelGGL(k_adj_rows_b<M>, dim3(nb), dim3(row_threads(M)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_ROW_SIZES, m, C)
+#undef C
+}
+hipError_t launch_fwd_cols(int ny, int nchunk, FwdColsArgs a, hipStream_t s) {
+  const dim3 g = grid_cols(ny, a.m, nchunk);
+  a.gx = g.x; a.gy = g.y;
+#define C(NY) case NY: hipLaunchKernelGGL(k_fwd_cols<NY>, g, dim3(col_threads(NY)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
+}
+hipError_t launch_fwd_cols_batched(int ny, const FwdColsArgs* args, BatchMap map, int nb, hipStream_t s) {
+#define C(NY) case NY: hipLaunchKernelGGL(k_fwd_cols_b<NY>, dim3(nb), dim3(col_threads(NY)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
+}
+hipError_t launch_holo_cols_inv(int ny, HoloColsInvArgs a, hipStream_t s) {
+  const dim3 g = grid_cols(ny, a.m, 1);
+  a.gx = g.x; a.gy = g.y;
+#define C(NY) case NY: hipLaunchKernelGGL(k_holo_cols_inv<NY>, g, dim3(col_threads(NY)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
+}
+hipError_t launch_holo_cols_inv_batched(int ny, const HoloColsInvArgs* args, BatchMap map, int nb,
+                                        hipStream_t s) {
+#define C(NY) case NY: hipLaunchKernelGGL(k_holo_cols_inv_b<NY>, dim3(nb), dim3(col_threads(NY)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
+}
+hipError_t launch_adj_cols(int ny, int nchunk, AdjColsArgs a, hipStream_t s) {
+  const dim3 g = grid_cols(ny, a.m, nchunk);
+  a.gx = g.x; a.gy = g.y;
+#define C(NY) case NY: hipLaunchKernelGGL(k_adj_cols<NY>, g, dim3(col_threads(NY)), 0, s, a); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
+}
+hipError_t launch_adj_cols_batched(int ny, const AdjColsArgs* args, BatchMap map, int nb, hipStream_t s) {
+#define C(NY) case NY: hipLaunchKernelGGL(k_adj_cols_b<NY>, dim3(nb), dim3(col_threads(NY)), 0, s, args, map); return hipGetLastError();
+  RIHVR_DISPATCH(RIHVR_COL_SIZES, ny, C)
+#undef C
 }
 
-hipError_t launch_rows_c2r(int m, const RowsC2RArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (m) {
-#define CASE(M)                                                                           \
-  case M: {                                                                               \
-    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
-    hipLaunchKernelGGL(k_rows_c2r<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
-                       pt.tw_row);                                                        \
-    return hipGetLastError();                                                             \
-  }
-    RIHVR_ROW_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+dim3 grid_obj(int nx, int ny, int nz) {
+  (void)nx;
+  return dim3((unsigned)(((long)ny * nz + kObjRows - 1) / kObjRows));
 }
-
-hipError_t launch_adj_rows(int m, const AdjRowsArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (m) {
-#define CASE(M)                                                                           \
-  case M: {                                                                               \
-    const int nb = (a.nrows + kRowsPerBlock(M) - 1) / kRowsPerBlock(M);                   \
-    hipLaunchKernelGGL(k_adj_rows<M>, dim3(nb), dim3(kRowsPerBlock(M) * kRowThreads(M)), 0, s, a, \
-                       pt.tw_row);                                                        \
-    return hipGetLastError();                                                             \
-  }
-    RIHVR_ROW_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+int obj_blocks(int nx, int ny, int nz) { return (int)grid_obj(nx, ny, nz).x; }
+hipError_t launch_obj(ObjArgs a, hipStream_t s) {
+  const dim3 g = grid_obj(a.nx, a.ny, a.nz);
+  a.gx = g.x; a.gy = 1;
+  hipLaunchKernelGGL(k_obj, g, dim3(kObjThreads), 0, s, a);
+  return hipGetLastError();
 }
-
-hipError_t launch_fwd_cols(int ny, int nchunk, const FwdColsArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (ny) {
-#define CASE(NY)                                                                          \
-  case NY: {                                                                              \
-    constexpr int W = kColW(NY);                                                          \
-    hipLaunchKernelGGL(k_fwd_cols<NY>, dim3((a.m + W - 1) / W, nchunk), dim3(W * (NY / kColP(NY))), 0, \
-                       s, a, pt);                                                         \
-    return hipGetLastError();                                                             \
-  }
-    RIHVR_COL_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_obj_batched(const ObjArgs* args, BatchMap map, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_obj_b, dim3(nb), dim3(kObjThreads), 0, s, args, map);
+  return hipGetLastError();
 }
-
-hipError_t launch_holo_cols_inv(int ny, const HoloColsInvArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (ny) {
-#define CASE(NY)                                                                          \
-  case NY: {                                                                              \
-    constexpr int W = kColW(NY);                                                          \
-    hipLaunchKernelGGL(k_holo_cols_inv<NY>, dim3((a.m + W - 1) / W), dim3(W * (NY / kColP(NY))), 0, s, \
-                       a, pt);                                                            \
-    return hipGetLastError();                                                             \
-  }
-    RIHVR_COL_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_scalars(ScalarArgs a, hipStream_t s) {
+  a.gx = 1; a.gy = 1;
+  hipLaunchKernelGGL(k_scalars, dim3(1), dim3(kScalarThreads), 0, s, a);
+  return hipGetLastError();
 }
-
-hipError_t launch_adj_cols(int ny, int nchunk, const AdjColsArgs& a, const PlanTables& pt, hipStream_t s) {
-  switch (ny) {
-#define CASE(NY)                                                                          \
-  case NY: {                                                                              \
-    constexpr int W = kColW(NY);                                                          \
-    hipLaunchKernelGGL(k_adj_cols<NY>, dim3((a.m + W - 1) / W, nchunk), dim3(W * (NY / kColP(NY))), 0, \
-                       s, a, pt);                                                         \
-    return hipGetLastError();                                                             \
-  }
-    RIHVR_COL_SIZES(CASE)
-#undef CASE
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_scalars_batched(const ScalarArgs* args, BatchMap map, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(k_scalars_b, dim3(nb), dim3(kScalarThreads), 0, s, args, map);
+  return hipGetLastError();
+}
+hipError_t launch_count_done(const SolveState* const* states, int n, int32_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_count_done, dim3(1), dim3(1024), 0, s, states, n, out);
+  return hipGetLastError();
 }
 
 }  // namespace rihvr

@@ -48,8 +48,20 @@ int col_tile_width(int ny);    // columns per column tile
 bool fft_len_supported(int L);
 
 // ---------------------------------------------------------------------------
-// Kernel launchers (kernels.hip).  All return hipError_t of the launch.
+// Every kernel exists in two forms.  The single form runs one frame with the
+// grid of that frame.  The batched form runs many frames (of one transform size
+// where the kernel is specialised on a size) in one launch: the frames' block
+// counts are laid end to end (prefix offsets offs[0..n], offs[0] = 0); block b
+// finds its frame f with offs[f] <= b < offs[f+1], takes that frame's argument
+// struct from a device array and decomposes b - offs[f] with the frame's grid
+// (gx, gy), which the host writes into each struct.  Frames whose solve has
+// stopped return at once.
 // ---------------------------------------------------------------------------
+struct BatchMap {
+  const uint32_t* offs;  // device, n + 1 entries
+  int n;
+};
+
 // Row-wise packed R2C of real rows [nrows][2m] -> [nrows][m] complex.  Rows with
 // rowflag == 0 are skipped (nothing written).  mode 0: input x;  mode 1: input
 // r = (1+beta) ax[cur] - beta ax[prev] - b computed on the fly (solver residual);
@@ -63,8 +75,12 @@ struct RowsR2CArgs {
   const uint8_t* rowflag;    // nullable
   const SolveState* st;      // nullable (mode 0 outside a solve)
   int mode;
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_rows_r2c(int m, const RowsR2CArgs& a, const PlanTables& pt, hipStream_t s);
+dim3 grid_rows(int m, int nrows);
+hipError_t launch_rows_r2c(int m, RowsR2CArgs a, hipStream_t s);
+hipError_t launch_rows_r2c_batched(int m, const RowsR2CArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
 // Column FFT of the packed spectra of planes [z-chunk], multiply by cos(phase_j)
 // and sum over the planes of the chunk -> partial spectra gp[chunk][ny][m].
@@ -75,14 +91,22 @@ struct FwdColsArgs {
   const uint8_t* rowflag;    // nullable [nz][ny]
   const uint8_t* planeflag;  // nullable [nz]
   const SolveState* st;      // nullable
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_fwd_cols(int ny, int nchunk, const FwdColsArgs& a, const PlanTables& pt, hipStream_t s);
+dim3 grid_cols(int ny, int m, int nchunk);
+hipError_t launch_fwd_cols(int ny, int nchunk, FwdColsArgs a, hipStream_t s);
+hipError_t launch_fwd_cols_batched(int ny, const FwdColsArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
 // Sum of nchunk partial spectra, then unscaled inverse column FFT -> gi [ny][m].
 struct HoloColsInvArgs {
   const float2* gp; float2* gi; int m, nchunk; const SolveState* st;
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_holo_cols_inv(int ny, const HoloColsInvArgs& a, const PlanTables& pt, hipStream_t s);
+hipError_t launch_holo_cols_inv(int ny, HoloColsInvArgs a, hipStream_t s);
+hipError_t launch_holo_cols_inv_batched(int ny, const HoloColsInvArgs* args, BatchMap map, int nblocks,
+                                        hipStream_t s);
 
 // Row-wise packed C2R (scaled by 1/(nx ny)).  mode 0: write to out.  mode 1
 // (solver): write ax[it & 1] and a per-block FP64 partial of 1/2 sum (ax - b)^2.
@@ -94,15 +118,21 @@ struct RowsC2RArgs {
   const SolveState* st;
   int mode;
   float scale;
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_rows_c2r(int m, const RowsC2RArgs& a, const PlanTables& pt, hipStream_t s);
+hipError_t launch_rows_c2r(int m, RowsC2RArgs a, hipStream_t s);
+hipError_t launch_rows_c2r_batched(int m, const RowsC2RArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
 // Adjoint column pass: column FFT of the packed residual spectrum, then for each
 // plane of the chunk multiply by cos(phase_j) and inverse column FFT -> u[j].
 struct AdjColsArgs {
   const float2* th; float2* u; int m, nz, planes_per_chunk; const SolveState* st;
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_adj_cols(int ny, int nchunk, const AdjColsArgs& a, const PlanTables& pt, hipStream_t s);
+hipError_t launch_adj_cols(int ny, int nchunk, AdjColsArgs a, hipStream_t s);
+hipError_t launch_adj_cols_batched(int ny, const AdjColsArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
 // Adjoint row pass: packed C2R of u[j][y] scaled by 1/(nx ny).  mode 0: out = g.
 // mode 1 (solver): v = y - step g with y = x[cur] + beta (x[cur] - x[prev]),
@@ -116,8 +146,11 @@ struct AdjRowsArgs {
   double step;
   int mode;
   float scale;
+  PlanTables pt;
+  int gx, gy;
 };
-hipError_t launch_adj_rows(int m, const AdjRowsArgs& a, const PlanTables& pt, hipStream_t s);
+hipError_t launch_adj_rows(int m, AdjRowsArgs a, hipStream_t s);
+hipError_t launch_adj_rows_batched(int m, const AdjRowsArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
 // Objective pieces of a volume: per-block partials of sum(x) and TV3D(x).
 struct ObjArgs {
@@ -126,18 +159,27 @@ struct ObjArgs {
   const uint8_t* rowflag;     // nullable: skip rows whose neighbourhood is empty
   double* psum; double* ptv;  // [nblocks]
   const SolveState* st;
+  int gx, gy;
 };
-hipError_t launch_obj(const ObjArgs& a, int* nblocks_out, hipStream_t s);
+dim3 grid_obj(int nx, int ny, int nz);
 int obj_blocks(int nx, int ny, int nz);
+hipError_t launch_obj(ObjArgs a, hipStream_t s);
+hipError_t launch_obj_batched(const ObjArgs* args, BatchMap map, int nblocks, hipStream_t s);
 
-// FISTA scalars: reduce partials, objective, gap, stop flag, momentum, slots.
+// FISTA scalars (one block per frame): reduce partials, objective, gap, stop
+// flag, momentum, slots.
 struct ScalarArgs {
   SolveState* st;
   const double* pdfit; int n_dfit;
   const double* psum; const double* ptv; int n_obj;
   double* hist;   // [kHistCap]
+  int gx, gy;
 };
-hipError_t launch_scalars(const ScalarArgs& a, hipStream_t s);
+hipError_t launch_scalars(ScalarArgs a, hipStream_t s);
+hipError_t launch_scalars_batched(const ScalarArgs* args, BatchMap map, int nblocks, hipStream_t s);
+
+// Number of frames of a batch whose solve has stopped -> *out (one block).
+hipError_t launch_count_done(const SolveState* const* states, int n, int32_t* out, hipStream_t s);
 
 struct StateInit {
   double f_ref, gap_tol, l1, tv;
@@ -178,5 +220,14 @@ struct ProxArgs {
 };
 hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
 int prox_passes(int inner_iters, double tau);
+
+// Batched prox: the argument structs of every pass of every frame are built on
+// the host (prox_pass_args) and uploaded; launch p runs pass p of all frames.
+struct TvPassArgs;
+size_t tv_pass_args_size();
+// Fills `out` (npass structs, host memory of npass * tv_pass_args_size() bytes)
+// for one frame and returns the number of passes and the frame's blocks per pass.
+int prox_pass_args(const ProxArgs& a, void* out, int* blocks_per_pass);
+hipError_t launch_tv_pass_batched(const void* args, BatchMap map, int nblocks, hipStream_t s);
 
 }  // namespace rihvr

@@ -29,6 +29,7 @@
 // dual between two buffers.  The last pass adds a half step (primal recovery),
 // the soft threshold, the occupancy flags of the result and the store of x.
 #include <algorithm>
+#include <vector>
 
 #include "rihvr_internal.h"
 
@@ -52,6 +53,7 @@ struct TvPassArgs {
   int first, final_, nonneg;
   int zchunk;                     // output planes per block
   float tau, c, thr;
+  int gx, gy;                     // tiles along x and y (the grid of one frame)
 };
 
 __device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1 (0 at lane 0)
@@ -74,22 +76,23 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 }
 
 template <int H, bool EDGE, bool FIRST>
-__device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, float (*s_py)[2][kTvWaves][64],
-                                             float (*s_ut)[2][kTvWaves][64], float* s_v) {
+__device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int bz,
+                                             float (*s_py)[2][kTvWaves][64], float (*s_ut)[2][kTvWaves][64],
+                                             float* s_v) {
   constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
   const float* __restrict__ v = uniform_ptr(A.v ? A.v : A.vol[A.st->prev]);
   float* __restrict__ xo = uniform_ptr(A.x ? A.x : A.vol[A.st->next]);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x = blockIdx.x * IX - H + lane;
-  const int ybase = blockIdx.y * IY - H + wv * Q;
+  const int x = bx * IX - H + lane;
+  const int ybase = by * IY - H + wv * Q;
   const bool inx = !EDGE || (x >= 0 && x < nx);
   const bool xlo = !EDGE || x > 0, xhi = !EDGE || x + 1 < nx;
   const bool ix_store = inx && lane >= H && lane < kTvRX - H;
   const size_t sz = (size_t)nx * ny;
   const int L = A.levels;
-  const int zb = blockIdx.z * A.zchunk, ze = min(nz, zb + A.zchunk);
+  const int zb = bz * A.zchunk, ze = min(nz, zb + A.zchunk);
   const int M = L + 1;
   const int zs = max(0, zb - M), zl = min(nz, ze + M);
   const float tau = A.tau, cc = A.c;
@@ -294,22 +297,42 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, float (*s_py)[
 }
 
 template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
+__device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int by, int bz) {
   __shared__ float s_py[H + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step, parity
   __shared__ float s_ut[H][2][kTvWaves][64];      // top-row u per wave, per step, parity
   __shared__ float s_v[(H + 1) * kTvQ * kTvWaves * 64];  // v ring, thread-private
   if (A.st != nullptr && A.st->done) return;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;
-  const int x0 = blockIdx.x * IX - H, y0 = blockIdx.y * IY - H;
+  const int x0 = bx * IX - H, y0 = by * IY - H;
   // interior tile: every point of the region and its +-1 neighbours lie inside
   const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
   if (A.first) {
-    if (interior) tv_pass_body<H, false, true>(A, s_py, s_ut, s_v);
-    else tv_pass_body<H, true, true>(A, s_py, s_ut, s_v);
+    if (interior) tv_pass_body<H, false, true>(A, bx, by, bz, s_py, s_ut, s_v);
+    else tv_pass_body<H, true, true>(A, bx, by, bz, s_py, s_ut, s_v);
   } else {
-    if (interior) tv_pass_body<H, false, false>(A, s_py, s_ut, s_v);
-    else tv_pass_body<H, true, false>(A, s_py, s_ut, s_v);
+    if (interior) tv_pass_body<H, false, false>(A, bx, by, bz, s_py, s_ut, s_v);
+    else tv_pass_body<H, true, false>(A, bx, by, bz, s_py, s_ut, s_v);
   }
+}
+
+template <int H>
+__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
+  tv_pass_entry<H>(A, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+template <int H>
+__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass_b(const TvPassArgs* __restrict__ args,
+                                                             BatchMap map) {
+  const uint32_t b = blockIdx.x;
+  int lo = 0, hi = map.n;  // largest f with offs[f] <= b
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (map.offs[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  const TvPassArgs A = args[lo];
+  const int lb = (int)(b - map.offs[lo]);
+  tv_pass_entry<H>(A, lb % A.gx, (lb / A.gx) % A.gy, lb / (A.gx * A.gy));
 }
 
 // Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut so that
@@ -332,7 +355,12 @@ int prox_passes(int inner_iters, double tau) {
   return (inner_iters + 1 + kTvH - 1) / kTvH;   // K dual steps + one primal half step
 }
 
-hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
+size_t tv_pass_args_size() { return sizeof(TvPassArgs); }
+
+// Argument structs of every pass of one prox application.  Dual steps per
+// pass: non-final passes take kTvH, the final pass the rest (at most kTvH - 1,
+// leaving room for the primal half step in its halo).
+int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   const double tau = pa.step * pa.tv;
   const double thr = pa.step * pa.l1;
   const bool use_tv = tau > 0.0 && pa.inner_iters > 0;
@@ -352,8 +380,10 @@ hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
   a.thr = (float)thr;
   dim3 grid;
   pass_grid(pa.nx, pa.ny, pa.nz, kTvH, &grid, &a.zchunk);
-  // dual steps per pass: non-final passes take kTvH, the final pass the rest
-  // (at most kTvH - 1, leaving room for the primal half step in its halo)
+  a.gx = grid.x;
+  a.gy = grid.y;
+  if (blocks_per_pass) *blocks_per_pass = grid.x * grid.y * grid.z;
+  TvPassArgs* o = static_cast<TvPassArgs*>(out);
   int done = 0;
   for (int p = 0; p < npass; ++p) {
     const bool fin = p == npass - 1;
@@ -367,10 +397,27 @@ hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
       a.pin[k] = src[k];
       a.pout[k] = dst[k];
     }
-    hipLaunchKernelGGL(k_tv_pass<kTvH>, grid, dim3(kTvWaves * 64), 0, s, a);
+    o[p] = a;
     done += lv;
   }
+  return npass;
+}
+
+hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
+  const double tau = pa.step * pa.tv;
+  const int K = (tau > 0.0 && pa.inner_iters > 0) ? pa.inner_iters : 0;
+  std::vector<TvPassArgs> args(prox_passes(K, tau));
+  int nb = 0;
+  const int npass = prox_pass_args(pa, args.data(), &nb);
+  const dim3 grid(args[0].gx, args[0].gy, (nb / (args[0].gx * args[0].gy)));
+  for (int p = 0; p < npass; ++p) hipLaunchKernelGGL(k_tv_pass<kTvH>, grid, dim3(kTvWaves * 64), 0, s, args[p]);
   if (launches) *launches = npass;
+  return hipGetLastError();
+}
+
+hipError_t launch_tv_pass_batched(const void* args, BatchMap map, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_tv_pass_b<kTvH>, dim3(nblocks), dim3(kTvWaves * 64), 0, s,
+                     static_cast<const TvPassArgs*>(args), map);
   return hipGetLastError();
 }
 

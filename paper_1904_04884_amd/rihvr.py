@@ -43,6 +43,7 @@ PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size",
     "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
+    "ri_workspace_size_batched",
     "ri_status_string", "ri_last_error",
 )
 
@@ -108,6 +109,8 @@ def lib():
     L.ri_solve.argtypes = [vp, C.POINTER(ri_solve_params), vp, vp, vp, sz, vp, C.POINTER(ri_solve_report)]
     L.ri_solve_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(ri_solve_params), C.POINTER(vp),
                                    C.POINTER(vp), vp, sz, vp, C.POINTER(ri_solve_report)]
+    L.ri_workspace_size_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(ri_solve_params),
+                                            C.POINTER(sz)]
     L.ri_status_string.argtypes = [C.c_int]
     L.ri_status_string.restype = C.c_char_p
     L.ri_last_error.argtypes = []
@@ -173,6 +176,14 @@ def ri_solve_batched(n, plans, params, b, x_inout, ws, ws_bytes, stream, reports
     B = (C.c_void_p * n)(*b)
     X = (C.c_void_p * n)(*x_inout)
     return lib().ri_solve_batched(n, P, Q, B, X, ws, ws_bytes, stream, reports)
+
+
+def ri_workspace_size_batched(n, plans, params) -> int:
+    P = (C.c_void_p * n)(*plans)
+    Q = (ri_solve_params * n)(*params)
+    v = C.c_size_t()
+    _check(lib().ri_workspace_size_batched(n, P, Q, C.byref(v)), "ri_workspace_size_batched")
+    return v.value
 
 
 def ri_status_string(status: int) -> str:

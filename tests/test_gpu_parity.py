@@ -288,25 +288,62 @@ def test_scale_covariance(torch_cuda, plans, c1_problem):
     assert rel_l2(to_host(x2), 4.0 * to_host(x1)) <= 1e-5
 
 
-def test_batched_matches_single(torch_cuda, plans):
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_matches_single(torch_cuda, plans, graph):
+    """Uneven frames (sizes 2^a and 3*2^a, shared and distinct transform sizes,
+    different plane counts and stop iterations) solved in one batch must equal
+    the per-frame solves exactly."""
     torch = torch_cuda
-    gs = [geom(64, 64, 8), geom(48, 96, 5), geom(128, 128, 12)]
+    gs = [geom(64, 64, 8), geom(48, 96, 5), geom(128, 128, 12), geom(64, 64, 3), geom(96, 96, 7)]
+    iters = [6, 4, 6, 9, 5]
     rng = np.random.default_rng(13)
     bs = [to_dev(torch, rng.standard_normal((g.ny, g.nx))) for g in gs]
     ps = [plans(g) for g in gs]
-    singles = [p.solve(b, 0.05, 0.02, 6, 4)[0] for p, b in zip(ps, bs)]
-    sizes = [(rihvr.ri_workspace_size(p.handle, rihvr.RI_OP_SOLVE) + 255) // 256 * 256 for p in ps]
-    ws = torch.empty(sum(sizes) + 256, dtype=torch.uint8, device="cuda")
+    singles = [p.solve(b, 0.05, 0.02, k, 4)[0].clone() for p, b, k in zip(ps, bs, iters)]
+    flags = 0 if graph else rihvr.RI_SOLVE_NO_GRAPH
+    params = [p.solve_params(0.05, 0.02, k, 4, flags=flags) for p, k in zip(ps, iters)]
+    handles = [p.handle for p in ps]
+    nbytes = rihvr.ri_workspace_size_batched(len(ps), handles, params)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     xs = [torch.empty(p.shape, dtype=torch.float32, device="cuda") for p in ps]
-    params = [p.solve_params(0.05, 0.02, 6, 4) for p in ps]
     reps = (rihvr.ri_solve_report * len(ps))()
-    st = rihvr.ri_solve_batched(len(ps), [p.handle for p in ps], params, [b.data_ptr() for b in bs],
+    st = rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs],
+                                [x.data_ptr() for x in xs], ws.data_ptr(), ws.numel(),
+                                torch.cuda.current_stream().cuda_stream, reps)
+    assert st == rihvr.RI_OK, rihvr.ri_last_error()
+    for a, sgl in zip(xs, singles):
+        assert torch.equal(a, sgl)
+    assert [r.iters for r in reps] == iters
+    # too small a workspace is refused before anything runs
+    assert rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs],
+                                  [x.data_ptr() for x in xs], ws.data_ptr(), nbytes - 1,
+                                  torch.cuda.current_stream().cuda_stream, None) == rihvr.RI_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_batched_gap_stop_per_frame(torch_cuda, plans):
+    """Each frame stops at its own gap; finished frames do no further work."""
+    torch = torch_cuda
+    gs = [geom(64, 64, 6), geom(96, 48, 4)]
+    rng = np.random.default_rng(14)
+    bs = [to_dev(torch, rng.standard_normal((g.ny, g.nx))) for g in gs]
+    ps = [plans(g) for g in gs]
+    refs = [p.solve(b, 0.05, 0.02, 200, 4, flags=rihvr.RI_SOLVE_RESTART)[1]["objective_min"] for p, b in zip(ps, bs)]
+    params = [p.solve_params(0.05, 0.02, 200, 4, gap_tol=tol, f_ref=f, check_every=3)
+              for p, f, tol in zip(ps, refs, (1e-2, 1e-3))]
+    single = [p.solve(b, 0.05, 0.02, 200, 4, gap_tol=tol, f_ref=f, check_every=3)
+              for p, b, f, tol in zip(ps, bs, refs, (1e-2, 1e-3))]
+    handles = [p.handle for p in ps]
+    nbytes = rihvr.ri_workspace_size_batched(len(ps), handles, params)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    xs = [torch.empty(p.shape, dtype=torch.float32, device="cuda") for p in ps]
+    reps = (rihvr.ri_solve_report * len(ps))()
+    st = rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs],
                                 [x.data_ptr() for x in xs], ws.data_ptr(), ws.numel(),
                                 torch.cuda.current_stream().cuda_stream, reps)
     assert st == rihvr.RI_OK
-    for a, s in zip(xs, singles):
-        assert torch.equal(a, s)
-    assert all(r.iters == 6 for r in reps)
+    for r, (x1, rep1, _), x in zip(reps, single, xs):
+        assert r.converged == 1 and r.iters == rep1["iters"]
+        assert torch.equal(x, x1)
 
 
 # ---------------------------------------------------------------------------
