@@ -191,6 +191,47 @@ ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_para
                            const float* const* b, float* const* x_inout,
                            void* ws, size_t ws_bytes, void* stream, ri_solve_report* reports);
 
+/*
+ * Learned warm start: a 3D U-Net proposes x_0 for ri_solve (RI_INIT_GIVEN).
+ * The paper has no learned component; the network only changes where FISTA
+ * starts, and the solve's objective still decides the result.
+ *
+ * Architecture: `levels` resolution levels with base * 2^l channels; per
+ * level two 3x3x3 convolutions + ReLU, 2x2x2 max pooling down, 2x2x2 stride-2
+ * transposed convolutions up, skip concatenation [up, skip], a 1x1x1 head and
+ * a final ReLU (x_0 >= 0).  Activations and packed weights are BF16, matrix
+ * products accumulate in FP32 on the matrix cores; the parameters and the Adam
+ * moments are FP32 device arrays of ri_unet_param_count() floats, ordered
+ * layer by layer (encoder levels 0..L-1: conv a, conv b; decoder levels
+ * L-2..0: up, conv a, conv b; head), each layer weights then bias; conv
+ * weights [kz][ky][kx][cin][cout], up weights [dz][dy][dx][cin][cout], head [cin].
+ * Volumes are FP32 [d][h][w] device arrays; d, h, w must be multiples of
+ * 2^(levels-1).  The network input is scale * in (the back-propagated
+ * hologram A^T b, scaled by 1/||A||^2).  Workspaces come from the caller.
+ */
+typedef struct {
+  int32_t levels;   /* 1..6 */
+  int32_t base;     /* channels of level 0, a multiple of 8; base * 2^(levels-1) <= 128 */
+} ri_unet_config;
+
+ri_status ri_unet_param_count(const ri_unet_config* cfg, size_t* count);
+/* He-normal weights from a seeded generator, biases 0.01 (synchronous). */
+ri_status ri_unet_init_params(const ri_unet_config* cfg, uint64_t seed, float* params, void* stream);
+ri_status ri_unet_workspace_size(const ri_unet_config* cfg, int32_t d, int32_t h, int32_t w, int32_t training,
+                                 size_t* bytes);
+/* out = network(scale * in). */
+ri_status ri_unet_forward(const ri_unet_config* cfg, const float* params, const float* in, float scale, float* out,
+                          int32_t d, int32_t h, int32_t w, void* ws, size_t ws_bytes, void* stream);
+/*
+ * One training step on one volume: forward, mean-squared-error loss against
+ * `target` (written to *loss_out, a device float, if non-NULL), backward into
+ * `grads`, then, if lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8, bias
+ * correction with `step` >= 1) of params, adam_m, adam_v.
+ */
+ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params, float* grads, float* adam_m, float* adam_v,
+                             int32_t step, float lr, const float* in, float scale, const float* target, int32_t d,
+                             int32_t h, int32_t w, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+
 const char* ri_status_string(ri_status status);
 const char* ri_last_error(void);
 

@@ -9,5 +9,7 @@ Modules:
   prox    - 3D TV, gradient-projection TV prox, soft threshold, fused-lasso prox
   fista   - objective and the FISTA iteration
   detect  - threshold / connected components / weighted centroids / matching
+  unet    - warm-start 3D U-Net forward and analytic backward
 """
 from . import optics, prox, fista, detect  # noqa: F401
+from . import unet  # noqa: F401,E402

@@ -50,6 +50,10 @@ extern "C" const char* ri_status_string(ri_status s) {
 
 extern "C" const char* ri_last_error(void) { return g_last_error; }
 
+namespace rihvr {
+ri_status set_error(ri_status st, const char* msg) { return fail(st, "%s", msg); }
+}  // namespace rihvr
+
 // ---------------------------------------------------------------------------
 // Plan
 // ---------------------------------------------------------------------------

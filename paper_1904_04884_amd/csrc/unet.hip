@@ -1,0 +1,449 @@
+// Warm-start 3D U-Net kernels for gfx950: BF16 activations and weights, FP32
+// accumulation on the matrix cores (v_mfma_f32_16x16x32_bf16).
+//
+// Activations are channels-last, [z][y][x][c] with a channel stride (so a
+// concatenation is two views of one buffer).  Every convolution-like layer is
+// one "gather GEMM": row r is an output voxel, the reduction index k = t*C + c
+// runs over taps t and input channels c, and the operand row of tap t is read
+// from a source voxel chosen by the layer's gather mode.  Weights are packed as
+// B[t][n][c] (n the GEMM column, c contiguous) so each lane loads 8 consecutive
+// reduction values with one 16-byte load.
+//
+// MFMA 16x16x32 operand layout (per wavefront of 64 lanes, lane l):
+//   A (16 x 32): row l % 16, reduction elements 8 (l / 16) .. 8 (l / 16) + 7
+//   B (32 x 16): column l % 16, reduction elements 8 (l / 16) .. + 7
+//   D (16 x 16): rows 4 (l / 16) .. 4 (l / 16) + 3, column l % 16
+#include "unet_internal.h"
+
+namespace rihvr {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ float bf2f(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  // round to nearest even (finite inputs)
+  uint32_t u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// tap t of a 3x3x3 stencil -> (dz, dy, dx) in {-1, 0, 1}
+__device__ __forceinline__ void tap3(int t, int& dz, int& dy, int& dx) {
+  dz = t / 9 - 1;
+  dy = (t / 3) % 3 - 1;
+  dx = t % 3 - 1;
+}
+
+// Source voxel (linear index at the source resolution) of row r for tap t, or -1.
+__device__ __forceinline__ long gg_source(const GatherGemmArgs& a, long r, int t) {
+  const int D = a.D, H = a.H, W = a.W;  // row grid
+  const int x = (int)(r % W), y = (int)((r / W) % H), z = (int)(r / ((long)W * H));
+  switch (a.mode) {
+    case GG_CONV3_FWD:
+    case GG_CONV3_BWD: {
+      int dz, dy, dx;
+      tap3(t, dz, dy, dx);
+      if (a.mode == GG_CONV3_BWD) { dz = -dz; dy = -dy; dx = -dx; }
+      const int zz = z + dz, yy = y + dy, xx = x + dx;
+      if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) return -1;
+      return ((long)zz * H + yy) * W + xx;
+    }
+    case GG_UP_FWD:
+    case GG_POINT:
+      return r;
+    case GG_UP_BWD: {
+      // row r is coarse voxel (z, y, x); tap t = dz*4 + dy*2 + dx selects the fine voxel
+      const int zz = 2 * z + (t >> 2), yy = 2 * y + ((t >> 1) & 1), xx = 2 * x + (t & 1);
+      return ((long)zz * (2 * H) + yy) * (2 * W) + xx;
+    }
+  }
+  return -1;
+}
+
+// Block: 4 wavefronts x 16 rows = 64 rows; every wavefront computes all NB
+// column tiles of its rows.
+template <int NB>
+__global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const long row0 = (long)blockIdx.x * 64 + wv * 16;
+  const long nrows = (long)a.D * a.H * a.W;
+  const long ra = row0 + (lane & 15);   // A row of this lane
+  const int kq = (lane >> 4) * 8;       // reduction offset of this lane within a 32-chunk
+  const int K = a.T * a.C;
+  f32x4 acc[NB];
+#pragma unroll
+  for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const uint16_t* __restrict__ src = a.src;
+  const uint16_t* __restrict__ wt = a.wt;
+  for (int k0 = 0; k0 < K; k0 += 32) {
+    const int k = k0 + kq;
+    bf16x8 av;
+    uint4 araw = make_uint4(0, 0, 0, 0);
+    int t = 0, c = 0;
+    const bool kin = k < K;
+    if (kin) {
+      t = k / a.C;
+      c = k - t * a.C;
+      if (ra < nrows) {
+        const long sv = gg_source(a, ra, t);
+        if (sv >= 0) araw = *reinterpret_cast<const uint4*>(src + sv * a.src_cs + a.src_c0 + c);
+      }
+    }
+    av = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      uint4 braw = make_uint4(0, 0, 0, 0);
+      if (kin) braw = *reinterpret_cast<const uint4*>(wt + ((size_t)t * a.Npad + j * 16 + (lane & 15)) * a.C + c);
+      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, braw), acc[j], 0, 0, 0);
+    }
+  }
+  // epilogue: rows 4 (lane / 16) + i, column 16 j + lane % 16
+#pragma unroll
+  for (int j = 0; j < NB; ++j) {
+    const int n = j * 16 + (lane & 15);
+    if (n >= a.N) continue;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const long r = row0 + (lane >> 4) * 4 + i;
+      if (r >= nrows) continue;
+      float v = acc[j][i];
+      long dvox = r;
+      int dch = n;
+      if (a.mode == GG_UP_FWD) {
+        // column n = d * Cout + co writes fine voxel 2 q + d, channel co
+        const int d = n / a.up_cout, co = n - d * a.up_cout;
+        const int x = (int)(r % a.W), y = (int)((r / a.W) % a.H), z = (int)(r / ((long)a.W * a.H));
+        dvox = ((long)(2 * z + (d >> 2)) * (2 * a.H) + 2 * y + ((d >> 1) & 1)) * (2 * a.W) + 2 * x + (d & 1);
+        dch = co;
+      }
+      if (a.bias) v += a.bias[dch];
+      if (a.relu) v = fmaxf(v, 0.f);
+      const size_t o = (size_t)dvox * a.dst_cs + a.dst_c0 + dch;
+      if (a.out_f32) {
+        float* d = reinterpret_cast<float*>(a.dst);
+        d[o] = a.accumulate ? d[o] + v : v;
+      } else {
+        uint16_t* d = reinterpret_cast<uint16_t*>(a.dst);
+        d[o] = f2bf(a.accumulate ? bf2f(d[o]) + v : v);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[t][c][n] += sum_r S(r, t)[c] * G(r, t)[n]  (FP32 atomics;
+// [t][c][n] is the [tap][cin][cout] layout of the master weights).
+// Block: one tap, a chunk of rows and a group of up to 16 (n, c) output tiles;
+// 32-row slabs of G and S are staged in LDS, tiles are spread over the 4
+// wavefronts.
+// ---------------------------------------------------------------------------
+constexpr int kWgRows = 32;
+constexpr int kWgMaxN = 128, kWgMaxC = 256;
+
+__global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
+  __shared__ uint16_t sg[kWgRows][kWgMaxN];
+  __shared__ uint16_t ss[kWgRows][kWgMaxC];
+  const int t = blockIdx.y;
+  const long nrows = (long)a.D * a.H * a.W;
+  const long r0 = (long)blockIdx.x * a.rows_per_block;
+  const long r1 = min(nrows, r0 + a.rows_per_block);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int tn = a.Npad / 16, tc = a.Cpad / 16, ntile = tn * tc;
+  constexpr int MAXT = 4;  // tiles per wavefront kept in registers (16 tiles per block)
+  const int tile0 = blockIdx.z * 16;
+  f32x4 acc[MAXT];
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) acc[i] = f32x4{0.f, 0.f, 0.f, 0.f};
+  GatherGemmArgs ga{};
+  ga.mode = a.mode;
+  ga.D = a.D; ga.H = a.H; ga.W = a.W;
+  for (long rb = r0; rb < r1; rb += kWgRows) {
+    __syncthreads();
+    // stage G rows (all n) and S rows (all c) of this slab
+    for (int e = threadIdx.x; e < kWgRows * a.Npad; e += 256) {
+      const int rr = e / a.Npad, n = e - rr * a.Npad;
+      const long r = rb + rr;
+      uint16_t gv = 0;
+      if (r < r1 && n < a.N) {
+        long gvox = r;
+        if (a.mode == GG_UP_FWD) {
+          // gradient rows live at the fine voxel of tap t
+          const int x = (int)(r % a.W), y = (int)((r / a.W) % a.H), z = (int)(r / ((long)a.W * a.H));
+          gvox = ((long)(2 * z + (t >> 2)) * (2 * a.H) + 2 * y + ((t >> 1) & 1)) * (2 * a.W) + 2 * x + (t & 1);
+        }
+        gv = a.g[(size_t)gvox * a.g_cs + a.g_c0 + n];
+      }
+      sg[rr][n] = gv;
+    }
+    for (int e = threadIdx.x; e < kWgRows * a.Cpad; e += 256) {
+      const int rr = e / a.Cpad, c = e - rr * a.Cpad;
+      const long r = rb + rr;
+      uint16_t sv = 0;
+      if (r < r1 && c < a.C) {
+        long svox = r;
+        if (a.mode == GG_CONV3_FWD) svox = gg_source(ga, r, t);
+        if (svox >= 0) sv = a.s[(size_t)svox * a.s_cs + a.s_c0 + c];
+      }
+      ss[rr][c] = sv;
+    }
+    __syncthreads();
+    // A (16 n x 32 r): lane row n = 16 tn_i + lane % 16, r = 8 (lane / 16) + 0..7
+    // B (32 r x 16 c): lane column c = 16 tc_i + lane % 16
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+      const int tile = tile0 + wv + 4 * i;
+      if (tile >= ntile) break;
+      const int ni = tile / tc, ci = tile - ni * tc;
+      uint16_t av[8], bv[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const int rr = (lane >> 4) * 8 + q;
+        av[q] = sg[rr][ni * 16 + (lane & 15)];
+        bv[q] = ss[rr][ci * 16 + (lane & 15)];
+      }
+      bf16x8 A, B;
+      __builtin_memcpy(&A, av, 16);
+      __builtin_memcpy(&B, bv, 16);
+      acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, B, acc[i], 0, 0, 0);
+    }
+  }
+  // D rows = n, columns = c
+#pragma unroll
+  for (int i = 0; i < MAXT; ++i) {
+    const int tile = tile0 + wv + 4 * i;
+    if (tile >= ntile) break;
+    const int ni = tile / tc, ci = tile - ni * tc;
+    const int c = ci * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = ni * 16 + (lane >> 4) * 4 + q;
+      if (n < a.N && c < a.C) atomicAdd(&a.dw[((size_t)t * a.C + c) * a.N + n], acc[i][q]);
+    }
+  }
+}
+
+// bias gradient: db[n] += sum_r g[r][n]
+__global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows,
+                                                   long rows_per_block, int up_fine, float* db) {
+  const long r0 = (long)blockIdx.x * rows_per_block, r1 = min(nrows, r0 + rows_per_block);
+  for (int n = threadIdx.x; n < N; n += 256) {
+    float s = 0.f;
+    for (long r = r0; r < r1; ++r) s += bf2f(g[(size_t)r * cs + c0 + n]);
+    atomicAdd(&db[n], s);
+  }
+  (void)up_fine;
+}
+
+// ---------------------------------------------------------------------------
+// Max pooling 2x2x2 (forward with argmax, backward accumulating)
+// ---------------------------------------------------------------------------
+__global__ void k_pool_fwd(const uint16_t* x, int xcs, int xc0, uint16_t* y, int ycs, uint8_t* idx, int C,
+                           int D, int H, int W) {  // D, H, W: coarse dims
+  const long n = (long)D * H * W * C;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const long q = e / C;
+    const int qx = (int)(q % W), qy = (int)((q / W) % H), qz = (int)(q / ((long)W * H));
+    float best = 0.f;
+    int bi = 0;
+    for (int d = 0; d < 8; ++d) {
+      const long f = ((long)(2 * qz + (d >> 2)) * (2 * H) + 2 * qy + ((d >> 1) & 1)) * (2 * W) + 2 * qx + (d & 1);
+      const float v = bf2f(x[(size_t)f * xcs + xc0 + c]);
+      if (d == 0 || v > best) { best = v; bi = d; }
+    }
+    y[(size_t)q * ycs + c] = f2bf(best);
+    idx[(size_t)q * C + c] = (uint8_t)bi;
+  }
+}
+
+__global__ void k_pool_bwd(const uint16_t* gy, int gycs, const uint8_t* idx, uint16_t* gx, int gxcs, int gxc0,
+                           int C, int D, int H, int W) {  // coarse dims; gx accumulates
+  const long n = (long)D * H * W * C;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const long q = e / C;
+    const int qx = (int)(q % W), qy = (int)((q / W) % H), qz = (int)(q / ((long)W * H));
+    const int d = idx[(size_t)q * C + c];
+    const long f = ((long)(2 * qz + (d >> 2)) * (2 * H) + 2 * qy + ((d >> 1) & 1)) * (2 * W) + 2 * qx + (d & 1);
+    const size_t o = (size_t)f * gxcs + gxc0 + c;
+    gx[o] = f2bf(bf2f(gx[o]) + bf2f(gy[(size_t)q * gycs + c]));
+  }
+}
+
+// g <- g * (y > 0) over a channel view
+__global__ void k_relu_mask(uint16_t* g, int gcs, int gc0, const uint16_t* y, int ycs, int yc0, int C, long nvox) {
+  const long n = nvox * C;
+  for (long e = (long)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (long)gridDim.x * blockDim.x) {
+    const int c = (int)(e % C);
+    const long v = e / C;
+    if (!(bf2f(y[(size_t)v * ycs + yc0 + c]) > 0.f)) g[(size_t)v * gcs + gc0 + c] = 0;
+  }
+}
+
+__global__ void k_fill_u16(uint16_t* p, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// input: x_bf16[v][0] = scale * in[v], channels 1..cs-1 zero
+__global__ void k_input(const float* in, float scale, uint16_t* x, int cs, long nvox) {
+  for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < nvox; v += (long)gridDim.x * blockDim.x) {
+    x[(size_t)v * cs] = f2bf(scale * in[v]);
+    for (int c = 1; c < cs; ++c) x[(size_t)v * cs + c] = 0;
+  }
+}
+
+// MSE loss of y (FP32) against t; gradient 2 (y - t) / n * (y > 0) into g[v][0]
+__global__ void k_mse(const float* y, const float* t, long n, float inv_n, uint16_t* g, int gcs, float* loss) {
+  __shared__ float red[4];
+  float s = 0.f;
+  for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
+    const float d = y[v] - t[v];
+    s += d * d;
+    g[(size_t)v * gcs] = f2bf(y[v] > 0.f ? 2.f * d * inv_n : 0.f);
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) * inv_n);
+}
+
+// Adam on FP32 master weights
+__global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// Pack FP32 master weights W[t][cin][cout] into BF16 B[t][n][c] for one use:
+// transpose = 1: n = cout, c = cin (forward); 0: n = cin, c = cout (input
+// gradient).  Channels beyond the real counts are zero.
+__global__ void k_pack(const float* w, int T, int cin, int cout, int transpose, int Npad, int Cpad, uint16_t* out) {
+  const size_t n = (size_t)T * Npad * Cpad;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % Cpad);
+    const int nn = (int)((e / Cpad) % Npad);
+    const int t = (int)(e / ((size_t)Cpad * Npad));
+    float v = 0.f;
+    if (transpose) {
+      if (nn < cout && c < cin) v = w[((size_t)t * cin + c) * cout + nn];
+    } else {
+      if (nn < cin && c < cout) v = w[((size_t)t * cin + nn) * cout + c];
+    }
+    out[e] = f2bf(v);
+  }
+}
+
+// Up-convolution forward packing: B[0][n = d*cout + co][c = ci] = U[d][ci][co].
+__global__ void k_pack_up_fwd(const float* u, int cin, int cout, uint16_t* out) {
+  const size_t n = (size_t)8 * cout * cin;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int ci = (int)(e % cin);
+    const int col = (int)(e / cin);
+    const int d = col / cout, co = col - d * cout;
+    out[e] = f2bf(u[((size_t)d * cin + ci) * cout + co]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int ew_grid(size_t n) {
+  size_t b = (n + 255) / 256;
+  return (int)(b > 16384 ? 16384 : (b == 0 ? 1 : b));
+}
+
+hipError_t launch_gather_gemm(const GatherGemmArgs& a, hipStream_t s) {
+  const long nrows = (long)a.D * a.H * a.W;
+  const dim3 g((unsigned)((nrows + 63) / 64));
+  switch (a.Npad / 16) {
+    case 1: hipLaunchKernelGGL(k_gather_gemm<1>, g, dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL(k_gather_gemm<2>, g, dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(k_gather_gemm<4>, g, dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(k_gather_gemm<8>, g, dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL(k_gather_gemm<16>, g, dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL(k_gather_gemm<32>, g, dim3(256), 0, s, a); break;
+    case 64: hipLaunchKernelGGL(k_gather_gemm<64>, g, dim3(256), 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_wgrad(const WgradArgs& a, int taps, hipStream_t s) {
+  if (a.Npad > kWgMaxN || a.Cpad > kWgMaxC || a.Npad % 16 || a.Cpad % 16) return hipErrorInvalidValue;
+  const long nrows = (long)a.D * a.H * a.W;
+  const int nb = (int)((nrows + a.rows_per_block - 1) / a.rows_per_block);
+  const int groups = ((a.Npad / 16) * (a.Cpad / 16) + 15) / 16;
+  hipLaunchKernelGGL(k_wgrad, dim3(nb, taps, groups), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows, float* db, hipStream_t s) {
+  const long per = 4096;
+  const int nb = (int)((nrows + per - 1) / per);
+  hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, s, g, cs, c0, N, nrows, per, 0, db);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_fwd(const uint16_t* x, int xcs, int xc0, uint16_t* y, int ycs, uint8_t* idx, int C, int D,
+                           int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_fwd, dim3(ew_grid((size_t)D * H * W * C)), dim3(256), 0, s, x, xcs, xc0, y, ycs, idx, C,
+                     D, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_pool_bwd(const uint16_t* gy, int gycs, const uint8_t* idx, uint16_t* gx, int gxcs, int gxc0, int C,
+                           int D, int H, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_pool_bwd, dim3(ew_grid((size_t)D * H * W * C)), dim3(256), 0, s, gy, gycs, idx, gx, gxcs,
+                     gxc0, C, D, H, W);
+  return hipGetLastError();
+}
+
+hipError_t launch_relu_mask(uint16_t* g, int gcs, int gc0, const uint16_t* y, int ycs, int yc0, int C, long nvox,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_relu_mask, dim3(ew_grid((size_t)nvox * C)), dim3(256), 0, s, g, gcs, gc0, y, ycs, yc0, C,
+                     nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u16(uint16_t* p, size_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_u16, dim3(ew_grid(n)), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long nvox, hipStream_t s) {
+  hipLaunchKernelGGL(k_input, dim3(ew_grid(nvox)), dim3(256), 0, s, in, scale, x, cs, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_mse(const float* y, const float* t, long n, uint16_t* g, int gcs, float* loss, hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(ew_grid(n)), dim3(256), 0, s, y, t, n, 1.f / (float)n, g, gcs, loss);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
+                       int step, hipStream_t s) {
+  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(ew_grid(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(const float* w, int T, int cin, int cout, int transpose, int Npad, int Cpad, uint16_t* out,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(k_pack, dim3(ew_grid((size_t)T * Npad * Cpad)), dim3(256), 0, s, w, T, cin, cout, transpose,
+                     Npad, Cpad, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_up_fwd(const float* u, int cin, int cout, uint16_t* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_up_fwd, dim3(ew_grid((size_t)8 * cin * cout)), dim3(256), 0, s, u, cin, cout, out);
+  return hipGetLastError();
+}
+
+}  // namespace rihvr

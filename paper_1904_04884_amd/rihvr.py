@@ -44,6 +44,8 @@ EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size",
     "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
+    "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
+    "ri_unet_train_step",
     "ri_status_string", "ri_last_error",
 )
 
@@ -81,6 +83,10 @@ class ri_solve_report(C.Structure):
         }
 
 
+class ri_unet_config(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("base", C.c_int32)]
+
+
 class RihvrError(RuntimeError):
     def __init__(self, status: int, where: str, detail: str):
         super().__init__(f"{where}: status {status} ({detail})")
@@ -111,6 +117,13 @@ def lib():
                                    C.POINTER(vp), vp, sz, vp, C.POINTER(ri_solve_report)]
     L.ri_workspace_size_batched.argtypes = [C.c_int32, C.POINTER(vp), C.POINTER(ri_solve_params),
                                             C.POINTER(sz)]
+    cfgp, fp = C.POINTER(ri_unet_config), C.c_float
+    L.ri_unet_param_count.argtypes = [cfgp, C.POINTER(sz)]
+    L.ri_unet_init_params.argtypes = [cfgp, C.c_uint64, vp, vp]
+    L.ri_unet_workspace_size.argtypes = [cfgp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(sz)]
+    L.ri_unet_forward.argtypes = [cfgp, vp, vp, fp, vp, C.c_int32, C.c_int32, C.c_int32, vp, sz, vp]
+    L.ri_unet_train_step.argtypes = [cfgp, vp, vp, vp, vp, C.c_int32, fp, vp, fp, vp, C.c_int32, C.c_int32,
+                                     C.c_int32, vp, vp, sz, vp]
     L.ri_status_string.argtypes = [C.c_int]
     L.ri_status_string.restype = C.c_char_p
     L.ri_last_error.argtypes = []
@@ -184,6 +197,32 @@ def ri_workspace_size_batched(n, plans, params) -> int:
     v = C.c_size_t()
     _check(lib().ri_workspace_size_batched(n, P, Q, C.byref(v)), "ri_workspace_size_batched")
     return v.value
+
+
+def ri_unet_param_count(cfg: ri_unet_config) -> int:
+    v = C.c_size_t()
+    _check(lib().ri_unet_param_count(C.byref(cfg), C.byref(v)), "ri_unet_param_count")
+    return v.value
+
+
+def ri_unet_init_params(cfg, seed, params, stream) -> int:
+    return lib().ri_unet_init_params(C.byref(cfg), seed, params, stream)
+
+
+def ri_unet_workspace_size(cfg, d, h, w, training) -> int:
+    v = C.c_size_t()
+    _check(lib().ri_unet_workspace_size(C.byref(cfg), d, h, w, training, C.byref(v)), "ri_unet_workspace_size")
+    return v.value
+
+
+def ri_unet_forward(cfg, params, inp, scale, out, d, h, w, ws, ws_bytes, stream) -> int:
+    return lib().ri_unet_forward(C.byref(cfg), params, inp, scale, out, d, h, w, ws, ws_bytes, stream)
+
+
+def ri_unet_train_step(cfg, params, grads, m, v, step, lr, inp, scale, target, d, h, w, loss, ws, ws_bytes,
+                       stream) -> int:
+    return lib().ri_unet_train_step(C.byref(cfg), params, grads, m, v, step, lr, inp, scale, target, d, h, w,
+                                    loss, ws, ws_bytes, stream)
 
 
 def ri_status_string(status: int) -> str:
@@ -305,3 +344,49 @@ class Plan:
 
 def objective_gap(f, f_ref):
     return (f - f_ref) / f_ref if f_ref > 0 else math.nan
+
+
+class UNet:
+    """Warm-start network with FP32 parameters and Adam moments in torch tensors."""
+
+    def __init__(self, levels=4, base=16, seed=0):
+        import torch
+        self.torch = torch
+        self.cfg = ri_unet_config(int(levels), int(base))
+        self.n = ri_unet_param_count(self.cfg)
+        self.params = torch.empty(self.n, dtype=torch.float32, device="cuda")
+        self.grads = torch.zeros_like(self.params)
+        self.m = torch.zeros_like(self.params)
+        self.v = torch.zeros_like(self.params)
+        self.step = 0
+        self._ws = None
+        _check(ri_unet_init_params(self.cfg, int(seed), self.params.data_ptr(), _stream_handle(torch)),
+               "ri_unet_init_params")
+
+    def _workspace(self, d, h, w, training):
+        n = ri_unet_workspace_size(self.cfg, d, h, w, 1 if training else 0)
+        if self._ws is None or self._ws.numel() < n:
+            self._ws = self.torch.empty(n, dtype=self.torch.uint8, device="cuda")
+        return self._ws
+
+    def forward(self, inp, scale=1.0, out=None):
+        torch = self.torch
+        d, h, w = inp.shape
+        out = torch.empty_like(inp) if out is None else out
+        ws = self._workspace(d, h, w, False)
+        _check(ri_unet_forward(self.cfg, self.params.data_ptr(), inp.data_ptr(), float(scale), out.data_ptr(),
+                               d, h, w, ws.data_ptr(), ws.numel(), _stream_handle(torch)), "ri_unet_forward")
+        return out
+
+    def train_step(self, inp, target, lr=1e-3, scale=1.0):
+        torch = self.torch
+        d, h, w = inp.shape
+        ws = self._workspace(d, h, w, True)
+        loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+        if lr > 0:
+            self.step += 1
+        _check(ri_unet_train_step(self.cfg, self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
+                                  self.v.data_ptr(), max(self.step, 1), float(lr), inp.data_ptr(), float(scale),
+                                  target.data_ptr(), d, h, w, loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(torch)), "ri_unet_train_step")
+        return loss

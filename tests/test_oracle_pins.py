@@ -356,3 +356,62 @@ def test_p15_recovery_c1():
     within = [e for e in errs if abs(e[0]) <= 1 and abs(e[1]) <= 1 and abs(e[2]) <= 1]
     ep = len(within) / len(sc.centers)
     assert ep >= 0.75, (ep, len(found))
+
+
+# --- U-Net oracle: layers against brute force, network gradient by finite differences ---
+def test_unet_layers_brute_force():
+    from oracle import unet as ou
+    rng = np.random.default_rng(20)
+    x = rng.standard_normal((3, 4, 2, 2))
+    w = rng.standard_normal((3, 3, 3, 2, 3))
+    b = rng.standard_normal(3)
+    y = ou.conv3(x, w, b)
+    yb = np.zeros((3, 4, 2, 3))
+    for z, yy, xx, co in itertools.product(range(3), range(4), range(2), range(3)):
+        s = b[co]
+        for kz, ky, kx, ci in itertools.product(range(3), range(3), range(3), range(2)):
+            zz, y2, x2 = z + kz - 1, yy + ky - 1, xx + kx - 1
+            if 0 <= zz < 3 and 0 <= y2 < 4 and 0 <= x2 < 2:
+                s += w[kz, ky, kx, ci, co] * x[zz, y2, x2, ci]
+        yb[z, yy, xx, co] = s
+    assert np.max(np.abs(y - yb)) <= 1e-12
+    x2 = rng.standard_normal((4, 2, 2, 3))
+    p, idx = ou.maxpool2(x2)
+    for z, yy, xx, c in itertools.product(range(2), range(1), range(1), range(3)):
+        blk = x2[2 * z:2 * z + 2, 2 * yy:2 * yy + 2, 2 * xx:2 * xx + 2, c]
+        assert p[z, yy, xx, c] == blk.max()
+        d = idx[z, yy, xx, c]
+        assert blk[d >> 2, (d >> 1) & 1, d & 1] == blk.max()
+    u = rng.standard_normal((2, 2, 2, 3, 2))
+    bu = rng.standard_normal(2)
+    up = ou.upconv2(p, u, bu)
+    for z, yy, xx, co in itertools.product(range(4), range(2), range(2), range(2)):
+        q = p[z // 2, yy // 2, xx // 2]
+        assert up[z, yy, xx, co] == pytest.approx(q @ u[z % 2, yy % 2, xx % 2, :, co] + bu[co], abs=1e-12)
+
+
+@pytest.mark.parametrize("levels", [2, 3])
+def test_unet_gradients_finite_differences(levels):
+    from oracle import unet as ou
+    rng = np.random.default_rng(21 + levels)
+    base = 4
+    p = ou.init_params(levels, base, rng)
+    x = rng.standard_normal((8, 8, 8))
+    t = np.maximum(rng.standard_normal((8, 8, 8)), 0.0)
+    _, g = ou.loss_and_grads(p, x, t, levels, base)
+    worst = 0.0
+    for k in p:
+        flatp = p[k].reshape(-1)
+        for i in rng.choice(flatp.size, size=min(2, flatp.size), replace=False):
+            old = flatp[i]
+            e = 1e-6
+            flatp[i] = old + e
+            lp = ou.loss_and_grads(p, x, t, levels, base)[0]
+            flatp[i] = old - e
+            lm = ou.loss_and_grads(p, x, t, levels, base)[0]
+            flatp[i] = old
+            fd = (lp - lm) / (2 * e)
+            an = g[k].reshape(-1)[i]
+            # central differences with e = 1e-6 carry ~1e-10 of cancellation error
+            worst = max(worst, abs(fd - an) / (1e-8 + 1e-5 * abs(an)))
+    assert worst <= 1.0, worst
