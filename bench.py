@@ -99,6 +99,140 @@ def cpu_baseline(scenes, iters_to_gap, nvox_full, cfg):
     }
 
 
+def burgers_frames(scenes, n_frames, seed=0):
+    """Uneven frames of a particle time series in a Burgers vortex (768^2 field,
+    up to 200 planes, 1500 particles): frame t is a centred crop of size 256,
+    512 or 768 with a plane count in [64, 200]."""
+    rng = np.random.default_rng(seed)
+    field, nz_max, npart = 768, 200, 1500
+    traj = scenes.burgers_series(n_frames, field, nz_max, npart, rng)
+    diam = rng.uniform(2.0, 6.0, npart)
+    frames = []
+    base = scenes.geometry_c2()
+    for t in range(n_frames):
+        size = int(rng.choice([256, 512, 768]))
+        nz = int(rng.integers(64, 201))
+        off = (field - size) // 2
+        g = base.with_(nx=size, ny=size, nz=nz)
+        c = traj[t].copy()
+        c[:, 1] -= off
+        c[:, 2] -= off
+        keep = (c[:, 0] < nz - 0.5) & (c[:, 1] >= 4) & (c[:, 1] < size - 4) & (c[:, 2] >= 4) & (c[:, 2] < size - 4)
+        idx, val, _, _ = scenes.disk_particles(g, int(keep.sum()), rng, centers=c[keep], diam=diam[keep])
+        noise = scenes.noise_field(g, 0.02, rng)
+        frames.append((g, idx, val, noise))
+    return frames
+
+
+def run_batched(args, torch, rihvr, scenes):
+    """Batched solve of uneven frames against the same frames solved one by one."""
+    cfg = scenes.config_c2()
+    frames = burgers_frames(scenes, args.batched, seed=args.seed)
+    plans, bs, xs = [], [], []
+    for g, idx, val, noise in frames:
+        p = rihvr.Plan(g)
+        lin = np.ravel_multi_index((idx[:, 0], idx[:, 1], idx[:, 2]), g.shape)
+        xt = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+        xt.view(-1)[torch.from_numpy(lin).cuda()] = torch.from_numpy(val.astype(np.float32)).cuda()
+        b = p.forward(xt) + torch.from_numpy(noise.astype(np.float32)).cuda()
+        del xt
+        plans.append(p)
+        bs.append(b.contiguous())
+        xs.append(torch.empty(g.shape, dtype=torch.float32, device="cuda"))
+    nvox = sum(g.nx * g.ny * g.nz for g, _, _, _ in frames)
+    iters = args.batch_iters
+    log(f"batched: {len(frames)} frames, {nvox / 1e9:.2f} G voxels, {iters} iterations each")
+    params = [p.solve_params(cfg.l1, cfg.tv, iters, cfg.inner_iters) for p in plans]
+    handles = [p.handle for p in plans]
+    nbytes = rihvr.ri_workspace_size_batched(len(plans), handles, params)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+
+    def batched():
+        st = rihvr.ri_solve_batched(len(plans), handles, params, [b.data_ptr() for b in bs],
+                                    [x.data_ptr() for x in xs], ws.data_ptr(), ws.numel(), stream, None)
+        assert st == rihvr.RI_OK, rihvr.ri_last_error()
+
+    batched()  # warm-up (graph capture, caches)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    batched()
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    del ws
+    # the same frames one at a time (each with its own graph)
+    for p, b in zip(plans, bs):
+        p.solve(b, cfg.l1, cfg.tv, iters, cfg.inner_iters, report=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for p, b in zip(plans, bs):
+        p.solve(b, cfg.l1, cfg.tv, iters, cfg.inner_iters, report=False)
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    return {
+        "metric": "holograms/s, batched uneven frames (Burgers-vortex series)",
+        "frames": len(frames), "iterations": iters, "voxels": nvox,
+        "batched_holograms_per_s": len(frames) / tb, "per_frame_holograms_per_s": len(frames) / ts,
+        "speedup": ts / tb, "batched_voxel_iters_per_s": nvox * iters / tb,
+        "sizes": [[g.nx, g.nz] for g, _, _, _ in frames],
+    }
+
+
+def run_warmstart(args, torch, rihvr, scenes):
+    """Iterations to gap 1e-4, cold vs learned warm start, on held-out scenes."""
+    from paper_1904_04884_amd import warmstart
+    cfg = scenes.config_c2()
+    g = scenes.geometry_c2().with_(nx=args.ws_size, ny=args.ws_size, nz=args.ws_planes)
+    plan = rihvr.Plan(g)
+    ws = warmstart.WarmStart(plan, levels=4, base=16, seed=0)
+
+    def holo(seed):
+        n = int(np.random.default_rng(seed).integers(500, 3001) * (g.nx * g.ny * g.nz) / (512 * 512 * 128))
+        sc = scenes.scene_c2(seed=seed, geom=g, n_particles=max(n, 10))
+        lin = np.ravel_multi_index((sc.idx[:, 0], sc.idx[:, 1], sc.idx[:, 2]), g.shape)
+        xt = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+        xt.view(-1)[torch.from_numpy(lin).cuda()] = torch.from_numpy(sc.val.astype(np.float32)).cuda()
+        return (plan.forward(xt) + torch.from_numpy(sc.noise.astype(np.float32)).cuda()).contiguous()
+
+    t0 = time.perf_counter()
+    pairs = [ws.make_pair(holo(1000 + i), cfg.l1, cfg.tv, args.ws_pair_iters, cfg.inner_iters)[0]
+             for i in range(args.ws_pairs)]
+    t_pairs = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    curve = ws.train(pairs, steps=args.ws_steps, crop=(32, 64, 64), lr=1e-3, log_every=max(1, args.ws_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pairs
+    cold, warm, used, t_cold, t_warm = [], [], [], 0.0, 0.0
+    for i in range(args.ws_eval):
+        b = holo(9000 + i)
+        f_ref = plan.solve(b, cfg.l1, cfg.tv, 20 * 100, cfg.inner_iters,
+                           flags=rihvr.RI_SOLVE_RESTART)[1]["objective_min"]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rc, _ = plan.solve(b, cfg.l1, cfg.tv, 2000, cfg.inner_iters, f_ref=f_ref, gap_tol=1e-4, check_every=1)
+        torch.cuda.synchronize()
+        t_cold += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, rw, u = ws.solve(b, cfg.l1, cfg.tv, 2000, cfg.inner_iters, f_ref=f_ref, gap_tol=1e-4, check_every=1)
+        torch.cuda.synchronize()
+        t_warm += time.perf_counter() - t0
+        cold.append(rc["iters"])
+        warm.append(rw["iters"])
+        used.append(bool(u))
+        log(f"held-out {i}: cold {rc['iters']} warm {rw['iters']} (proposal used {u})")
+    plan.close()
+    return {
+        "metric": "iterations to objective gap 1e-4, cold vs learned warm start",
+        "geometry": [g.nx, g.ny, g.nz], "pairs": args.ws_pairs, "pair_iters": args.ws_pair_iters,
+        "train_steps": args.ws_steps, "loss_curve": curve, "t_pairs_s": t_pairs, "t_train_s": t_train,
+        "cold_iters": cold, "warm_iters": warm, "proposal_used": used,
+        "cold_holograms_per_s": len(cold) / t_cold, "warm_holograms_per_s": len(warm) / t_warm,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +245,15 @@ def main():
     ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--plain", action="store_true", help="also time plain per-frame FISTA (dense, no graph)")
+    ap.add_argument("--batched", type=int, default=0, help="run the batched uneven-frame mode with this many frames")
+    ap.add_argument("--batch-iters", type=int, default=30)
+    ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start evaluation mode")
+    ap.add_argument("--ws-size", type=int, default=256)
+    ap.add_argument("--ws-planes", type=int, default=64)
+    ap.add_argument("--ws-pairs", type=int, default=48)
+    ap.add_argument("--ws-pair-iters", type=int, default=300)
+    ap.add_argument("--ws-steps", type=int, default=1500)
+    ap.add_argument("--ws-eval", type=int, default=4)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -125,6 +268,12 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     rihvr.lib()
+    if args.batched:
+        print(json.dumps(run_batched(args, torch, rihvr, scenes)), flush=True)
+        return
+    if args.warmstart:
+        print(json.dumps(run_warmstart(args, torch, rihvr, scenes)), flush=True)
+        return
     cfg = scenes.config_c2()
     g = scenes.geometry_c2()
     nvox = g.nx * g.ny * g.nz

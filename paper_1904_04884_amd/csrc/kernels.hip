@@ -468,7 +468,8 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
       const float gy = has_y ? ((fy ? r0[i + nx] : 0.f) - v) : 0.f;
       const float gz = has_z ? ((fz ? r0[(size_t)ny * nx + i] : 0.f) - v) : 0.f;
       s_acc += (double)v;
-      t_acc += sqrt((double)gx * gx + (double)gy * gy + (double)gz * gz);
+      // per-voxel norm in FP32 (relative error ~1e-7), sums in FP64
+      t_acc += (double)sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
     }
   }
   s_acc = block_sum<kObjThreads>(s_acc, red[0]);
