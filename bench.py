@@ -129,8 +129,15 @@ def run_batched(args, torch, rihvr, scenes):
     cfg = scenes.config_c2()
     frames = burgers_frames(scenes, args.batched, seed=args.seed)
     plans, bs, xs = [], [], []
+    import tempfile
+    cache = os.path.join(tempfile.mkdtemp(prefix="rihvr_tune_"), "tune.jsonl")
+    t_tune, n_timed = 0.0, 0
     for g, idx, val, noise in frames:
         p = rihvr.Plan(g)
+        if not args.no_autotune:
+            r = p.autotune(cfg.inner_iters, cache)   # one timing per distinct shape, cached after
+            t_tune += r["tune_ms"] / 1e3
+            n_timed += 0 if r["from_cache"] else 1
         lin = np.ravel_multi_index((idx[:, 0], idx[:, 1], idx[:, 2]), g.shape)
         xt = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
         xt.view(-1)[torch.from_numpy(lin).cuda()] = torch.from_numpy(val.astype(np.float32)).cuda()
@@ -141,7 +148,8 @@ def run_batched(args, torch, rihvr, scenes):
         xs.append(torch.empty(g.shape, dtype=torch.float32, device="cuda"))
     nvox = sum(g.nx * g.ny * g.nz for g, _, _, _ in frames)
     iters = args.batch_iters
-    log(f"batched: {len(frames)} frames, {nvox / 1e9:.2f} G voxels, {iters} iterations each")
+    log(f"batched: {len(frames)} frames, {nvox / 1e9:.2f} G voxels, {iters} iterations each; "
+        f"autotune {t_tune:.1f} s ({n_timed} shapes timed)")
     params = [p.solve_params(cfg.l1, cfg.tv, iters, cfg.inner_iters) for p in plans]
     handles = [p.handle for p in plans]
     nbytes = rihvr.ri_workspace_size_batched(len(plans), handles, params)
@@ -176,6 +184,7 @@ def run_batched(args, torch, rihvr, scenes):
         "frames": len(frames), "iterations": iters, "voxels": nvox,
         "batched_holograms_per_s": len(frames) / tb, "per_frame_holograms_per_s": len(frames) / ts,
         "speedup": ts / tb, "batched_voxel_iters_per_s": nvox * iters / tb,
+        "autotune_s": t_tune, "autotuned_shapes": n_timed,
         "sizes": [[g.nx, g.nz] for g, _, _, _ in frames],
     }
 
@@ -254,6 +263,9 @@ def main():
     ap.add_argument("--ws-pair-iters", type=int, default=300)
     ap.add_argument("--ws-steps", type=int, default=1500)
     ap.add_argument("--ws-eval", type=int, default=4)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--tuning", type=str, default=None,
+                    help="fixed launch shapes tv_levels,tv_blocks,col_blocks (no autotuning; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -280,6 +292,14 @@ def main():
     t0 = time.perf_counter()
     plan = rihvr.Plan(g)
     log(f"plan: ||A||^2 = {plan.lipschitz:.6f} ({time.perf_counter() - t0:.2f} s)")
+    tune = None
+    if args.tuning:
+        lv, tb, cb = (int(v) for v in args.tuning.split(","))
+        plan.tuning = {"tv_levels": lv, "tv_blocks": tb, "col_blocks": cb}
+    elif not args.no_autotune:
+        tune = plan.autotune(cfg.inner_iters)
+        log(f"autotune: {tune['best']} ({tune['candidates']} shapes, {tune['tune_ms'] / 1e3:.2f} s); "
+            f"A + A^T + prox {tune['default_ms']:.3f} -> {tune['best_ms']:.3f} ms")
     sc, x_true, b = build_scene(torch, rihvr, scenes, plan, args.seed)
     log(f"scene: {len(sc.centers)} particles, {len(sc.val)} voxels; |b| = {float(b.norm()):.4g}")
 
@@ -379,7 +399,9 @@ def main():
                         "2000 disk particles d~U[2,6] px, noise 0.02, l1 0.02, tv 0.01, K_in 20, cold start, "
                         "gap 1e-4 vs restarted reference",
             "nx": g.nx, "ny": g.ny, "nz": g.nz, "seed": args.seed,
+            "tuning": plan.tuning,
         },
+        "autotune": tune,
         "iters_to_gap": mean_iters,
         "converged": converged,
         "voxel_iters_per_s": nvox * mean_iters * value,

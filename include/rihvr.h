@@ -115,7 +115,25 @@ typedef struct {
 typedef struct ri_plan ri_plan;
 
 /* Workspace queries */
-typedef enum { RI_OP_FORWARD = 0, RI_OP_ADJOINT = 1, RI_OP_PROX = 2, RI_OP_SOLVE = 3 } ri_op;
+typedef enum { RI_OP_FORWARD = 0, RI_OP_ADJOINT = 1, RI_OP_PROX = 2, RI_OP_SOLVE = 3, RI_OP_AUTOTUNE = 4 } ri_op;
+
+/*
+ * Launch shape of a plan (no effect on what is computed; FP32 rounding of the
+ * forward's plane sums depends on col_blocks).  Defaults: 3, 1536, 512.
+ *   tv_levels   dual steps fused into one pass of the TV prox (2, 3 or 4): a
+ *               pass streams the volume once, so fewer passes read less, but
+ *               each pass recomputes a wider halo and uses more registers.
+ *   tv_blocks   blocks per TV pass the z-range is cut for (64 .. 65536;
+ *               chunks keep at least 16 planes).
+ *   col_blocks  blocks of the per-plane column transforms of A and A^T the
+ *               z-range is cut for (16 .. 8192).  More chunks mean more
+ *               partial spectra: ri_workspace_size grows with it.
+ */
+typedef struct {
+  int32_t tv_levels;
+  int32_t tv_blocks;
+  int32_t col_blocks;
+} ri_tuning;
 
 /*
  * Create a plan for one geometry on the current HIP device: FP64 phase table
@@ -128,8 +146,41 @@ ri_status ri_plan_create(const ri_geometry* geometry, ri_plan** out);
 ri_status ri_plan_destroy(ri_plan* plan);
 /* ||A||^2 of the plan (host value). */
 ri_status ri_plan_lipschitz(const ri_plan* plan, double* out);
-/* Bytes of scratch space that `op` needs with this plan. */
+/* Bytes of scratch space that `op` needs with this plan (and its current tuning). */
 ri_status ri_workspace_size(const ri_plan* plan, ri_op op, size_t* bytes);
+
+/*
+ * Tuning of a plan.  ri_plan_set_tuning validates every field (RI_ERR_INVALID_ARG
+ * otherwise, plan unchanged) and drops the plan's cached solve graph; the
+ * workspace sizes of RI_OP_FORWARD, RI_OP_ADJOINT and RI_OP_SOLVE may change.
+ */
+ri_status ri_plan_get_tuning(const ri_plan* plan, ri_tuning* out);
+ri_status ri_plan_set_tuning(ri_plan* plan, const ri_tuning* tuning);
+
+typedef struct {
+  ri_tuning best;           /* the tuning now set on the plan */
+  int32_t from_cache;       /* 1: taken from the cache file, nothing was timed */
+  int32_t cache_written;    /* 1: the cache file was updated; -1: writing it failed */
+  int32_t candidates;       /* launch shapes timed */
+  double default_ms;        /* forward + adjoint + prox of one iteration, default tuning */
+  double best_ms;           /* the same with the chosen tuning */
+  double tune_ms;           /* wall time of the call */
+} ri_autotune_report;
+
+/*
+ * Choose the plan's tuning by timing its kernels on the device: the column
+ * transforms of A and A^T for each distinct col_blocks chunking, and one TV
+ * prox of `inner_iters` dual steps for each distinct (tv_levels, tv_blocks)
+ * grid, on zero-filled data in the workspace (ri_workspace_size(RI_OP_AUTOTUNE)
+ * bytes, contents overwritten), then set the fastest.  The choice is keyed by
+ * device name, compute-unit count, nx, ny, nz and inner_iters; with a non-NULL
+ * `cache_path` (a text file of one JSON object per line) a matching entry is
+ * used without timing, and a new choice is added to the file (rewritten
+ * through a temporary file and a rename).  Synchronises `stream`.  `report`
+ * is nullable.
+ */
+ri_status ri_plan_autotune(ri_plan* plan, int32_t inner_iters, const char* cache_path, void* ws,
+                           size_t ws_bytes, void* stream, ri_autotune_report* report);
 
 /*
  * b_out = A x.  x: volume [nz][ny][nx]; b_out: hologram [ny][nx].
@@ -184,6 +235,8 @@ ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const float* b,
  * hold ri_workspace_size_batched() bytes.  params[i], b[i], x_inout[i] and
  * reports[i] (nullable array; filled after one synchronisation) belong to
  * frame i.  The x_inout volumes must not overlap each other, any b or ws.
+ * Each frame runs with its own plan's tuning (TV passes are grouped by
+ * tv_levels), so its result equals that of ri_solve with the same plan.
  */
 ri_status ri_workspace_size_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
                                     size_t* bytes);

@@ -3,11 +3,15 @@
 // replay, stop-flag polling, phase timing).
 #include <hip/hip_runtime.h>
 
+#include <unistd.h>
+
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <string>
 #include <vector>
 
 #include "rihvr_internal.h"
@@ -80,6 +84,7 @@ struct ri_plan {
   int32_t* host_flag = nullptr;  // pinned, for stop polling
   hipStream_t capture = nullptr;
   GraphCache gc;
+  ri_tuning tune{kTvDefaultLevels, kTvDefaultBlocks, kColDefaultBlocks};
   PlanTables tables() const { return PlanTables{theta, zc, tw_row, tw_col}; }
 };
 
@@ -98,6 +103,12 @@ static void free_plan(ri_plan* p) {
   if (p->tw_col) hipFree(p->tw_col);
   if (p->host_flag) hipHostFree(p->host_flag);
   delete p;
+}
+
+static void drop_graph(ri_plan* p) {
+  if (p->gc.exec) hipGraphExecDestroy(p->gc.exec);
+  if (p->gc.graph) hipGraphDestroy(p->gc.graph);
+  p->gc = GraphCache{};
 }
 
 static void twiddles(int n, std::vector<float2>& out) {
@@ -234,23 +245,31 @@ struct Layout {
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
-static void chunking(const ri_plan* p, int* nchunk, int* ppc) {
+// Candidate launch shapes of the autotuner (distinct grids only are timed).
+static const int kTvBlockCands[] = {768, 1536, 3072, 6144};
+static const int kColBlockCands[] = {128, 256, 512, 1024, 2048};
+static const int kColTuneMax = 2048;
+
+// Planes per chunk of the column transforms: the z-range is cut until the
+// column kernels hold about `col_blocks` blocks.
+static void chunking(const ri_plan* p, int col_blocks, int* nchunk, int* ppc) {
   const int W = col_tile_width(p->g.ny);
   const int tiles = (p->m + W - 1) / W;
-  int want = std::max(1, (512 + tiles - 1) / tiles);
+  int want = std::max(1, (col_blocks + tiles - 1) / tiles);
   want = std::min(want, p->g.nz);
   const int per = (p->g.nz + want - 1) / want;
   *ppc = per;
   *nchunk = (p->g.nz + per - 1) / per;
 }
 
-static Layout make_layout(const ri_plan* p, ri_op op) {
+static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
+  if (op == RI_OP_AUTOTUNE) return make_layout(p, RI_OP_SOLVE, kColTuneMax);  // room for every candidate
   Layout L;
   const size_t nx = p->g.nx, ny = p->g.ny, nz = p->g.nz, m = p->m;
   const size_t vol = nx * ny * nz * sizeof(float);
   const size_t spec = m * ny * nz * sizeof(float2);
   const size_t hspec = m * ny * sizeof(float2);
-  chunking(p, &L.nchunk, &L.ppc);
+  chunking(p, col_blocks > 0 ? col_blocks : p->tune.col_blocks, &L.nchunk, &L.ppc);
   size_t off = 256;  // slack so the base can be aligned up
   auto take = [&](size_t bytes) {
     size_t o = off;
@@ -291,7 +310,7 @@ static Layout make_layout(const ri_plan* p, ri_op op) {
 
 extern "C" ri_status ri_workspace_size(const ri_plan* p, ri_op op, size_t* bytes) {
   if (!p || !bytes) return fail(RI_ERR_INVALID_ARG, "NULL argument");
-  if (op < RI_OP_FORWARD || op > RI_OP_SOLVE) return fail(RI_ERR_INVALID_ARG, "unknown op %d", (int)op);
+  if (op < RI_OP_FORWARD || op > RI_OP_AUTOTUNE) return fail(RI_ERR_INVALID_ARG, "unknown op %d", (int)op);
   *bytes = make_layout(p, op).total;
   return RI_OK;
 }
@@ -377,15 +396,9 @@ extern "C" ri_status ri_forward(ri_plan* p, const float* x, float* b_out, void* 
   return RI_OK;
 }
 
-extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* ws, size_t ws_bytes, void* stream) {
-  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
-  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
-  ri_status st = check_common(p, y, x_out, ws, ws_bytes, RI_OP_ADJOINT, hb, vb);
-  if (st != RI_OK) return st;
-  if (overlaps(y, hb, x_out, vb)) return fail(RI_ERR_INVALID_ARG, "y and x_out overlap");
-  const Layout L = make_layout(p, RI_OP_ADJOINT);
+static hipError_t enqueue_adjoint(ri_plan* p, const Layout& L, void* ws, const float* y, float* x_out,
+                                  hipStream_t s) {
   const PlanTables pt = p->tables();
-  hipStream_t s = (hipStream_t)stream;
   const int ny = p->g.ny, nz = p->g.nz, m = p->m;
   RowsR2CArgs ra{};
   ra.x = y;
@@ -393,7 +406,8 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   ra.nrows = ny;
   ra.mode = 0;
   ra.pt = pt;
-  HIP_TRY(launch_rows_r2c(m, ra, s));
+  hipError_t e = launch_rows_r2c(m, ra, s);
+  if (e != hipSuccess) return e;
   AdjColsArgs aa{};
   aa.th = at<float2>(ws, L.th);
   aa.u = at<float2>(ws, L.spec);
@@ -401,7 +415,8 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   aa.nz = nz;
   aa.planes_per_chunk = L.ppc;
   aa.pt = pt;
-  HIP_TRY(launch_adj_cols(ny, L.nchunk, aa, s));
+  e = launch_adj_cols(ny, L.nchunk, aa, s);
+  if (e != hipSuccess) return e;
   AdjRowsArgs ar{};
   ar.u = at<float2>(ws, L.spec);
   ar.nrows = ny * nz;
@@ -410,7 +425,16 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   ar.mode = 0;
   ar.scale = (float)(1.0 / ((double)p->g.nx * ny));
   ar.pt = pt;
-  HIP_TRY(launch_adj_rows(m, ar, s));
+  return launch_adj_rows(m, ar, s);
+}
+
+extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* ws, size_t ws_bytes, void* stream) {
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
+  ri_status st = check_common(p, y, x_out, ws, ws_bytes, RI_OP_ADJOINT, hb, vb);
+  if (st != RI_OK) return st;
+  if (overlaps(y, hb, x_out, vb)) return fail(RI_ERR_INVALID_ARG, "y and x_out overlap");
+  HIP_TRY(enqueue_adjoint(p, make_layout(p, RI_OP_ADJOINT), ws, y, x_out, (hipStream_t)stream));
   return RI_OK;
 }
 
@@ -439,6 +463,8 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   a.step = step;
   a.l1 = pp->l1;
   a.tv = pp->tv;
+  a.levels = p->tune.tv_levels;
+  a.blocks = p->tune.tv_blocks;
   HIP_TRY(launch_prox(a, (hipStream_t)stream, nullptr));
   return RI_OK;
 }
@@ -616,6 +642,8 @@ static IterArgs iteration_args(const SolveCtx& c) {
   pa.l1 = c.l1;
   pa.tv = c.tv;
   pa.st = c.st;
+  pa.levels = p->tune.tv_levels;
+  pa.blocks = p->tune.tv_blocks;
   return I;
 }
 
@@ -855,7 +883,7 @@ static size_t kind_args_size(int kind) {
 }
 
 static int prox_pass_count(const ri_plan* p, const ri_solve_params& sp) {
-  return prox_passes(sp.inner_iters, (1.0 / p->lipschitz) * sp.tv);
+  return prox_passes(sp.inner_iters, (1.0 / p->lipschitz) * sp.tv, p->tune.tv_levels);
 }
 
 // The launches of one batched iteration (frames grouped by transform size).
@@ -888,16 +916,19 @@ static std::vector<BatchLaunch> batch_launches(int n, ri_plan* const* plans, con
   group(BK_RESID, true, false);
   group(BK_ADJ_COLS, false, true);
   group(BK_ADJ_ROWS, true, false);
+  // TV pass p of every frame that has one, one launch per fusion depth
   int maxpass = 0;
   for (int i = 0; i < n; ++i) maxpass = std::max(maxpass, prox_pass_count(plans[i], params[i]));
   for (int p = 0; p < maxpass; ++p) {
-    BatchLaunch b;
-    b.kind = BK_TV;
-    b.size = 0;
-    b.pass = p;
-    for (int i = 0; i < n; ++i)
-      if (p < prox_pass_count(plans[i], params[i])) b.frames.push_back(i);
-    out.push_back(b);
+    for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
+      BatchLaunch b;
+      b.kind = BK_TV;
+      b.size = H;
+      b.pass = p;
+      for (int i = 0; i < n; ++i)
+        if (plans[i]->tune.tv_levels == H && p < prox_pass_count(plans[i], params[i])) b.frames.push_back(i);
+      if (!b.frames.empty()) out.push_back(b);
+    }
   }
   return out;
 }
@@ -1073,7 +1104,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
         case BK_SCAL: e = launch_scalars_batched((const ScalarArgs*)a, mp, bl.nblocks, q); break;
         case BK_ADJ_COLS: e = launch_adj_cols_batched(bl.size, (const AdjColsArgs*)a, mp, bl.nblocks, q); break;
         case BK_ADJ_ROWS: e = launch_adj_rows_batched(bl.size, (const AdjRowsArgs*)a, mp, bl.nblocks, q); break;
-        case BK_TV: e = launch_tv_pass_batched(a, mp, bl.nblocks, q); break;
+        case BK_TV: e = launch_tv_pass_batched(bl.size, a, mp, bl.nblocks, q); break;
       }
       if (e != hipSuccess) return e;
     }
@@ -1130,4 +1161,251 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     if (st != RI_OK && agg == RI_OK) agg = st;
   }
   return agg;
+}
+
+// ---------------------------------------------------------------------------
+// Tuning: launch shapes per geometry, chosen by timing on the device and kept
+// in an optional cache file (one JSON object per line).
+// ---------------------------------------------------------------------------
+static ri_status validate_tuning(const ri_tuning* t) {
+  if (!t) return fail(RI_ERR_INVALID_ARG, "tuning is NULL");
+  if (t->tv_levels < kTvLevelsMin || t->tv_levels > kTvLevelsMax)
+    return fail(RI_ERR_INVALID_ARG, "tv_levels=%d must be in [%d, %d]", t->tv_levels, kTvLevelsMin, kTvLevelsMax);
+  if (t->tv_blocks < 64 || t->tv_blocks > 65536)
+    return fail(RI_ERR_INVALID_ARG, "tv_blocks=%d must be in [64, 65536]", t->tv_blocks);
+  if (t->col_blocks < kColMinBlocks || t->col_blocks > kColMaxBlocks)
+    return fail(RI_ERR_INVALID_ARG, "col_blocks=%d must be in [%d, %d]", t->col_blocks, kColMinBlocks, kColMaxBlocks);
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_get_tuning(const ri_plan* p, ri_tuning* out) {
+  if (!p || !out) return fail(RI_ERR_INVALID_ARG, "NULL argument");
+  *out = p->tune;
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_set_tuning(ri_plan* p, const ri_tuning* t) {
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const ri_status vs = validate_tuning(t);
+  if (vs != RI_OK) return vs;
+  p->tune = *t;
+  drop_graph(p);
+  return RI_OK;
+}
+
+static std::string tune_key(const ri_plan* p, int inner) {
+  hipDeviceProp_t prop{};
+  char arch[96] = "unknown";
+  int cus = 0;
+  if (hipGetDeviceProperties(&prop, p->device) == hipSuccess) {
+    std::snprintf(arch, sizeof(arch), "%s", prop.gcnArchName);
+    cus = prop.multiProcessorCount;
+  }
+  for (char* c = arch; *c; ++c)
+    if (*c == '"' || *c == '\\' || *c == '|' || (unsigned char)*c < 32) *c = '_';
+  char key[256];
+  std::snprintf(key, sizeof(key), "%s|%d|%dx%dx%d|k%d|v1", arch, cus, p->g.nx, p->g.ny, p->g.nz, inner);
+  return key;
+}
+
+static bool json_int(const std::string& line, const char* name, int* out) {
+  const std::string pat = std::string("\"") + name + "\":";
+  const size_t at_ = line.find(pat);
+  if (at_ == std::string::npos) return false;
+  const char* b = line.c_str() + at_ + pat.size();
+  char* e = nullptr;
+  const long v = std::strtol(b, &e, 10);
+  if (e == b || v < -2147483647L || v > 2147483647L) return false;
+  *out = (int)v;
+  return true;
+}
+
+static std::vector<std::string> read_lines(const char* path) {
+  std::vector<std::string> lines;
+  FILE* f = std::fopen(path, "r");
+  if (!f) return lines;
+  std::string cur;
+  int ch;
+  while ((ch = std::fgetc(f)) != EOF) {
+    if (ch == '\n') {
+      if (!cur.empty()) lines.push_back(cur);
+      cur.clear();
+    } else {
+      cur.push_back((char)ch);
+    }
+  }
+  if (!cur.empty()) lines.push_back(cur);
+  std::fclose(f);
+  return lines;
+}
+
+static std::string key_field(const std::string& key) { return "{\"key\": \"" + key + "\","; }
+
+static bool cache_lookup(const char* path, const std::string& key, ri_tuning* out) {
+  const std::string head = key_field(key);
+  for (const std::string& line : read_lines(path)) {
+    if (line.compare(0, head.size(), head) != 0) continue;
+    ri_tuning t{};
+    if (!json_int(line, "tv_levels", &t.tv_levels) || !json_int(line, "tv_blocks", &t.tv_blocks) ||
+        !json_int(line, "col_blocks", &t.col_blocks))
+      continue;
+    if (t.tv_levels < kTvLevelsMin || t.tv_levels > kTvLevelsMax || t.tv_blocks < 64 || t.tv_blocks > 65536 ||
+        t.col_blocks < kColMinBlocks || t.col_blocks > kColMaxBlocks)
+      continue;
+    *out = t;
+    return true;
+  }
+  return false;
+}
+
+static bool cache_store(const char* path, const std::string& key, const ri_tuning& t, double best_ms,
+                        double default_ms) {
+  const std::string head = key_field(key);
+  std::vector<std::string> lines;
+  for (const std::string& line : read_lines(path))
+    if (line.compare(0, head.size(), head) != 0) lines.push_back(line);
+  char buf[512];
+  std::snprintf(buf, sizeof(buf), "%s \"tv_levels\": %d, \"tv_blocks\": %d, \"col_blocks\": %d, "
+                "\"best_ms\": %.6g, \"default_ms\": %.6g}", head.c_str(), t.tv_levels, t.tv_blocks, t.col_blocks,
+                best_ms, default_ms);
+  lines.push_back(buf);
+  const std::string tmp = std::string(path) + ".tmp." + std::to_string((long)getpid());
+  FILE* f = std::fopen(tmp.c_str(), "w");
+  if (!f) return false;
+  bool ok = true;
+  for (const std::string& line : lines) ok = ok && std::fprintf(f, "%s\n", line.c_str()) > 0;
+  ok = (std::fclose(f) == 0) && ok;
+  if (ok) ok = std::rename(tmp.c_str(), path) == 0;
+  if (!ok) std::remove(tmp.c_str());
+  return ok;
+}
+
+// Average device time of one call of `enq` on stream s: one untimed call, one
+// timed call to size the repetition count (~5 ms of work, 3..50 calls).
+template <class F>
+static hipError_t time_calls(hipStream_t s, F&& enq, double* ms) {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipError_t e = hipEventCreate(&a);
+  if (e == hipSuccess) e = hipEventCreate(&b);
+  float t = 0.f;
+  int reps = 1;
+  if (e == hipSuccess) e = enq();
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  if (e == hipSuccess) e = enq();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  if (e == hipSuccess) {
+    reps = (int)std::min(50.0, std::max(3.0, std::ceil(5.0 / std::max(1e-3, (double)t))));
+    e = hipEventRecord(a, s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r) e = enq();
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+  }
+  if (a) hipEventDestroy(a);
+  if (b) hipEventDestroy(b);
+  *ms = (double)t / reps;
+  return e;
+}
+
+extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const char* cache_path, void* ws,
+                                      size_t ws_bytes, void* stream, ri_autotune_report* report) {
+  const auto t0 = std::chrono::steady_clock::now();
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (inner_iters < 0) return fail(RI_ERR_INVALID_ARG, "inner_iters=%d must be >= 0", inner_iters);
+  const Layout LT = make_layout(p, RI_OP_AUTOTUNE);
+  if (!ws) return fail(RI_ERR_INVALID_ARG, "workspace is NULL (needs %zu bytes)", LT.total);
+  if (ws_bytes < LT.total) return fail(RI_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", ws_bytes, LT.total);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(RI_ERR_INVALID_ARG, "plan belongs to device %d, current device is %d", p->device, dev);
+  hipStream_t s = (hipStream_t)stream;
+  ri_autotune_report rep{};
+  const std::string key = tune_key(p, inner_iters);
+  const ri_tuning dflt{kTvDefaultLevels, kTvDefaultBlocks, kColDefaultBlocks};
+  auto finish = [&](const ri_tuning& t) {
+    p->tune = t;
+    drop_graph(p);
+    rep.best = t;
+    rep.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (report) *report = rep;
+    return RI_OK;
+  };
+  if (cache_path) {
+    ri_tuning hit{};
+    if (cache_lookup(cache_path, key, &hit)) {
+      rep.from_cache = 1;
+      return finish(hit);
+    }
+  }
+  const int nx = p->g.nx, ny = p->g.ny, nz = p->g.nz;
+  const size_t nvox = (size_t)nx * ny * nz;
+  float* xv = at<float>(ws, LT.vol1);   // x for A, v for the prox (zeros)
+  float* xo = at<float>(ws, LT.vol2);   // A^T y, prox output
+  float* hy = at<float>(ws, LT.ax0);    // A x, y for A^T (zeros)
+  HIP_TRY(launch_fill_f32(xv, nvox, 0.f, s));
+  HIP_TRY(launch_fill_f32(hy, (size_t)nx * ny, 0.f, s));
+
+  // column chunking: forward + adjoint
+  std::vector<int> seen;
+  double col_best = 0.0, col_dflt = 0.0;
+  int col_choice = dflt.col_blocks;
+  for (int c : kColBlockCands) {
+    int nchunk = 0, ppc = 0;
+    chunking(p, c, &nchunk, &ppc);
+    if (std::find(seen.begin(), seen.end(), nchunk) != seen.end() && c != dflt.col_blocks) continue;
+    seen.push_back(nchunk);
+    const Layout L = make_layout(p, RI_OP_SOLVE, c);
+    if (L.total > LT.total) continue;
+    double ms = 0.0;
+    HIP_TRY(time_calls(s, [&]() -> hipError_t {
+      hipError_t e = enqueue_forward(p, L, ws, xv, hy, s);
+      return e == hipSuccess ? enqueue_adjoint(p, L, ws, hy, xo, s) : e;
+    }, &ms));
+    ++rep.candidates;
+    if (c == dflt.col_blocks) col_dflt = ms;
+    if (col_best == 0.0 || ms < col_best) { col_best = ms; col_choice = c; }
+  }
+  if (col_best > 0.99 * col_dflt) { col_best = col_dflt; col_choice = dflt.col_blocks; }
+
+  // TV prox: fusion depth x z-chunking
+  double tv_best = 0.0, tv_dflt = 0.0;
+  int lv_choice = dflt.tv_levels, tb_choice = dflt.tv_blocks;
+  std::vector<std::pair<int, int>> seen_tv;
+  for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
+    for (int b : kTvBlockCands) {
+      const bool is_dflt = H == dflt.tv_levels && b == dflt.tv_blocks;
+      const std::pair<int, int> g{H, tv_pass_zchunk(nx, ny, nz, H, b)};
+      if (std::find(seen_tv.begin(), seen_tv.end(), g) != seen_tv.end() && !is_dflt) continue;
+      seen_tv.push_back(g);
+      ProxArgs a{};
+      a.v = xv;
+      a.x = xo;
+      for (int k = 0; k < 3; ++k) a.pa[k] = at<float>(ws, LT.pa[k]);
+      for (int k = 0; k < 3; ++k) a.pb[k] = at<float>(ws, LT.pb[k]);
+      a.rowflag = at<uint8_t>(ws, LT.rowflag);
+      a.planeflag = at<uint8_t>(ws, LT.planeflag);
+      a.nx = nx; a.ny = ny; a.nz = nz;
+      a.inner_iters = inner_iters;
+      a.nonneg = 1;
+      a.step = 1.0 / p->lipschitz;
+      a.l1 = 0.0;
+      a.tv = 1.0;
+      a.levels = H;
+      a.blocks = b;
+      double ms = 0.0;
+      HIP_TRY(time_calls(s, [&]() -> hipError_t { return launch_prox(a, s, nullptr); }, &ms));
+      ++rep.candidates;
+      if (is_dflt) tv_dflt = ms;
+      if (tv_best == 0.0 || ms < tv_best) { tv_best = ms; lv_choice = H; tb_choice = b; }
+    }
+  }
+  if (tv_best > 0.99 * tv_dflt) { tv_best = tv_dflt; lv_choice = dflt.tv_levels; tb_choice = dflt.tv_blocks; }
+
+  const ri_tuning best{lv_choice, tb_choice, col_choice};
+  rep.default_ms = col_dflt + tv_dflt;
+  rep.best_ms = col_best + tv_best;
+  if (cache_path) rep.cache_written = cache_store(cache_path, key, best, rep.best_ms, rep.default_ms) ? 1 : -1;
+  return finish(best);
 }

@@ -44,7 +44,9 @@ struct PlanTables {
 
 // Launch shapes (host side mirrors of the compile-time choices).
 int rows_per_block(int m);     // rows of a length-m packed transform per row block
-int col_tile_width(int ny);    // columns per column tile
+int col_tile_width(int ny);
+// Default / largest target block count of the column transforms (z-chunking).
+constexpr int kColDefaultBlocks = 512, kColMinBlocks = 16, kColMaxBlocks = 8192;    // columns per column tile
 bool fft_len_supported(int L);
 
 // ---------------------------------------------------------------------------
@@ -217,9 +219,15 @@ struct ProxArgs {
   int nonneg;
   double step, l1, tv;   // outside a solve (st == nullptr)
   const SolveState* st;  // solver: weights from st, step from `step`
+  int levels;            // dual steps fused per pass (kTvLevelsMin..kTvLevelsMax; else the default)
+  int blocks;            // target blocks per pass (<= 0: the default)
 };
+constexpr int kTvLevelsMin = 2, kTvLevelsMax = 4, kTvDefaultLevels = 3;
+constexpr int kTvDefaultBlocks = 1536;
 hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
-int prox_passes(int inner_iters, double tau);
+int prox_passes(int inner_iters, double tau, int levels);
+// Planes per block of a pass for the given tuning (distinct values = distinct grids).
+int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks);
 
 // Batched prox: the argument structs of every pass of every frame are built on
 // the host (prox_pass_args) and uploaded; launch p runs pass p of all frames.
@@ -228,6 +236,6 @@ size_t tv_pass_args_size();
 // Fills `out` (npass structs, host memory of npass * tv_pass_args_size() bytes)
 // for one frame and returns the number of passes and the frame's blocks per pass.
 int prox_pass_args(const ProxArgs& a, void* out, int* blocks_per_pass);
-hipError_t launch_tv_pass_batched(const void* args, BatchMap map, int nblocks, hipStream_t s);
+hipError_t launch_tv_pass_batched(int levels, const void* args, BatchMap map, int nblocks, hipStream_t s);
 
 }  // namespace rihvr

@@ -315,14 +315,21 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
   }
 }
 
+// Register budget: the two- and three-deep pipelines fit 128 VGPRs, so LDS
+// (not registers) limits them to two blocks of eight waves per CU; the
+// four-deep one, and the three-deep batched entry (which also holds the frame
+// lookup), keep their full register file.
+template <int H, bool BATCHED>
+constexpr int tv_min_blocks() { return (H <= 2 || (H == 3 && !BATCHED)) ? 4 : 1; }
+
 template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass(TvPassArgs A) {
+__global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, false>())) k_tv_pass(TvPassArgs A) {
   tv_pass_entry<H>(A, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass_b(const TvPassArgs* __restrict__ args,
-                                                             BatchMap map) {
+__global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, true>())) k_tv_pass_b(const TvPassArgs* __restrict__ args,
+                                                                                  BatchMap map) {
   const uint32_t b = blockIdx.x;
   int lo = 0, hi = map.n;  // largest f with offs[f] <= b
   while (hi - lo > 1) {
@@ -335,37 +342,44 @@ __global__ void __launch_bounds__(kTvWaves * 64) k_tv_pass_b(const TvPassArgs* _
   tv_pass_entry<H>(A, lb % A.gx, (lb / A.gx) % A.gy, lb / (A.gx * A.gy));
 }
 
-// Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut so that
-// the grid holds at least ~3 blocks per CU where the volume allows it.
-static void pass_grid(int nx, int ny, int nz, int H, dim3* grid, int* zchunk) {
+// Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut into
+// chunks of at least 16 planes until the grid holds about `want` blocks.
+static void pass_grid(int nx, int ny, int nz, int H, int want, dim3* grid, int* zchunk) {
   const int tx = (nx + (kTvRX - 2 * H) - 1) / (kTvRX - 2 * H);
   const int ty = (ny + (kTvRY - 2 * H) - 1) / (kTvRY - 2 * H);
-  const int want = 1536;
-  int nzc = std::max(1, std::min(nz / 16, (want + tx * ty - 1) / (tx * ty)));
-  if (nzc < 1) nzc = 1;
+  const int nzc = std::max(1, std::min(nz / 16, (want + tx * ty - 1) / (tx * ty)));
   const int zc = (nz + nzc - 1) / nzc;
   *zchunk = zc;
   *grid = dim3(tx, ty, (nz + zc - 1) / zc);
 }
 
-constexpr int kTvH = 4;
+static int clamp_levels(int H) { return H < kTvLevelsMin ? kTvDefaultLevels : std::min(H, kTvLevelsMax); }
 
-int prox_passes(int inner_iters, double tau) {
+int prox_passes(int inner_iters, double tau, int levels) {
   if (!(tau > 0.0) || inner_iters <= 0) return 1;
-  return (inner_iters + 1 + kTvH - 1) / kTvH;   // K dual steps + one primal half step
+  const int H = clamp_levels(levels);
+  return (inner_iters + 1 + H - 1) / H;   // K dual steps + one primal half step
 }
 
 size_t tv_pass_args_size() { return sizeof(TvPassArgs); }
 
+int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks) {
+  dim3 g;
+  int zc = 0;
+  pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks, &g, &zc);
+  return zc;
+}
+
 // Argument structs of every pass of one prox application.  Dual steps per
-// pass: non-final passes take kTvH, the final pass the rest (at most kTvH - 1,
+// pass: non-final passes take H, the final pass the rest (at most H - 1,
 // leaving room for the primal half step in its halo).
 int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   const double tau = pa.step * pa.tv;
   const double thr = pa.step * pa.l1;
   const bool use_tv = tau > 0.0 && pa.inner_iters > 0;
   const int K = use_tv ? pa.inner_iters : 0;
-  const int npass = prox_passes(K, tau);
+  const int H = clamp_levels(pa.levels);
+  const int npass = prox_passes(K, tau, H);
   TvPassArgs a{};
   a.v = pa.v;
   a.x = pa.x;
@@ -379,7 +393,7 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   a.c = use_tv ? (float)(1.0 / (12.0 * tau)) : 0.f;
   a.thr = (float)thr;
   dim3 grid;
-  pass_grid(pa.nx, pa.ny, pa.nz, kTvH, &grid, &a.zchunk);
+  pass_grid(pa.nx, pa.ny, pa.nz, H, pa.blocks > 0 ? pa.blocks : kTvDefaultBlocks, &grid, &a.zchunk);
   a.gx = grid.x;
   a.gy = grid.y;
   if (blocks_per_pass) *blocks_per_pass = grid.x * grid.y * grid.z;
@@ -387,7 +401,7 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   int done = 0;
   for (int p = 0; p < npass; ++p) {
     const bool fin = p == npass - 1;
-    const int lv = fin ? K - done : std::min(kTvH, K - done);
+    const int lv = fin ? K - done : std::min(H, K - done);
     a.levels = lv;
     a.first = (done == 0) ? 1 : 0;
     a.final_ = fin ? 1 : 0;
@@ -406,18 +420,29 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
 hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
   const double tau = pa.step * pa.tv;
   const int K = (tau > 0.0 && pa.inner_iters > 0) ? pa.inner_iters : 0;
-  std::vector<TvPassArgs> args(prox_passes(K, tau));
+  const int H = clamp_levels(pa.levels);
+  std::vector<TvPassArgs> args(prox_passes(K, tau, H));
   int nb = 0;
   const int npass = prox_pass_args(pa, args.data(), &nb);
   const dim3 grid(args[0].gx, args[0].gy, (nb / (args[0].gx * args[0].gy)));
-  for (int p = 0; p < npass; ++p) hipLaunchKernelGGL(k_tv_pass<kTvH>, grid, dim3(kTvWaves * 64), 0, s, args[p]);
+  for (int p = 0; p < npass; ++p) {
+    switch (H) {
+      case 2: hipLaunchKernelGGL(k_tv_pass<2>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
+      case 3: hipLaunchKernelGGL(k_tv_pass<3>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
+      default: hipLaunchKernelGGL(k_tv_pass<4>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
+    }
+  }
   if (launches) *launches = npass;
   return hipGetLastError();
 }
 
-hipError_t launch_tv_pass_batched(const void* args, BatchMap map, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL(k_tv_pass_b<kTvH>, dim3(nblocks), dim3(kTvWaves * 64), 0, s,
-                     static_cast<const TvPassArgs*>(args), map);
+hipError_t launch_tv_pass_batched(int levels, const void* args, BatchMap map, int nblocks, hipStream_t s) {
+  const TvPassArgs* a = static_cast<const TvPassArgs*>(args);
+  switch (clamp_levels(levels)) {
+    case 2: hipLaunchKernelGGL(k_tv_pass_b<2>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
+    case 3: hipLaunchKernelGGL(k_tv_pass_b<3>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
+    default: hipLaunchKernelGGL(k_tv_pass_b<4>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
+  }
   return hipGetLastError();
 }
 

@@ -36,12 +36,13 @@ RI_SOLVE_NO_GRAPH = 0x2
 RI_SOLVE_RESTART = 0x4
 RI_SOLVE_TIMING = 0x8
 
-RI_OP_FORWARD, RI_OP_ADJOINT, RI_OP_PROX, RI_OP_SOLVE = 0, 1, 2, 3
+RI_OP_FORWARD, RI_OP_ADJOINT, RI_OP_PROX, RI_OP_SOLVE, RI_OP_AUTOTUNE = 0, 1, 2, 3, 4
 RI_NUM_PHASES = 6
 PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 
 EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size",
+    "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_autotune",
     "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
     "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
@@ -83,6 +84,24 @@ class ri_solve_report(C.Structure):
         }
 
 
+class ri_tuning(C.Structure):
+    _fields_ = [("tv_levels", C.c_int32), ("tv_blocks", C.c_int32), ("col_blocks", C.c_int32)]
+
+    def as_dict(self):
+        return {"tv_levels": self.tv_levels, "tv_blocks": self.tv_blocks, "col_blocks": self.col_blocks}
+
+
+class ri_autotune_report(C.Structure):
+    _fields_ = [("best", ri_tuning), ("from_cache", C.c_int32), ("cache_written", C.c_int32),
+                ("candidates", C.c_int32), ("default_ms", C.c_double), ("best_ms", C.c_double),
+                ("tune_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"best": self.best.as_dict(), "from_cache": bool(self.from_cache),
+                "cache_written": self.cache_written, "candidates": self.candidates,
+                "default_ms": self.default_ms, "best_ms": self.best_ms, "tune_ms": self.tune_ms}
+
+
 class ri_unet_config(C.Structure):
     _fields_ = [("levels", C.c_int32), ("base", C.c_int32)]
 
@@ -109,6 +128,9 @@ def lib():
     L.ri_plan_destroy.argtypes = [vp]
     L.ri_plan_lipschitz.argtypes = [vp, C.POINTER(C.c_double)]
     L.ri_workspace_size.argtypes = [vp, C.c_int, C.POINTER(sz)]
+    L.ri_plan_get_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
+    L.ri_plan_set_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
+    L.ri_plan_autotune.argtypes = [vp, C.c_int32, C.c_char_p, vp, sz, vp, C.POINTER(ri_autotune_report)]
     L.ri_forward.argtypes = [vp, vp, vp, vp, sz, vp]
     L.ri_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
     L.ri_prox_fused_lasso.argtypes = [vp, C.POINTER(ri_prox_params), C.c_double, vp, vp, vp, sz, vp]
@@ -164,6 +186,22 @@ def ri_workspace_size(plan: int, op: int) -> int:
     v = C.c_size_t()
     _check(lib().ri_workspace_size(plan, op, C.byref(v)), "ri_workspace_size")
     return v.value
+
+
+def ri_plan_get_tuning(plan: int) -> ri_tuning:
+    t = ri_tuning()
+    _check(lib().ri_plan_get_tuning(plan, C.byref(t)), "ri_plan_get_tuning")
+    return t
+
+
+def ri_plan_set_tuning(plan: int, tuning: ri_tuning) -> int:
+    return lib().ri_plan_set_tuning(plan, C.byref(tuning))
+
+
+def ri_plan_autotune(plan, inner_iters, cache_path, ws, ws_bytes, stream, report=None) -> int:
+    path = None if cache_path is None else str(cache_path).encode()
+    return lib().ri_plan_autotune(plan, inner_iters, path, ws, ws_bytes, stream,
+                                  C.byref(report) if report is not None else None)
 
 
 def ri_forward(plan, x, b_out, ws, ws_bytes, stream) -> int:
@@ -281,6 +319,24 @@ class Plan:
             ws = self.torch.empty(max(n, 1), dtype=self.torch.uint8, device="cuda")
             self._ws[op] = ws
         return ws, n
+
+    @property
+    def tuning(self) -> dict:
+        return ri_plan_get_tuning(self.handle).as_dict()
+
+    @tuning.setter
+    def tuning(self, t: dict):
+        _check(ri_plan_set_tuning(self.handle, ri_tuning(int(t["tv_levels"]), int(t["tv_blocks"]),
+                                                         int(t["col_blocks"]))), "ri_plan_set_tuning")
+
+    def autotune(self, inner_iters: int, cache_path=None) -> dict:
+        """Time the candidate launch shapes on the device and keep the fastest (see ri_plan_autotune)."""
+        ws, n = self.workspace(RI_OP_AUTOTUNE)
+        rep = ri_autotune_report()
+        _check(ri_plan_autotune(self.handle, int(inner_iters), cache_path, ws.data_ptr(), ws.numel(),
+                                _stream_handle(self.torch), rep), "ri_plan_autotune")
+        self._ws.pop(RI_OP_AUTOTUNE, None)
+        return rep.as_dict()
 
     def _chk(self, t, shape):
         torch = self.torch

@@ -53,10 +53,15 @@ int main(void) {
   printf("ri_prox_params %zu\n", sizeof(ri_prox_params));
   printf("ri_solve_params %zu\n", sizeof(ri_solve_params));
   printf("ri_solve_report %zu\n", sizeof(ri_solve_report));
+  printf("ri_tuning %zu\n", sizeof(ri_tuning));
+  printf("ri_autotune_report %zu\n", sizeof(ri_autotune_report));
   F(ri_geometry, pixel_um) F(ri_geometry, flags)
   F(ri_prox_params, inner_iters) F(ri_prox_params, nonneg)
   F(ri_solve_params, gap_tol) F(ri_solve_params, init) F(ri_solve_params, flags) F(ri_solve_params, nonneg)
   F(ri_solve_report, objective) F(ri_solve_report, phase_ms) F(ri_solve_report, phase_launches)
+  F(ri_tuning, tv_blocks) F(ri_tuning, col_blocks)
+  F(ri_autotune_report, from_cache) F(ri_autotune_report, candidates) F(ri_autotune_report, default_ms)
+  F(ri_autotune_report, tune_ms)
   return 0;
 }
 """
@@ -72,6 +77,8 @@ int main(void) {
         "ri_prox_params": C.sizeof(rihvr.ri_prox_params),
         "ri_solve_params": C.sizeof(rihvr.ri_solve_params),
         "ri_solve_report": C.sizeof(rihvr.ri_solve_report),
+        "ri_tuning": C.sizeof(rihvr.ri_tuning),
+        "ri_autotune_report": C.sizeof(rihvr.ri_autotune_report),
     }
     for k, v in ctypes_side.items():
         assert int(got[k]) == v, k
@@ -116,6 +123,11 @@ def test_null_arguments_rejected(lib):
     sp = rihvr.ri_solve_params()
     assert lib.ri_solve(None, C.byref(sp), None, None, None, 0, None, None) == rihvr.RI_ERR_INVALID_ARG
     assert lib.ri_plan_destroy(None) == rihvr.RI_ERR_INVALID_ARG
+    t = rihvr.ri_tuning(3, 1536, 512)
+    assert lib.ri_plan_get_tuning(None, C.byref(t)) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_plan_set_tuning(None, C.byref(t)) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_plan_autotune(None, 10, None, None, 0, None, None) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_workspace_size(None, rihvr.RI_OP_AUTOTUNE, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
     assert rihvr.ri_solve_batched(0, [], [], [], [], None, 0, None) == rihvr.RI_OK
     assert lib.ri_solve_batched(-1, None, None, None, None, None, 0, None, None) == rihvr.RI_ERR_INVALID_ARG
 

@@ -1,0 +1,167 @@
+"""Launch-shape tuning of a plan: every tuning computes the same operators, the
+autotuner picks one of its candidates and keeps it in its cache file, and a
+batch of frames with different tunings equals the per-frame solves.
+
+Parity bars are those of the operator and prox tests (relative L2 1e-5 against
+the FP64 oracle); the batched comparison is exact.
+"""
+import json
+
+import numpy as np
+import pytest
+
+from oracle import optics, prox
+from paper_1904_04884_amd import rihvr, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def to_host(t):
+    return t.detach().cpu().numpy().astype(np.float64)
+
+
+def geom(nx, ny, nz):
+    return scenes.geometry_c1().with_(nx=nx, ny=ny, nz=nz)
+
+
+@pytest.fixture
+def plan_of(torch_cuda):
+    made = []
+
+    def make(g, **tuning):
+        p = rihvr.Plan(g)
+        if tuning:
+            t = p.tuning
+            t.update(tuning)
+            p.tuning = t
+        made.append(p)
+        return p
+    yield make
+    for p in made:
+        p.close()
+
+
+def test_default_tuning_and_validation(plan_of):
+    p = plan_of(geom(64, 48, 6))
+    assert p.tuning == {"tv_levels": 3, "tv_blocks": 1536, "col_blocks": 512}
+    for bad in ({"tv_levels": 1}, {"tv_levels": 5}, {"tv_blocks": 63}, {"tv_blocks": 65537},
+                {"col_blocks": 15}, {"col_blocks": 8193}):
+        t = p.tuning
+        t.update(bad)
+        with pytest.raises(rihvr.RihvrError) as e:
+            p.tuning = t
+        assert e.value.status == rihvr.RI_ERR_INVALID_ARG
+        assert p.tuning == {"tv_levels": 3, "tv_blocks": 1536, "col_blocks": 512}
+
+
+@pytest.mark.parametrize("levels", [2, 3, 4])
+@pytest.mark.parametrize("blocks", [64, 768, 6144])
+def test_prox_parity_every_tv_tuning(torch_cuda, plan_of, levels, blocks):
+    """Fusion depths 2..4 and z-chunkings from one chunk to 16-plane chunks, with
+    dual-step counts that leave 0, 1 and 2 steps for the final pass."""
+    torch = torch_cuda
+    g = geom(192, 96, 40)
+    p = plan_of(g, tv_levels=levels, tv_blocks=blocks)
+    rng = np.random.default_rng(31 + levels)
+    v = (0.3 * rng.standard_normal(g.shape)).astype(np.float32)
+    step, l1, tv = 0.5, 0.05, 0.3
+    for k in (1, 5, 8):
+        ref = prox.prox_fused_lasso(v.astype(np.float64), step, l1, tv, k)
+        out = to_host(p.prox(to_dev(torch, v), step, l1, tv, k))
+        assert rel_l2(out, ref) <= 1e-5, (levels, blocks, k)
+
+
+@pytest.mark.parametrize("col_blocks", [16, 128, 2048, 8192])
+@pytest.mark.parametrize("shape", [(128, 128, 32), (96, 48, 7)])
+def test_operators_every_column_chunking(torch_cuda, plan_of, col_blocks, shape):
+    torch = torch_cuda
+    g = geom(*shape)
+    p = plan_of(g, col_blocks=col_blocks)
+    rng = np.random.default_rng(41)
+    x = rng.random(g.shape)
+    y = rng.standard_normal((g.ny, g.nx))
+    assert rel_l2(to_host(p.forward(to_dev(torch, x))), optics.forward(g, x)) <= 1e-5
+    assert rel_l2(to_host(p.adjoint(to_dev(torch, y))), optics.adjoint(g, y)) <= 1e-5
+
+
+def test_autotune_picks_a_candidate_and_caches_it(torch_cuda, plan_of, tmp_path):
+    torch = torch_cuda
+    g = geom(128, 128, 32)
+    cache = tmp_path / "tune.jsonl"
+    p = plan_of(g)
+    r = p.autotune(4, cache)
+    assert not r["from_cache"] and r["cache_written"] == 1 and r["candidates"] >= 3
+    assert r["best"] == p.tuning
+    assert r["best"]["tv_levels"] in (2, 3, 4)
+    assert 0 < r["best_ms"] <= r["default_ms"]
+    lines = cache.read_text().splitlines()
+    assert len(lines) == 1
+    entry = json.loads(lines[0])
+    assert "|128x128x32|k4|" in entry["key"]
+    assert {k: entry[k] for k in ("tv_levels", "tv_blocks", "col_blocks")} == r["best"]
+    # a second plan of the same geometry takes the cached choice without timing
+    q = plan_of(g)
+    r2 = q.autotune(4, cache)
+    assert r2["from_cache"] and r2["candidates"] == 0 and q.tuning == r["best"]
+    # another inner-iteration count is another entry; re-tuning replaces, not duplicates
+    q.autotune(7, cache)
+    p.autotune(4, None)
+    assert len(cache.read_text().splitlines()) == 2
+    # the tuned plan still computes the prox of the oracle
+    rng = np.random.default_rng(43)
+    v = (0.3 * rng.standard_normal(g.shape)).astype(np.float32)
+    ref = prox.prox_fused_lasso(v.astype(np.float64), 0.5, 0.05, 0.3, 4)
+    assert rel_l2(to_host(p.prox(to_dev(torch, v), 0.5, 0.05, 0.3, 4)), ref) <= 1e-5
+
+
+def test_autotune_rejects_small_workspace(torch_cuda, plan_of):
+    torch = torch_cuda
+    p = plan_of(geom(64, 64, 8))
+    n = rihvr.ri_workspace_size(p.handle, rihvr.RI_OP_AUTOTUNE)
+    assert n >= rihvr.ri_workspace_size(p.handle, rihvr.RI_OP_SOLVE)
+    ws = torch.empty(n, dtype=torch.uint8, device="cuda")
+    st = rihvr.ri_plan_autotune(p.handle, 4, None, ws.data_ptr(), n - 1, torch.cuda.current_stream().cuda_stream)
+    assert st == rihvr.RI_ERR_WORKSPACE_TOO_SMALL
+    assert rihvr.ri_plan_autotune(p.handle, -1, None, ws.data_ptr(), n,
+                                  torch.cuda.current_stream().cuda_stream) == rihvr.RI_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batched_mixed_tunings_match_single(torch_cuda, plan_of, graph):
+    """Frames with different fusion depths and chunkings in one batch (TV passes
+    grouped by depth) equal their per-frame solves exactly."""
+    torch = torch_cuda
+    spec = [((64, 64, 8), dict(tv_levels=2, tv_blocks=64)),
+            ((48, 96, 5), dict(tv_levels=4, col_blocks=16)),
+            ((128, 128, 20), dict(tv_levels=3, tv_blocks=6144, col_blocks=2048)),
+            ((64, 64, 3), dict(tv_levels=4)),
+            ((96, 96, 7), dict(tv_levels=2, col_blocks=128))]
+    ps = [plan_of(geom(*s), **t) for s, t in spec]
+    iters = [6, 4, 6, 9, 5]
+    rng = np.random.default_rng(17)
+    bs = [to_dev(torch, rng.standard_normal((p.geom.ny, p.geom.nx))) for p in ps]
+    singles = [p.solve(b, 0.05, 0.02, k, 5)[0].clone() for p, b, k in zip(ps, bs, iters)]
+    flags = 0 if graph else rihvr.RI_SOLVE_NO_GRAPH
+    params = [p.solve_params(0.05, 0.02, k, 5, flags=flags) for p, k in zip(ps, iters)]
+    handles = [p.handle for p in ps]
+    nbytes = rihvr.ri_workspace_size_batched(len(ps), handles, params)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    xs = [torch.empty(p.shape, dtype=torch.float32, device="cuda") for p in ps]
+    reps = (rihvr.ri_solve_report * len(ps))()
+    st = rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs],
+                                [x.data_ptr() for x in xs], ws.data_ptr(), ws.numel(),
+                                torch.cuda.current_stream().cuda_stream, reps)
+    assert st == rihvr.RI_OK, rihvr.ri_last_error()
+    for a, sgl in zip(xs, singles):
+        assert torch.equal(a, sgl)
+    assert [r.iters for r in reps] == iters
