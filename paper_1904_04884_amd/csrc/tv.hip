@@ -63,9 +63,6 @@ __device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
 }
 
-// Pass body.  EDGE: the tile touches the volume boundary, so every access and
-// every difference is masked; interior tiles (most of them) skip the masks.
-// FIRST: the incoming dual is zero (nothing is read).
 // A pointer known to be the same in every lane (keeps address bases in SGPRs).
 template <class T>
 __device__ __forceinline__ T* uniform_ptr(T* p) {
@@ -75,7 +72,29 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
-template <int H, bool EDGE, bool FIRST>
+// Planes are addressed through buffer resources: a scalar descriptor of one
+// plane (base, size in bytes) and a 32-bit per-lane byte offset.  A load at an
+// offset past the plane returns 0 and a store there is dropped, so lanes
+// outside the volume or outside the stored region use kTvOff.
+constexpr unsigned kTvOff = 0x80000000u;
+constexpr int kTvRsrcWord3 = 0x00020000;  // 32-bit data format, no stride / swizzle
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(const float* base, size_t plane, size_t sz) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base) + plane * sz, (short)0, (int)(sz * 4),
+                                           kTvRsrcWord3);
+}
+__device__ __forceinline__ float buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+
+// Pass body.  EDGE: the tile touches the volume boundary, so every access and
+// every difference is masked; interior tiles (most of them) skip the masks.
+// FIRST: the incoming dual is zero (nothing is read).  FINAL: the last pass
+// (primal recovery and output) instead of storing the dual.
+
+template <int H, bool EDGE, bool FIRST, bool FINAL>
 __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int bz,
                                              float (*s_py)[2][kTvWaves][64], float (*s_ut)[2][kTvWaves][64],
                                              float* s_v) {
@@ -97,17 +116,19 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   const int zs = max(0, zb - M), zl = min(nz, ze + M);
   const float tau = A.tau, cc = A.c;
 
-  bool iny[Q], ylo[Q], yhi[Q], ys[Q];
-  unsigned off[Q];  // in-plane byte offset (32 bit, so loads use a scalar base + vector offset)
+  bool ylo[Q], yhi[Q], ys[Q];
+  unsigned off[Q];   // in-plane byte offset of the load (kTvOff outside the volume)
+  unsigned offs[Q];  // ... of the store (kTvOff outside the stored interior)
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
     const int y = ybase + q;
-    iny[q] = !EDGE || (y >= 0 && y < ny);
+    const bool iny = !EDGE || (y >= 0 && y < ny);
     ylo[q] = !EDGE || y > 0;
     yhi[q] = !EDGE || y + 1 < ny;
     const int r = wv * Q + q;
-    ys[q] = iny[q] && r >= H && r < kTvRY - H;
-    off[q] = (inx && iny[q]) ? (unsigned)(y * nx + x) * 4u : 0u;
+    ys[q] = ix_store && iny && r >= H && r < kTvRY - H;
+    off[q] = (inx && iny) ? (unsigned)(y * nx + x) * 4u : kTvOff;
+    offs[q] = ys[q] ? off[q] : kTvOff;
   }
   // per fused step: previous plane's dual (3) and primal (1); final stage: previous p_z
   float Pp[H][Q][3], Up[H][Q], PzF[Q];
@@ -121,149 +142,123 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
 #pragma unroll
   for (int q = 0; q < Q; ++q) PzF[q] = 0.f;
 
-  // v of recent planes lives in a thread-private LDS ring (slot = plane mod H+1);
-  // the next plane's v and dual are prefetched into registers one step ahead.
-  float vN[Q], pN[Q][3];
-  auto ld = [](const float* base, unsigned ob) -> float {
-    return *(const __attribute__((address_space(1))) float*)(reinterpret_cast<const char*>(base) + ob);
+  // Input planes are prefetched two ahead into two register sets used in
+  // turn (the z loop is unrolled by two so that each set keeps its registers
+  // and a set is read only after its loads, issued two planes earlier, are
+  // done).  v of recent planes lives in a thread-private LDS ring
+  // (slot = plane mod H+1).
+  struct InPlane {
+    float v[Q];
+    float p[Q][3];
   };
-  auto load_plane = [&](int a) {
-    const float* vp = v + (size_t)a * sz;
+  auto load_plane = [&](InPlane& P, int a) {
+    const __amdgpu_buffer_rsrc_t rv = plane_rsrc(v, a, sz);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) vN[q] = (inx && iny[q]) ? ld(vp, off[q]) : 0.f;
+    for (int q = 0; q < Q; ++q) P.v[q] = buf_ld(rv, off[q]);
     if constexpr (!FIRST) {
-      const float* p0 = A.pin[0] + (size_t)a * sz;
-      const float* p1 = A.pin[1] + (size_t)a * sz;
-      const float* p2 = A.pin[2] + (size_t)a * sz;
+      const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(A.pin[0], a, sz);
+      const __amdgpu_buffer_rsrc_t r1 = plane_rsrc(A.pin[1], a, sz);
+      const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(A.pin[2], a, sz);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        const bool in = inx && iny[q];
-        pN[q][0] = in ? ld(p0, off[q]) : 0.f;
-        pN[q][1] = in ? ld(p1, off[q]) : 0.f;
-        pN[q][2] = in ? ld(p2, off[q]) : 0.f;
+        P.p[q][0] = buf_ld(r0, off[q]);
+        P.p[q][1] = buf_ld(r1, off[q]);
+        P.p[q][2] = buf_ld(r2, off[q]);
       }
     }
   };
-  auto st_ = [](float* base, unsigned ob, float val) {
-    *(__attribute__((address_space(1))) float*)(reinterpret_cast<char*>(base) + ob) = val;
-  };
-  if constexpr (FIRST) {
-#pragma unroll
-    for (int q = 0; q < Q; ++q) pN[q][0] = pN[q][1] = pN[q][2] = 0.f;
-  }
   auto vring = [&](int a, int q) -> float& { return s_v[((a % (H + 1)) * Q + q) * NT + threadIdx.x]; };
-  load_plane(zs);
 
-  const int nsteps = (zl - zs) + L;
-  for (int s = 0; s < nsteps; ++s) {
-    const int par = s & 1;
-    const int a1 = zs + s;
-    float c3[Q][3];
+  // Arrival of the previous dual c3 at plane a for fused step l: u(a), then
+  // the dual step at plane a - 1 (which needs u(a) for its z-difference).
+  auto arrive = [&](int l, int a, int par, float (&c3)[Q][3]) {
+    s_py[l][par][wv][lane] = c3[Q - 1][1];
+    __syncthreads();
+    float un[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      if (a1 < zl) vring(a1, q) = vN[q];
-      c3[q][0] = pN[q][0];
-      c3[q][1] = pN[q][1];
-      c3[q][2] = pN[q][2];
+      const float pxm = dpp_from_left(c3[q][0]);
+      const float pym = (q > 0) ? c3[q - 1][1] : s_py[l][par][wv > 0 ? wv - 1 : 0][lane];
+      float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
+      d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
+      d += c3[q][2] - Pp[l][q][2];
+      un[q] = fmaf(tau, d, vring(a, q));
     }
-    if (a1 + 1 < zl) load_plane(a1 + 1);
+    if (a > zs) {
 #pragma unroll
-    for (int l = 0; l < H; ++l) {
-      if (l >= L) break;
-      const int a = zs + s - l;          // arrival plane of fused step l
-      if (a < zs || a > zl) continue;    // idle (uniform across the block)
-      if (a < zl) {
-        // ---- arrival of the previous dual at plane a ----
-        s_py[l][par][wv][lane] = c3[Q - 1][1];
-        __syncthreads();
-        float un[Q];
+      for (int q = 0; q < Q; ++q) {
+        const float u0 = Up[l][q];
+        const float uxp = dpp_from_right(u0);
+        const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
+        const float gx = xhi ? uxp - u0 : 0.f;
+        const float gy = yhi[q] ? uyp - u0 : 0.f;
+        const float gz = un[q] - u0;       // plane a exists
+        const float qx = fmaf(cc, gx, Pp[l][q][0]);
+        const float qy = fmaf(cc, gy, Pp[l][q][1]);
+        const float qz = fmaf(cc, gz, Pp[l][q][2]);
+        const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+        const float sc = fminf(1.f, __frsqrt_rn(n2));   // 1 / max(1, |q|)
+        Pp[l][q][0] = c3[q][0];
+        Pp[l][q][1] = c3[q][1];
+        Pp[l][q][2] = c3[q][2];
+        c3[q][0] = qx * sc;
+        c3[q][1] = qy * sc;
+        c3[q][2] = qz * sc;
+      }
+      // Up is read by the neighbours above (q+1) before it is replaced
 #pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const float pxm = dpp_from_left(c3[q][0]);
-          const float pym = (q > 0) ? c3[q - 1][1] : s_py[l][par][wv > 0 ? wv - 1 : 0][lane];
-          float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
-          d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
-          d += c3[q][2] - Pp[l][q][2];
-          un[q] = fmaf(tau, d, vring(a, q));
-        }
-        if (a > zs) {
-          // ---- dual step at plane a - 1 ----
+      for (int q = 0; q < Q; ++q) Up[l][q] = un[q];
+    } else {
 #pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            const float u0 = Up[l][q];
-            const float uxp = dpp_from_right(u0);
-            const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
-            const float gx = xhi ? uxp - u0 : 0.f;
-            const float gy = yhi[q] ? uyp - u0 : 0.f;
-            const float gz = un[q] - u0;       // plane a exists
-            const float qx = fmaf(cc, gx, Pp[l][q][0]);
-            const float qy = fmaf(cc, gy, Pp[l][q][1]);
-            const float qz = fmaf(cc, gz, Pp[l][q][2]);
-            const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-            const float sc = fminf(1.f, __frsqrt_rn(n2));   // 1 / max(1, |q|)
-            Pp[l][q][0] = c3[q][0];
-            Pp[l][q][1] = c3[q][1];
-            Pp[l][q][2] = c3[q][2];
-            c3[q][0] = qx * sc;
-            c3[q][1] = qy * sc;
-            c3[q][2] = qz * sc;
-          }
-          // Up is read by the neighbours above (q+1) before it is replaced
-#pragma unroll
-          for (int q = 0; q < Q; ++q) Up[l][q] = un[q];
-        } else {
-#pragma unroll
-          for (int q = 0; q < Q; ++q) {
-            Pp[l][q][0] = c3[q][0];
-            Pp[l][q][1] = c3[q][1];
-            Pp[l][q][2] = c3[q][2];
-            Up[l][q] = un[q];
-          }
-        }
-        s_ut[l][par][wv][lane] = un[0];
-      } else {
-        // ---- flush: dual step at the last plane zl - 1 (no plane above) ----
-        __syncthreads();
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          const float u0 = Up[l][q];
-          const float uxp = dpp_from_right(u0);
-          const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
-          const float gx = xhi ? uxp - u0 : 0.f;
-          const float gy = yhi[q] ? uyp - u0 : 0.f;
-          const float qx = fmaf(cc, gx, Pp[l][q][0]);
-          const float qy = fmaf(cc, gy, Pp[l][q][1]);
-          const float qz = Pp[l][q][2];
-          const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
-          const float sc = fminf(1.f, __frsqrt_rn(n2));
-          c3[q][0] = qx * sc;
-          c3[q][1] = qy * sc;
-          c3[q][2] = qz * sc;
-        }
+      for (int q = 0; q < Q; ++q) {
+        Pp[l][q][0] = c3[q][0];
+        Pp[l][q][1] = c3[q][1];
+        Pp[l][q][2] = c3[q][2];
+        Up[l][q] = un[q];
       }
     }
-    // ---- output stage: dual of the last fused step at plane m = zs + s - L ----
-    const int m = zs + s - L;
-    if (m < zs || m >= zl) continue;
+    s_ut[l][par][wv][lane] = un[0];
+  };
+  // Flush of fused step l: dual step at the last plane zl - 1 (no plane above).
+  auto flush = [&](int l, int par, float (&c3)[Q][3]) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const float u0 = Up[l][q];
+      const float uxp = dpp_from_right(u0);
+      const float uyp = (q < Q - 1) ? Up[l][q + 1] : s_ut[l][par ^ 1][wv < NW - 1 ? wv + 1 : wv][lane];
+      const float gx = xhi ? uxp - u0 : 0.f;
+      const float gy = yhi[q] ? uyp - u0 : 0.f;
+      const float qx = fmaf(cc, gx, Pp[l][q][0]);
+      const float qy = fmaf(cc, gy, Pp[l][q][1]);
+      const float qz = Pp[l][q][2];
+      const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
+      const float sc = fminf(1.f, __frsqrt_rn(n2));
+      c3[q][0] = qx * sc;
+      c3[q][1] = qy * sc;
+      c3[q][2] = qz * sc;
+    }
+  };
+  // Output stage: the dual of the last fused step at plane m (stored), or on
+  // the final pass the primal recovery, soft threshold, store and flags.
+  auto output = [&](int m, int par, float (&c3)[Q][3]) {
     const bool zstore = m >= zb && m < ze;
-    if (!A.final_) {
-      if (zstore && ix_store) {
-        float* o0 = A.pout[0] + (size_t)m * sz;
-        float* o1 = A.pout[1] + (size_t)m * sz;
-        float* o2 = A.pout[2] + (size_t)m * sz;
+    if constexpr (!FINAL) {
+      if (zstore) {
+        const __amdgpu_buffer_rsrc_t o0 = plane_rsrc(A.pout[0], m, sz);
+        const __amdgpu_buffer_rsrc_t o1 = plane_rsrc(A.pout[1], m, sz);
+        const __amdgpu_buffer_rsrc_t o2 = plane_rsrc(A.pout[2], m, sz);
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
-          if (!ys[q]) continue;
-          st_(o0, off[q], c3[q][0]);
-          st_(o1, off[q], c3[q][1]);
-          st_(o2, off[q], c3[q][2]);
+          buf_st(o0, offs[q], c3[q][0]);
+          buf_st(o1, offs[q], c3[q][1]);
+          buf_st(o2, offs[q], c3[q][2]);
         }
       }
     } else {
-      // primal recovery u = v + tau div p, soft threshold, store, flags
       s_py[H][par][wv][lane] = c3[Q - 1][1];
       __syncthreads();
-      float* xp = xo + (size_t)m * sz;
+      const __amdgpu_buffer_rsrc_t rx = plane_rsrc(xo, m, sz);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         float u = vring(m, q);
@@ -282,8 +277,8 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         } else {
           xv = copysignf(fmaxf(fabsf(u) - A.thr, 0.f), u);
         }
-        const bool st = zstore && ix_store && ys[q];
-        if (st) st_(xp, off[q], xv);
+        const bool st = zstore && ys[q];
+        if (zstore) buf_st(rx, offs[q], xv);
         if (A.rowflag != nullptr) {
           const bool nzr = __ballot(st && xv != 0.f) != 0;
           if (nzr && lane == 0) {
@@ -293,6 +288,60 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         }
       }
     }
+  };
+
+  // Steady part: plane a1 = zs + s arrives (a1 < zl), every fused step is an
+  // arrival or idle; the planes two ahead are being loaded meanwhile.
+  auto step = [&](int s, InPlane& P) {
+    const int par = s & 1;
+    const int a1 = zs + s;
+    float c3[Q][3];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      vring(a1, q) = P.v[q];
+      c3[q][0] = FIRST ? 0.f : P.p[q][0];
+      c3[q][1] = FIRST ? 0.f : P.p[q][1];
+      c3[q][2] = FIRST ? 0.f : P.p[q][2];
+    }
+    if (a1 + 2 < zl) load_plane(P, a1 + 2);
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+      if (l >= L) break;
+      const int a = a1 - l;
+      if (a < zs) break;                  // this and the later steps are idle
+      arrive(l, a, par, c3);
+    }
+    const int m = a1 - L;
+    if (m >= zs) output(m, par, c3);
+  };
+
+  InPlane PA, PB;
+  load_plane(PA, zs);
+  if (zs + 1 < zl) load_plane(PB, zs + 1);
+  const int s_main = zl - zs;
+  for (int s = 0; s < s_main; s += 2) {
+    step(s, PA);
+    if (s + 1 < s_main) step(s + 1, PB);
+  }
+  // Drain: no plane arrives; fused step l flushes at s = s_main + l.
+  const int nsteps = s_main + L;
+  for (int s = s_main; s < nsteps; ++s) {
+    const int par = s & 1;
+    const int a1 = zs + s;
+    float c3[Q][3];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) c3[q][0] = c3[q][1] = c3[q][2] = 0.f;
+#pragma unroll
+    for (int l = 0; l < H; ++l) {
+      if (l >= L) break;
+      const int a = a1 - l;
+      if (a > zl) continue;               // already flushed
+      if (a < zs) break;
+      if (a == zl) flush(l, par, c3);
+      else arrive(l, a, par, c3);
+    }
+    const int m = a1 - L;
+    if (m >= zs && m < zl) output(m, par, c3);
   }
 }
 
@@ -306,31 +355,56 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
   const int x0 = bx * IX - H, y0 = by * IY - H;
   // interior tile: every point of the region and its +-1 neighbours lie inside
   const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
-  if (A.first) {
-    if (interior) tv_pass_body<H, false, true>(A, bx, by, bz, s_py, s_ut, s_v);
-    else tv_pass_body<H, true, true>(A, bx, by, bz, s_py, s_ut, s_v);
+#define RIHVR_TV_BODY(E, F, FIN) tv_pass_body<H, E, F, FIN>(A, bx, by, bz, s_py, s_ut, s_v)
+  if (A.final_) {
+    if (A.first) {
+      if (interior) RIHVR_TV_BODY(false, true, true);
+      else RIHVR_TV_BODY(true, true, true);
+    } else {
+      if (interior) RIHVR_TV_BODY(false, false, true);
+      else RIHVR_TV_BODY(true, false, true);
+    }
   } else {
-    if (interior) tv_pass_body<H, false, false>(A, bx, by, bz, s_py, s_ut, s_v);
-    else tv_pass_body<H, true, false>(A, bx, by, bz, s_py, s_ut, s_v);
+    if (A.first) {
+      if (interior) RIHVR_TV_BODY(false, true, false);
+      else RIHVR_TV_BODY(true, true, false);
+    } else {
+      if (interior) RIHVR_TV_BODY(false, false, false);
+      else RIHVR_TV_BODY(true, false, false);
+    }
   }
+#undef RIHVR_TV_BODY
 }
 
-// Register budget: the two- and three-deep pipelines fit 128 VGPRs, so LDS
-// (not registers) limits them to two blocks of eight waves per CU; the
-// four-deep one, and the three-deep batched entry (which also holds the frame
-// lookup), keep their full register file.
+// Register budget: the two-deep pipeline fits 128 VGPRs (two blocks of eight
+// waves per CU); the deeper ones, and the batched entry (which also holds the
+// frame lookup), keep their full register file (one block per CU).
 template <int H, bool BATCHED>
-constexpr int tv_min_blocks() { return (H <= 2 || (H == 3 && !BATCHED)) ? 4 : 1; }
+constexpr int tv_min_blocks() { return (H <= 2 && !BATCHED) ? 4 : 1; }
+
+// Workgroups are dispatched round-robin over the 8 XCDs in order of their
+// linear id, and each XCD has its own L2.  Tiles overlap by their halo, so the
+// linear id is mapped to a tile index that gives every XCD one contiguous run
+// of tiles (x fastest): tiles running side by side on an XCD share their halo
+// rows and columns through its L2.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t n) {
+  constexpr uint32_t kXcds = 8;
+  const uint32_t q = n / kXcds, r = n % kXcds;   // XCD k runs q + (k < r) tiles
+  const uint32_t k = id % kXcds, j = id / kXcds;
+  return k * q + min(k, r) + j;
+}
 
 template <int H>
 __global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, false>())) k_tv_pass(TvPassArgs A) {
-  tv_pass_entry<H>(A, blockIdx.x, blockIdx.y, blockIdx.z);
+  const uint32_t n = gridDim.x * gridDim.y * gridDim.z;
+  const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), n);
+  tv_pass_entry<H>(A, t % A.gx, (t / A.gx) % A.gy, t / (A.gx * A.gy));
 }
 
 template <int H>
 __global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, true>())) k_tv_pass_b(const TvPassArgs* __restrict__ args,
                                                                                   BatchMap map) {
-  const uint32_t b = blockIdx.x;
+  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = map.n;  // largest f with offs[f] <= b
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
