@@ -13,7 +13,16 @@ Architecture (channels-last volumes [z][y][x][c]):
     C_{l+1} -> C_l (no activation), concatenation [up, skip] (up first), two
     3x3x3 convolutions + ReLU;
   head: 1x1x1 convolution C_0 -> 1 followed by ReLU (x_0 >= 0).
-Every convolution has a bias.  Loss: mean squared error to the target.
+Every convolution has a bias.  Training loss: weighted mean squared error of
+the head's pre-activation (before the ReLU, which applies at inference) to the
+target.
+
+Storage precision (optional): with store=bf16_round, every activation a
+layer writes (convolution outputs after ReLU, up-convolution outputs) is
+rounded to bfloat16 before the next layer reads it, so that the ReLU masks and
+max-pooling choices are taken on the same stored values as in a network kept
+in bfloat16; the arithmetic stays FP64 and the backward pass treats the
+rounding as the identity.  The head output is not rounded.
 
 Parameters are a dict of arrays:
   conv weights w[kz][ky][kx][cin][cout], bias b[cout];
@@ -25,7 +34,18 @@ from __future__ import annotations
 import numpy as np
 
 __all__ = ["layer_specs", "init_params", "forward", "loss_and_grads", "conv3", "conv3_backward",
-           "maxpool2", "maxpool2_backward", "upconv2", "upconv2_backward"]
+           "maxpool2", "maxpool2_backward", "upconv2", "upconv2_backward", "bf16_round"]
+
+
+def bf16_round(a):
+    """Nearest bfloat16 value (ties to even) of the float32 value of `a`.
+
+    bfloat16 keeps the top 16 bits of an IEEE float32 (sign, 8 exponent bits,
+    7 fraction bits); rounding adds half of the dropped range, plus one when the
+    kept part is odd, before truncating.  Finite inputs only."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
 
 
 def layer_specs(levels: int, base: int):
@@ -139,18 +159,19 @@ def relu(a):
 # ----------------------------------------------------------------------------
 # Network
 # ----------------------------------------------------------------------------
-def forward(params, x, levels, base, keep=False):
-    """x: [D][H][W] input; returns y [D][H][W] (and the activation cache)."""
+def forward(params, x, levels, base, keep=False, store=None):
+    """x: [D][H][W] input; returns y [D][H][W] (and the activation cache).
+    store: optional rounding applied to every stored activation (bf16_round)."""
+    st = store if store is not None else (lambda a: a)
     cache = {}
     h = x[..., None].astype(np.float64)
     skips = []
     for l in range(levels):
-        a = conv3(h, params[f"enc{l}a.w"], params[f"enc{l}a.b"])
-        cache[f"enc{l}a.in"], cache[f"enc{l}a.out"] = h, relu(a)
-        h = relu(a)
-        a = conv3(h, params[f"enc{l}b.w"], params[f"enc{l}b.b"])
-        cache[f"enc{l}b.in"], cache[f"enc{l}b.out"] = h, relu(a)
-        h = relu(a)
+        for s in ("a", "b"):
+            a = conv3(h, params[f"enc{l}{s}.w"], params[f"enc{l}{s}.b"])
+            cache[f"enc{l}{s}.in"] = h
+            h = st(relu(a))
+            cache[f"enc{l}{s}.out"] = h
         if l < levels - 1:
             skips.append(h)
             cache[f"pool{l}.in"] = h
@@ -158,24 +179,29 @@ def forward(params, x, levels, base, keep=False):
             cache[f"pool{l}.idx"] = idx
     for l in range(levels - 2, -1, -1):
         cache[f"up{l}.in"] = h
-        up = upconv2(h, params[f"up{l}.w"], params[f"up{l}.b"])
+        up = st(upconv2(h, params[f"up{l}.w"], params[f"up{l}.b"]))
         h = np.concatenate([up, skips[l]], axis=-1)
         for s in ("a", "b"):
             a = conv3(h, params[f"dec{l}{s}.w"], params[f"dec{l}{s}.b"])
-            cache[f"dec{l}{s}.in"], cache[f"dec{l}{s}.out"] = h, relu(a)
-            h = relu(a)
+            cache[f"dec{l}{s}.in"] = h
+            h = st(relu(a))
+            cache[f"dec{l}{s}.out"] = h
     cache["head.in"] = h
     y = relu(h @ params["head.w"] + params["head.b"])
     cache["head.out"] = y
     return (y, cache) if keep else y
 
 
-def loss_and_grads(params, x, target, levels, base):
-    """MSE loss mean((y - t)^2) and its gradient for every parameter."""
-    y, c = forward(params, x, levels, base, keep=True)
-    n = y.size
-    loss = float(((y - target) ** 2).sum() / n)
-    gy = 2.0 * (y - target) / n * (y > 0)
+def loss_and_grads(params, x, target, levels, base, store=None, pos_weight=1.0):
+    """Weighted MSE loss (1/n) sum w (z - t)^2 of the head's pre-activation z,
+    w = pos_weight where t > 0 and 1 elsewhere, and its gradient for every
+    parameter."""
+    _, c = forward(params, x, levels, base, keep=True, store=store)
+    z = c["head.in"] @ params["head.w"] + params["head.b"]
+    n = z.size
+    w = np.where(target > 0, pos_weight, 1.0)
+    loss = float((w * (z - target) ** 2).sum() / n)
+    gy = 2.0 * w * (z - target) / n
     return loss, _backward(params, c, gy, levels, base)
 
 

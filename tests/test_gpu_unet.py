@@ -1,8 +1,18 @@
 """GPU U-Net (BF16 MFMA kernels) against the FP64 network oracle, through the C ABI.
 
-BF16 activations and weights give ~3 significant digits, so outputs and
-gradients are compared in relative L2 with a 2e-2 bar (3e-2 for weight
-gradients, which sum many BF16 products)."""
+The network stores weights and activations in bfloat16 and accumulates in
+FP32.  The ReLU masks and max-pooling choices are decisions taken on stored
+values, so the oracle is run with the same bfloat16 storage (store=bf16_round:
+FP64 arithmetic, every stored activation rounded); without it a value that
+rounds across zero or changes a pooling winner moves a whole gradient entry.
+Bars (relative L2):
+  output and loss 4e-3 -- about one bfloat16 rounding (2^-8): what remains is
+    FP32 against FP64 accumulation, which moves a stored value by one
+    bfloat16 step only where it lies within ~1e-6 of a rounding boundary;
+  gradients 1.5e-2 -- the kernels also store every back-propagated gradient in
+    bfloat16 (the oracle does not), up to ~4L+2 roundings of 2^-9 on the way
+    to the first layer, with sums over many voxels for biases and weights.
+The plain FP64 network (no storage rounding) is also checked, at 2e-2."""
 import numpy as np
 import pytest
 
@@ -34,8 +44,8 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-@pytest.mark.parametrize("levels", [1, 2, 3])
-def test_unet_forward_and_gradients(torch_cuda, levels):
+@pytest.mark.parametrize("levels,pos_weight", [(1, 1.0), (2, 1.0), (3, 1.0), (2, 6.0)])
+def test_unet_forward_and_gradients(torch_cuda, levels, pos_weight):
     torch = torch_cuda
     base = 8
     rng = np.random.default_rng(levels)
@@ -47,22 +57,24 @@ def test_unet_forward_and_gradients(torch_cuda, levels):
     x = rng.standard_normal((D, H, W))
     x = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     target = np.maximum(rng.standard_normal((D, H, W)), 0.0)
-    y_ref = ou.forward(p, x, levels, base)
-    loss_ref, g_ref = ou.loss_and_grads(p, x, target, levels, base)
+    y_fp64 = ou.forward(p, x, levels, base)
+    y_ref = ou.forward(p, x, levels, base, store=ou.bf16_round)
+    loss_ref, g_ref = ou.loss_and_grads(p, x, target, levels, base, store=ou.bf16_round, pos_weight=pos_weight)
 
     net = rihvr.UNet(levels, base, seed=1)
     assert net.n == flat(p, levels, base).size
     net.params.copy_(torch.tensor(flat(p, levels, base), dtype=torch.float32))
     xin = torch.tensor(x, dtype=torch.float32).cuda()
     y = net.forward(xin).cpu().numpy()
-    assert rel(y, y_ref) <= 2e-2, rel(y, y_ref)
-    loss = net.train_step(xin, torch.tensor(target, dtype=torch.float32).cuda(), lr=0.0)
-    assert float(loss) == pytest.approx(loss_ref, rel=2e-2)
+    assert rel(y, y_fp64) <= 2e-2, rel(y, y_fp64)
+    assert rel(y, y_ref) <= 4e-3, rel(y, y_ref)
+    loss = net.train_step(xin, torch.tensor(target, dtype=torch.float32).cuda(), lr=0.0, pos_weight=pos_weight)
+    assert float(loss) == pytest.approx(loss_ref, rel=4e-3)
     g = unflat(net.grads.cpu().numpy().astype(np.float64), levels, base, p)
-    for k in g_ref:
-        if np.linalg.norm(g_ref[k]) == 0:
-            continue
-        assert rel(g[k], g_ref[k]) <= 3e-2, (k, rel(g[k], g_ref[k]))
+    errs = {k: rel(g[k], g_ref[k]) for k in g_ref if np.linalg.norm(g_ref[k]) > 0}
+    print("gradient errors:", {k: round(v, 5) for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= 1.5e-2, (k, e)
 
 
 def test_unet_training_reduces_loss(torch_cuda):
@@ -72,11 +84,20 @@ def test_unet_training_reduces_loss(torch_cuda):
     x = torch.tensor(rng.standard_normal((D, H, W)), dtype=torch.float32).cuda()
     t = torch.relu(x * 0.5).contiguous()
     net = rihvr.UNet(3, 8, seed=2)
-    losses = [float(net.train_step(x, t, lr=3e-3)) for _ in range(60)]
-    assert losses[-1] < 0.3 * losses[0], (losses[0], losses[-1])
+    losses = [float(net.train_step(x, t, lr=3e-3)) for _ in range(200)]
+    # the target relu(x / 2) is within reach of the network: the loss falls well
+    # below that of the initial output (the head starts at zero weights)
+    assert losses[-1] < 0.2 * losses[0], (losses[0], losses[-1])
+    assert np.mean(losses[-10:]) < 0.2 * losses[0]
 
 
 def test_unet_rejects_bad_shapes(torch_cuda):
+    torch = torch_cuda
+    net = rihvr.UNet(2, 8, seed=0)
+    z = torch.zeros((8, 8, 8), dtype=torch.float32, device="cuda")
+    for pw in (0.0, -1.0, float("inf")):
+        with pytest.raises(rihvr.RihvrError):
+            net.train_step(z, z, lr=0.0, pos_weight=pw)
     cfg = rihvr.ri_unet_config(4, 16)
     with pytest.raises(rihvr.RihvrError):
         rihvr.ri_unet_workspace_size(cfg, 12, 16, 16, 0)

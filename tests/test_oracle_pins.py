@@ -390,15 +390,15 @@ def test_unet_layers_brute_force():
         assert up[z, yy, xx, co] == pytest.approx(q @ u[z % 2, yy % 2, xx % 2, :, co] + bu[co], abs=1e-12)
 
 
-@pytest.mark.parametrize("levels", [2, 3])
-def test_unet_gradients_finite_differences(levels):
+@pytest.mark.parametrize("levels,pos_weight", [(2, 1.0), (3, 1.0), (2, 7.0)])
+def test_unet_gradients_finite_differences(levels, pos_weight):
     from oracle import unet as ou
     rng = np.random.default_rng(21 + levels)
     base = 4
     p = ou.init_params(levels, base, rng)
     x = rng.standard_normal((8, 8, 8))
     t = np.maximum(rng.standard_normal((8, 8, 8)), 0.0)
-    _, g = ou.loss_and_grads(p, x, t, levels, base)
+    _, g = ou.loss_and_grads(p, x, t, levels, base, pos_weight=pos_weight)
     worst = 0.0
     for k in p:
         flatp = p[k].reshape(-1)
@@ -406,12 +406,68 @@ def test_unet_gradients_finite_differences(levels):
             old = flatp[i]
             e = 1e-6
             flatp[i] = old + e
-            lp = ou.loss_and_grads(p, x, t, levels, base)[0]
+            lp = ou.loss_and_grads(p, x, t, levels, base, pos_weight=pos_weight)[0]
             flatp[i] = old - e
-            lm = ou.loss_and_grads(p, x, t, levels, base)[0]
+            lm = ou.loss_and_grads(p, x, t, levels, base, pos_weight=pos_weight)[0]
             flatp[i] = old
             fd = (lp - lm) / (2 * e)
             an = g[k].reshape(-1)[i]
             # central differences with e = 1e-6 carry ~1e-10 of cancellation error
             worst = max(worst, abs(fd - an) / (1e-8 + 1e-5 * abs(an)))
     assert worst <= 1.0, worst
+
+
+def test_bf16_round_is_round_to_nearest_even():
+    """The oracle's bfloat16 rounding against torch's float32 -> bfloat16
+    conversion (round to nearest, ties to even), including exact ties."""
+    import torch
+    from oracle import unet as ou
+    rng = np.random.default_rng(22)
+    a = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.integers(-20, 20, 4000),
+                        [0.0, -0.0, 1.0, -1.0, 3.0e38, 1.0e-38]]).astype(np.float32)
+    # exact ties: kept part even (rounds down) and odd (rounds up)
+    ties = (rng.integers(1 << 20, 1 << 30, 200, dtype=np.uint32) & 0xFFFF0000) | 0x8000
+    a = np.concatenate([a, ties.view(np.float32)])
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float64).numpy()
+    got = ou.bf16_round(a)
+    assert np.array_equal(got, ref)
+    assert np.array_equal(ou.bf16_round(got), got)
+    nz = np.abs(a) >= np.finfo(np.float32).tiny   # normal numbers: relative error <= 2^-8
+    assert np.max(np.abs(got[nz] - a[nz]) / np.abs(a[nz])) <= 2.0 ** -8
+
+
+def test_unet_bf16_storage_rounds_every_stored_activation():
+    from oracle import unet as ou
+    rng = np.random.default_rng(23)
+    levels, base = 3, 4
+    p = ou.init_params(levels, base, rng)
+    x = rng.standard_normal((8, 8, 8))
+    y0 = ou.forward(p, x, levels, base)
+    assert np.array_equal(ou.forward(p, x, levels, base, store=lambda a: a), y0)
+    y, c = ou.forward(p, x, levels, base, keep=True, store=ou.bf16_round)
+    for k, v in c.items():
+        if k.endswith(".out") and k != "head.out":
+            assert np.array_equal(ou.bf16_round(v), v), k
+    for l in range(levels - 1):
+        assert np.array_equal(ou.bf16_round(c[f"up{l}.in"]), c[f"up{l}.in"])
+    # storage in bfloat16 perturbs the output by about its unit roundoff, not more
+    assert np.linalg.norm(y - y0) <= 2e-2 * np.linalg.norm(y0)
+
+
+def test_unet_weighted_loss_definition():
+    """The weighted loss against its definition written out voxel by voxel."""
+    from oracle import unet as ou
+    rng = np.random.default_rng(24)
+    p = ou.init_params(1, 4, rng)
+    x = rng.standard_normal((4, 4, 4))
+    t = np.maximum(rng.standard_normal((4, 4, 4)), 0.0)
+    p["head.b"] = np.array(-0.3)   # some pre-activations below zero
+    y, c = ou.forward(p, x, 1, 4, keep=True)
+    z = np.zeros(t.shape)
+    for i in np.ndindex(t.shape):
+        z[i] = sum(c["head.in"][i][k] * p["head.w"][k] for k in range(4)) + p["head.b"]
+    assert np.array_equal(y, np.maximum(z, 0.0)) or np.allclose(y, np.maximum(z, 0.0), rtol=0, atol=1e-15)
+    assert (z < 0).any()
+    want = sum((3.0 if t[i] > 0 else 1.0) * (z[i] - t[i]) ** 2 for i in np.ndindex(t.shape)) / t.size
+    assert ou.loss_and_grads(p, x, t, 1, 4, pos_weight=3.0)[0] == pytest.approx(want, rel=1e-12)
+    assert ou.loss_and_grads(p, x, t, 1, 4)[0] == pytest.approx(float(((z - t) ** 2).mean()), rel=1e-12)
