@@ -268,7 +268,8 @@ typedef struct {
 } ri_unet_config;
 
 ri_status ri_unet_param_count(const ri_unet_config* cfg, size_t* count);
-/* He-normal weights from a seeded generator, biases 0.01 (synchronous). */
+/* He-normal weights from a seeded generator, biases 0.01; the head's weights
+ * start at zero.  Synchronous. */
 ri_status ri_unet_init_params(const ri_unet_config* cfg, uint64_t seed, float* params, void* stream);
 ri_status ri_unet_workspace_size(const ri_unet_config* cfg, int32_t d, int32_t h, int32_t w, int32_t training,
                                  size_t* bytes);
@@ -276,14 +277,19 @@ ri_status ri_unet_workspace_size(const ri_unet_config* cfg, int32_t d, int32_t h
 ri_status ri_unet_forward(const ri_unet_config* cfg, const float* params, const float* in, float scale, float* out,
                           int32_t d, int32_t h, int32_t w, void* ws, size_t ws_bytes, void* stream);
 /*
- * One training step on one volume: forward, mean-squared-error loss against
- * `target` (written to *loss_out, a device float, if non-NULL), backward into
- * `grads`, then, if lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8, bias
- * correction with `step` >= 1) of params, adam_m, adam_v.
+ * One training step on one volume: forward, weighted mean-squared-error loss
+ * (1/n) sum_v w_v (z_v - target_v)^2 on the head's pre-activation z (the
+ * final ReLU applies at inference only, so voxels below zero still learn),
+ * with w_v = pos_weight where target_v > 0 and 1 elsewhere (sparse targets;
+ * pos_weight = 1 is the plain MSE; must be finite and > 0), written to
+ * *loss_out (a device float) if non-NULL; backward into `grads`; then, if
+ * lr > 0, an Adam update (beta 0.9 / 0.999, eps 1e-8, bias correction with
+ * `step` >= 1) of params, adam_m, adam_v.
  */
 ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params, float* grads, float* adam_m, float* adam_v,
-                             int32_t step, float lr, const float* in, float scale, const float* target, int32_t d,
-                             int32_t h, int32_t w, float* loss_out, void* ws, size_t ws_bytes, void* stream);
+                             int32_t step, float lr, const float* in, float scale, const float* target,
+                             float pos_weight, int32_t d, int32_t h, int32_t w, float* loss_out, void* ws,
+                             size_t ws_bytes, void* stream);
 
 const char* ri_status_string(ri_status status);
 const char* ri_last_error(void);

@@ -280,9 +280,11 @@ ri_status forward(const Net& n, const float* params, const float* in, float scal
                                  params + db.b, 1, dbo, c, 0), s));
     h = dbo;
   }
+  // head: ReLU output for inference; training keeps the pre-activation (the
+  // loss is taken on it, so a voxel below zero still passes gradient)
   const Layer& hd = n.layers[n.head()];
   UTRY(launch_gather_gemm(gemm(GG_POINT, D, H, W, h, n.ch[0], 0, 1, hd.f_c, pk + hd.pf, 1, hd.f_npad, params + hd.b,
-                               1, at<float>(ws, B.y), 1, 0, 1), s));
+                               train ? 0 : 1, at<float>(ws, B.y), 1, 0, 1), s));
   return RI_OK;
 }
 
@@ -298,15 +300,15 @@ WgradArgs wg(int mode, int D, int H, int W, const uint16_t* g, int gcs, int gc0,
   return w;
 }
 
-ri_status backward(const Net& n, const float* params, const float* target, float* grads, int D, int H, int W,
-                   void* ws, const Buffers& B, hipStream_t s) {
+ri_status backward(const Net& n, const float* params, const float* target, float pos_weight, float* grads, int D,
+                   int H, int W, void* ws, const Buffers& B, hipStream_t s) {
   const int L = n.L;
   uint16_t* pk = at<uint16_t>(ws, B.packed);
   const long nv0 = (long)D * H * W;
   uint16_t* gy8 = at<uint16_t>(ws, B.gy8);
   UTRY(launch_zero_u16(gy8, (size_t)nv0 * 8, s));
   UTRY(hipMemsetAsync(at<float>(ws, B.loss), 0, sizeof(float), s));
-  UTRY(launch_mse(at<float>(ws, B.y), target, nv0, gy8, 8, at<float>(ws, B.loss), s));
+  UTRY(launch_mse(at<float>(ws, B.y), target, nv0, pos_weight, gy8, 8, at<float>(ws, B.loss), s));
   // head
   const Layer& hd = n.layers[n.head()];
   const uint16_t* top = L > 1 ? at<uint16_t>(ws, B.db[0]) : at<uint16_t>(ws, B.bbot);
@@ -410,7 +412,9 @@ extern "C" ri_status ri_unet_init_params(const ri_unet_config* cfg, uint64_t see
   for (const Layer& y : n.layers) {
     const size_t wsz = y.b - y.w;
     const double sd = y.kind == CONV ? std::sqrt(2.0 / (27.0 * y.cin)) : std::sqrt(1.0 / y.cin);
-    for (size_t i = 0; i < wsz; ++i) h[y.w + i] = (float)(sd * r.normal());
+    const bool head = &y == &n.layers[n.head()];
+    // the head starts at zero weights: the first output is the bias everywhere
+    for (size_t i = 0; i < wsz; ++i) h[y.w + i] = head ? 0.f : (float)(sd * r.normal());
     for (int i = 0; i < y.cout; ++i) h[y.b + i] = 0.01f;
   }
   UTRY(hipMemcpyAsync(params, h.data(), h.size() * sizeof(float), hipMemcpyHostToDevice, (hipStream_t)stream));
@@ -449,8 +453,8 @@ extern "C" ri_status ri_unet_forward(const ri_unet_config* cfg, const float* par
 
 extern "C" ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params, float* grads, float* adam_m,
                                         float* adam_v, int32_t step, float lr, const float* in, float scale,
-                                        const float* target, int32_t d, int32_t h, int32_t w, float* loss_out,
-                                        void* ws, size_t ws_bytes, void* stream) {
+                                        const float* target, float pos_weight, int32_t d, int32_t h, int32_t w,
+                                        float* loss_out, void* ws, size_t ws_bytes, void* stream) {
   ri_status st = check_cfg(cfg);
   if (st != RI_OK) return st;
   st = check_dims(cfg, d, h, w);
@@ -458,6 +462,8 @@ extern "C" ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params
   if (!params || !grads || !in || !target || !ws || (lr > 0 && (!adam_m || !adam_v)))
     return set_error(RI_ERR_INVALID_ARG, "NULL pointer");
   if (lr > 0 && step < 1) return set_error(RI_ERR_INVALID_ARG, "Adam step must be >= 1");
+  if (!(pos_weight > 0.f) || !std::isfinite(pos_weight))
+    return set_error(RI_ERR_INVALID_ARG, "pos_weight must be finite and > 0");
   const Net n = build_net(cfg->levels, cfg->base);
   const Buffers B = layout(n, d, h, w, true);
   if (ws_bytes < B.total) return set_error(RI_ERR_WORKSPACE_TOO_SMALL, "unet workspace too small");
@@ -465,7 +471,7 @@ extern "C" ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params
   UTRY(hipMemsetAsync(grads, 0, n.nparams * sizeof(float), s));
   st = forward(n, params, in, scale, d, h, w, ws, B, true, s);
   if (st != RI_OK) return st;
-  st = backward(n, params, target, grads, d, h, w, ws, B, s);
+  st = backward(n, params, target, pos_weight, grads, d, h, w, ws, B, s);
   if (st != RI_OK) return st;
   if (loss_out) UTRY(hipMemcpyAsync(loss_out, at<float>(ws, B.loss), sizeof(float), hipMemcpyDeviceToDevice, s));
   if (lr > 0) UTRY(launch_adam(params, grads, adam_m, adam_v, n.nparams, lr, 0.9f, 0.999f, 1e-8f, step, s));

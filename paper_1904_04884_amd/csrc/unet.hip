@@ -293,14 +293,17 @@ __global__ void k_input(const float* in, float scale, uint16_t* x, int cs, long 
   }
 }
 
-// MSE loss of y (FP32) against t; gradient 2 (y - t) / n * (y > 0) into g[v][0]
-__global__ void k_mse(const float* y, const float* t, long n, float inv_n, uint16_t* g, int gcs, float* loss) {
+// Weighted MSE of the head's pre-activation y (FP32) against t, weight pos_w
+// where t > 0 and 1 elsewhere; gradient 2 w (y - t) / n into g[v][0]
+__global__ void k_mse(const float* y, const float* t, long n, float inv_n, float pos_w, uint16_t* g, int gcs,
+                      float* loss) {
   __shared__ float red[4];
   float s = 0.f;
   for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < n; v += (long)gridDim.x * blockDim.x) {
     const float d = y[v] - t[v];
-    s += d * d;
-    g[(size_t)v * gcs] = f2bf(y[v] > 0.f ? 2.f * d * inv_n : 0.f);
+    const float w = t[v] > 0.f ? pos_w : 1.f;
+    s += w * d * d;
+    g[(size_t)v * gcs] = f2bf(2.f * w * d * inv_n);
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
@@ -422,8 +425,9 @@ hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long 
   return hipGetLastError();
 }
 
-hipError_t launch_mse(const float* y, const float* t, long n, uint16_t* g, int gcs, float* loss, hipStream_t s) {
-  hipLaunchKernelGGL(k_mse, dim3(ew_grid(n)), dim3(256), 0, s, y, t, n, 1.f / (float)n, g, gcs, loss);
+hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint16_t* g, int gcs, float* loss,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_mse, dim3(ew_grid(n)), dim3(256), 0, s, y, t, n, 1.f / (float)n, pos_w, g, gcs, loss);
   return hipGetLastError();
 }
 

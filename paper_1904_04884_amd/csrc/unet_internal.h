@@ -53,7 +53,8 @@ hipError_t launch_relu_mask(uint16_t* g, int gcs, int gc0, const uint16_t* y, in
                             hipStream_t s);
 hipError_t launch_zero_u16(uint16_t* p, size_t n, hipStream_t s);
 hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long nvox, hipStream_t s);
-hipError_t launch_mse(const float* y, const float* t, long n, uint16_t* g, int gcs, float* loss, hipStream_t s);
+hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint16_t* g, int gcs, float* loss,
+                      hipStream_t s);
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
                        int step, hipStream_t s);
 hipError_t launch_pack(const float* w, int T, int cin, int cout, int transpose, int Npad, int Cpad, uint16_t* out,

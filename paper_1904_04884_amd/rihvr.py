@@ -144,7 +144,7 @@ def lib():
     L.ri_unet_init_params.argtypes = [cfgp, C.c_uint64, vp, vp]
     L.ri_unet_workspace_size.argtypes = [cfgp, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.POINTER(sz)]
     L.ri_unet_forward.argtypes = [cfgp, vp, vp, fp, vp, C.c_int32, C.c_int32, C.c_int32, vp, sz, vp]
-    L.ri_unet_train_step.argtypes = [cfgp, vp, vp, vp, vp, C.c_int32, fp, vp, fp, vp, C.c_int32, C.c_int32,
+    L.ri_unet_train_step.argtypes = [cfgp, vp, vp, vp, vp, C.c_int32, fp, vp, fp, vp, fp, C.c_int32, C.c_int32,
                                      C.c_int32, vp, vp, sz, vp]
     L.ri_status_string.argtypes = [C.c_int]
     L.ri_status_string.restype = C.c_char_p
@@ -257,10 +257,10 @@ def ri_unet_forward(cfg, params, inp, scale, out, d, h, w, ws, ws_bytes, stream)
     return lib().ri_unet_forward(C.byref(cfg), params, inp, scale, out, d, h, w, ws, ws_bytes, stream)
 
 
-def ri_unet_train_step(cfg, params, grads, m, v, step, lr, inp, scale, target, d, h, w, loss, ws, ws_bytes,
-                       stream) -> int:
-    return lib().ri_unet_train_step(C.byref(cfg), params, grads, m, v, step, lr, inp, scale, target, d, h, w,
-                                    loss, ws, ws_bytes, stream)
+def ri_unet_train_step(cfg, params, grads, m, v, step, lr, inp, scale, target, pos_weight, d, h, w, loss, ws,
+                       ws_bytes, stream) -> int:
+    return lib().ri_unet_train_step(C.byref(cfg), params, grads, m, v, step, lr, inp, scale, target, pos_weight,
+                                    d, h, w, loss, ws, ws_bytes, stream)
 
 
 def ri_status_string(status: int) -> str:
@@ -434,7 +434,7 @@ class UNet:
                                d, h, w, ws.data_ptr(), ws.numel(), _stream_handle(torch)), "ri_unet_forward")
         return out
 
-    def train_step(self, inp, target, lr=1e-3, scale=1.0):
+    def train_step(self, inp, target, lr=1e-3, scale=1.0, pos_weight=1.0):
         torch = self.torch
         d, h, w = inp.shape
         ws = self._workspace(d, h, w, True)
@@ -443,6 +443,7 @@ class UNet:
             self.step += 1
         _check(ri_unet_train_step(self.cfg, self.params.data_ptr(), self.grads.data_ptr(), self.m.data_ptr(),
                                   self.v.data_ptr(), max(self.step, 1), float(lr), inp.data_ptr(), float(scale),
-                                  target.data_ptr(), d, h, w, loss.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  target.data_ptr(), float(pos_weight), d, h, w, loss.data_ptr(), ws.data_ptr(),
+                                  ws.numel(),
                                   _stream_handle(torch)), "ri_unet_train_step")
         return loss

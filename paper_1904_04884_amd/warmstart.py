@@ -1,14 +1,28 @@
 """Learned warm start for the FISTA solve.
 
 A 3D U-Net (ri_unet_*, BF16 matrix-core kernels) maps the back-propagated
-hologram A^T b, scaled by 1/||A||^2, to a proposed starting volume x_0 >= 0.
+hologram A^T b, scaled to unit RMS over the training set, to a proposed
+starting volume x_0 >= 0.
 Training pairs come from the library's own solver: for each seeded scene the
-hologram b and the volume the plain solver reaches from a cold start.  At solve
-time the proposal is kept only if its objective is below F(0) (else the solve
-starts cold), so the FISTA objective always decides the result.
+hologram b and the volume the plain solver reaches from a cold start.
 
-torch supplies device memory, the RNG for crop positions and tensor slicing
-for crops; every computation (A^T, the network, the solve) runs in librihvr.
+At solve time the proposal x_1 is rescaled to the best multiple s x_1 of
+itself: F(s x) is a convex quadratic in s >= 0 (the l1 and TV terms are
+positively homogeneous), so F(0), F(x_1) and F(2 x_1) -- three zero-iteration
+solves -- give s* = argmin F(s x_1).  The head is linear before its ReLU, so
+s x_1 is the network output with the head's weights and bias scaled by s.  The
+proposal is kept only if its objective is below F(0) (else the solve starts
+cold), so the FISTA objective always decides the result.
+
+Normalisation: the network sees A^T b * in_scale (in_scale = 1 / RMS of the
+training inputs) and is trained against targets * t_scale (t_scale = 1 / the
+largest target value), so that activations and outputs are O(1) in bfloat16;
+after training 1/t_scale is folded into the head's weights and bias (the head
+is linear before its ReLU), so a proposal is one ri_unet_forward call.
+
+torch supplies device memory, the RNG for crop positions, tensor slicing for
+crops and the two normalisation constants of the training data; every
+computation on the solve path (A^T, the network, the solve) runs in librihvr.
 """
 from __future__ import annotations
 
@@ -33,20 +47,37 @@ class WarmStart:
         self.plan = plan
         self.net = rihvr.UNet(levels, base, seed=seed)
         self.levels = levels
-        self.scale = 1.0 / plan.lipschitz
+        self.base = base
+        self.scale = None       # in_scale, set by the first train()
+        self.t_scale = 1.0      # folded into the head after train()
+        self._folded = False
 
     # -- data --------------------------------------------------------------
     def network_input(self, b):
-        """A^T b / ||A||^2 (the input the network sees, before its own scale)."""
+        """A^T b (the network multiplies it by in_scale)."""
         return self.plan.adjoint(b)
+
+    def _head(self):
+        n = self.base + 1  # head weights (one per first-level channel) and bias, last in the vector
+        return self.net.params[self.net.n - n:]
+
+    def _fold(self, on: bool):
+        if on != self._folded and self.t_scale != 1.0:
+            self._head().mul_(1.0 / self.t_scale if on else self.t_scale)
+        self._folded = on
 
     def make_pair(self, b, l1, tv, iters, inner):
         x, rep, _ = self.plan.solve(b, l1, tv, iters, inner)
         return Pair(b, x), rep
 
     # -- training ----------------------------------------------------------
-    def train(self, pairs, steps, crop=(32, 64, 64), lr=1e-3, seed=0, log_every=0):
-        """Adam on random crops of (A^T b / ||A||^2, solved x) pairs; returns the loss curve."""
+    def train(self, pairs, steps, crop=(32, 64, 64), lr=1e-3, seed=0, log_every=0, pos_weight=None):
+        """Adam on random crops of (A^T b, solved x) pairs; returns the loss curve.
+
+        The solved volumes are sparse (a few percent of voxels non-zero), so the
+        loss weights those voxels by pos_weight (default: 0.5 / the non-zero
+        fraction, within [1, 50]) to keep the all-zero output from being a
+        good minimum."""
         torch = self.torch
         g = torch.Generator().manual_seed(seed)
         nz, ny, nx = self.plan.shape
@@ -54,6 +85,15 @@ class WarmStart:
         m = 1 << (self.levels - 1)
         cz, cy, cx = cz // m * m, cy // m * m, cx // m * m
         inputs = [self.network_input(p.b) for p in pairs]
+        if self.scale is None:
+            ms = sum(float((t.double() ** 2).mean()) for t in inputs) / len(inputs)
+            self.scale = 1.0 / math.sqrt(max(ms, 1e-300))
+            self.t_scale = 1.0 / max(max(float(p.target.max()) for p in pairs), 1e-30)
+        if pos_weight is None:
+            rho = sum(float((p.target > 0).double().mean()) for p in pairs) / len(pairs)
+            pos_weight = min(50.0, max(1.0, 0.5 / max(rho, 1e-6)))
+        self.pos_weight = pos_weight
+        self._fold(False)
         losses = []
         for it in range(steps):
             k = int(torch.randint(len(pairs), (1,), generator=g))
@@ -61,22 +101,52 @@ class WarmStart:
             y0 = int(torch.randint(ny - cy + 1, (1,), generator=g))
             x0 = int(torch.randint(nx - cx + 1, (1,), generator=g))
             xi = inputs[k][z0:z0 + cz, y0:y0 + cy, x0:x0 + cx].contiguous()
-            ti = pairs[k].target[z0:z0 + cz, y0:y0 + cy, x0:x0 + cx].contiguous()
-            loss = self.net.train_step(xi, ti, lr=lr, scale=self.scale)
+            ti = (pairs[k].target[z0:z0 + cz, y0:y0 + cy, x0:x0 + cx] * self.t_scale).contiguous()
+            loss = self.net.train_step(xi, ti, lr=lr, scale=self.scale, pos_weight=pos_weight)
             if log_every and (it % log_every == 0 or it == steps - 1):
                 losses.append((it, float(loss)))
+        self._fold(True)
         return losses
 
     # -- use ---------------------------------------------------------------
-    def propose(self, b):
-        return self.net.forward(self.network_input(b), scale=self.scale)
+    def _forward(self, inp, head_scale=1.0):
+        if head_scale != 1.0:
+            self._head().mul_(head_scale)
+        try:
+            return self.net.forward(inp, scale=self.scale)
+        finally:
+            if head_scale != 1.0:
+                self._head().mul_(1.0 / head_scale)
+
+    def _objective(self, b, l1, tv, inner, x=None):
+        """F(x) (F(0) when x is None) from a zero-iteration solve."""
+        return self.plan.solve(b, l1, tv, 0, inner, x=None if x is None else x.clone())[1]["objective"]
+
+    def propose(self, b, l1=None, tv=None, inner=None):
+        """The network's x_0 for hologram b; with the solve's weights, rescaled to
+        minimise F along its ray.  Returns (x_0 or None, F(0), F(x_0))."""
+        if self.scale is None:
+            raise RuntimeError("WarmStart.propose before train()")
+        self._fold(True)
+        inp = self.network_input(b)
+        x1 = self._forward(inp)
+        if l1 is None:
+            return x1, math.nan, math.nan
+        f0 = self._objective(b, l1, tv, inner)
+        f1 = self._objective(b, l1, tv, inner, x1)
+        f2 = self._objective(b, l1, tv, inner, self._forward(inp, 2.0))
+        a = f2 - 2.0 * f1 + f0          # ||A x_1||^2
+        c = 0.5 * a - (f1 - f0)         # <A x_1, b> - l1 sum(x_1) - tv TV(x_1)
+        if not (math.isfinite(a) and math.isfinite(c) and a > 0.0 and c > 0.0):
+            return None, f0, math.inf
+        s = c / a
+        x = self._forward(inp, s)
+        return x, f0, self._objective(b, l1, tv, inner, x)
 
     def solve(self, b, l1, tv, max_iters, inner, f_ref=0.0, gap_tol=0.0, check_every=5, flags=0):
         """Warm-started solve with the cold-start fallback.  Returns (x, report, used_warm)."""
-        x0 = self.propose(b)
-        _, r0, _ = self.plan.solve(b, l1, tv, 0, inner, x=x0.clone())
-        f_zero = 0.5 * float((b.double() ** 2).sum())
-        warm = r0["objective"] < f_zero and math.isfinite(r0["objective"])
+        x0, f0, fx = self.propose(b, l1, tv, inner)
+        warm = x0 is not None and math.isfinite(fx) and fx < f0
         x, rep, st = self.plan.solve(b, l1, tv, max_iters, inner, x=x0 if warm else None, f_ref=f_ref,
                                      gap_tol=gap_tol, check_every=check_every, flags=flags)
         return x, rep, warm

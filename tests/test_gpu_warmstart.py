@@ -1,7 +1,7 @@
 """The learned warm start against the plain (cold) solve on held-out scenes.
 
 Pairs come from the library's own solver on seeded C1-optics scenes; a small
-U-Net is trained on crops on the GPU; held-out scenes are solved to a
+U-Net is trained on the whole volumes on the GPU; held-out scenes are solved to a
 relative objective gap from a cold start and from the network's proposal.
 The test records both iteration counts and requires the warm start to need
 fewer iterations on average (the objective decides; the fallback keeps any
@@ -32,7 +32,7 @@ def test_warm_start_gains_over_cold(torch_cuda):
             sc = scenes.scene_c1(seed=seed, n_particles=int(np.random.default_rng(seed).integers(30, 80)))
             p, _ = ws.make_pair(hologram(torch, plan, sc), cfg.l1, cfg.tv, 150, cfg.inner_iters)
             pairs.append(p)
-        curve = ws.train(pairs, steps=400, crop=(32, 64, 64), lr=2e-3, log_every=100)
+        curve = ws.train(pairs, steps=500, crop=(32, 128, 128), lr=2e-3, log_every=100)
         assert curve[-1][1] < curve[0][1]
         cold, warm, used = [], [], []
         for seed in range(9000, 9004):
