@@ -100,7 +100,7 @@ __device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int 
   float2* buf = lds[r];
   if (a.mode != 1) {
     const float* xin = a.x;
-    if (a.mode == 2) xin = a.xs[a.st->it % 3];   // solver iterate, before the scalar kernel
+    if (a.mode == 2) xin = pick3(a.xs[0], a.xs[1], a.xs[2], a.st->it % 3);   // solver iterate, before the scalar kernel
     const float2* src = reinterpret_cast<const float2*>(xin) + (size_t)row * M;
 #pragma unroll
     for (int s = 0; s < P; ++s) {
@@ -406,9 +406,8 @@ __device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int 
     return;
   }
   const SolveState* st = a.st;
-  float* xs[3] = {a.x0, a.x1, a.x2};
-  const float2* xc = reinterpret_cast<const float2*>(xs[st->cur]) + (size_t)row * M;
-  float2* xp = reinterpret_cast<float2*>(xs[st->prev]) + (size_t)row * M;
+  const float2* xc = reinterpret_cast<const float2*>(pick3(a.x0, a.x1, a.x2, st->cur)) + (size_t)row * M;
+  float2* xp = reinterpret_cast<float2*>(pick3(a.x0, a.x1, a.x2, st->prev)) + (size_t)row * M;
   const float beta = (float)st->beta;
   const float gs = (float)(a.step * (double)a.scale);
 #pragma unroll
@@ -440,8 +439,7 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
   const float* x = a.x0;
   if (a.st != nullptr) {
     // runs before the scalar kernel of the iteration: the iterate is slot it % 3
-    const float* xs[3] = {a.x0, a.x1, a.x2};
-    x = xs[a.st->it % 3];
+    x = pick3(a.x0, a.x1, a.x2, a.st->it % 3);
   }
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long nrows = (long)ny * nz;
@@ -586,8 +584,7 @@ __global__ void k_copy_f32(float* d, const float* s, size_t n) {
 }
 __global__ void k_copy_final(const float* x0, const float* x1, const float* x2, float* dst, size_t n,
                              const SolveState* st) {
-  const float* xs[3] = {x0, x1, x2};
-  const float* src = xs[st->cur];
+  const float* src = pick3(x0, x1, x2, st->cur);
   if (src == dst) return;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) dst[i] = src[i];
 }

@@ -9,6 +9,25 @@
 
 namespace rihvr {
 
+// A pointer known to be the same in every lane (keeps address bases in SGPRs).
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const uint64_t u = reinterpret_cast<uint64_t>(p);
+  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
+  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
+  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
+}
+
+// One of three buffers by a runtime slot index, chosen by selects among values
+// already read (an indexed local array would be placed in scratch memory).
+template <class T>
+__device__ __forceinline__ T* pick3(T* a, T* b, T* c, int i) {
+  a = uniform_ptr(a);
+  b = uniform_ptr(b);
+  c = uniform_ptr(c);
+  return i == 0 ? a : (i == 1 ? b : c);
+}
+
 // Solver state that lives in device memory for the duration of a solve.  All
 // control decisions (momentum, stop, buffer rotation) are taken on the device
 // so that one iteration can be replayed as a HIP graph.

@@ -35,7 +35,7 @@
 
 namespace rihvr {
 
-constexpr int kTvWaves = 8;
+constexpr int kTvWaves = 12;
 constexpr int kTvQ = 4;                 // rows per lane
 constexpr int kTvRX = 64;               // tile width (lanes)
 constexpr int kTvRY = kTvWaves * kTvQ;  // tile height
@@ -61,15 +61,6 @@ __device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-
 }
 __device__ __forceinline__ float dpp_from_right(float v) {  // lane i <- lane i+1 (0 at lane 63)
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x130, 0xf, 0xf, true));
-}
-
-// A pointer known to be the same in every lane (keeps address bases in SGPRs).
-template <class T>
-__device__ __forceinline__ T* uniform_ptr(T* p) {
-  const uint64_t u = reinterpret_cast<uint64_t>(p);
-  const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)u);
-  const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(u >> 32));
-  return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
 // Planes are addressed through buffer resources: a scalar descriptor of one
@@ -100,8 +91,8 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
                                              float* s_v) {
   constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
-  const float* __restrict__ v = uniform_ptr(A.v ? A.v : A.vol[A.st->prev]);
-  float* __restrict__ xo = uniform_ptr(A.x ? A.x : A.vol[A.st->next]);
+  const float* __restrict__ v = uniform_ptr(A.v ? A.v : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->prev));
+  float* __restrict__ xo = uniform_ptr(A.x ? A.x : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->next));
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int x = bx * IX - H + lane;
@@ -380,7 +371,7 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
 // waves per CU); the deeper ones, and the batched entry (which also holds the
 // frame lookup), keep their full register file (one block per CU).
 template <int H, bool BATCHED>
-constexpr int tv_min_blocks() { return (H <= 2 && !BATCHED) ? 4 : 1; }
+constexpr int tv_min_blocks() { return 1; }
 
 // Workgroups are dispatched round-robin over the 8 XCDs in order of their
 // linear id, and each XCD has its own L2.  Tiles overlap by their halo, so the
@@ -411,8 +402,9 @@ __global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, true>())) k_t
     if (map.offs[mid] <= b) lo = mid;
     else hi = mid;
   }
+  lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: the frame's arguments come in as scalar loads
   const TvPassArgs A = args[lo];
-  const int lb = (int)(b - map.offs[lo]);
+  const int lb = (int)(b - (uint32_t)__builtin_amdgcn_readfirstlane(map.offs[lo]));
   tv_pass_entry<H>(A, lb % A.gx, (lb / A.gx) % A.gy, lb / (A.gx * A.gy));
 }
 
