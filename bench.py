@@ -42,9 +42,10 @@ def prox_bytes_per_voxel(passes: int) -> float:
     return 16.0 + 28.0 * (passes - 2) + 20.0
 
 
-def measured_traffic():
+def measured_traffic(tuning):
     """HBM bytes per k_tv_pass dispatch from the committed rocprofv3 counter
-    summary, or None if the kernel source changed since the counters were taken."""
+    summary, or None if the kernel source changed since the counters were taken
+    or the plan runs with other launch shapes than the profiled run."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_tv_pass_c2_hbm_counters.md")
     src = os.path.join(ROOT, "paper_1904_04884_amd", "csrc", "tv.hip")
@@ -56,6 +57,9 @@ def measured_traffic():
                 kv[k.strip()] = v.strip()
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if kv.get("tv_source_sha256") != digest:
+            return None
+        want = "%d,%d,%d" % (tuning["tv_levels"], tuning["tv_blocks"], tuning["col_blocks"])
+        if kv.get("tuning") != want:
             return None
         return float(kv["traffic_bytes_per_dispatch"])
     except (OSError, KeyError, ValueError):
@@ -347,7 +351,7 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": prox_gbs / HBM_PEAK_GBS,
-        "traffic": measured_traffic(),
+        "traffic": measured_traffic(plan.tuning),
         "launch_ms": launch_ms,
         "passes": passes,
         "bytes_per_voxel_per_prox": prox_bytes_per_voxel(passes),
