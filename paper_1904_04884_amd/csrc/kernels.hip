@@ -36,7 +36,7 @@ __host__ __device__ constexpr int kRowsPerBlock(int m) {
 // Column transforms: points per thread, and columns per tile such that a block
 // has at most 512 threads (256 VGPRs per lane available, no spills) and the tile
 // plus one spare column fits the 160 KiB of LDS.
-__host__ __device__ constexpr int kColP(int ny) { return (ny % 3 == 0) ? 12 : (ny >= 1024 ? 16 : 8); }
+__host__ __device__ constexpr int kColP(int ny) { return (ny % 3 == 0) ? 12 : (ny >= 2048 ? 16 : 8); }
 __host__ __device__ constexpr int kColW(int ny) {
   int w = 16;
   while (w > 1 && ((ny / kColP(ny)) * w > 512 || (size_t)ny * (w + 1) * 8 > 160 * 1024)) w /= 2;
@@ -223,8 +223,16 @@ __device__ __forceinline__ void rows_c2r_body(const RowsC2RArgs& a, int bx, int 
 // Forward column pass with the propagation filter and the sum over planes.
 // Block: W columns x TC threads per column (TC = NY / P).
 // ---------------------------------------------------------------------------
+//
+// Software pipeline over the planes of the chunk: the tile of the next
+// non-empty plane is requested right after the barrier that precedes the
+// transform of the current one, so its loads run under the transform; the row
+// flags that decide which rows of that tile are read are themselves staged
+// into LDS one plane earlier still (one dword of flags per thread).
+// Direct form (no prefetch) for the transform sizes whose pipelined form would
+// not fit the register file: every row flag is read from global memory.
 template <int NY>
-__device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int by) {
+__device__ __forceinline__ void fwd_cols_body_direct(const FwdColsArgs& a, int bx, int by) {
   const PlanTables& pt = a.pt;
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
@@ -271,6 +279,100 @@ __device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int 
       }
     }
     __syncthreads();
+  }
+  if (!colok) return;
+  float2* dst = a.gp + (size_t)by * NY * m + kx;
+#pragma unroll
+  for (int s = 0; s < P; ++s) dst[(size_t)(q + s * TC) * m] = acc[s];
+}
+
+template <int NY>
+__device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int by) {
+  if constexpr (kColP(NY) > 8) {
+    fwd_cols_body_direct<NY>(a, bx, by);
+    return;
+  }
+  const PlanTables& pt = a.pt;
+  constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
+  constexpr int NFW = NY / 4;          // dwords of row flags per plane
+  static_assert(W * TC >= NFW, "one flag dword per thread");
+  __shared__ float2 lds[NY * W];
+  __shared__ uint32_t lds_fl[NFW];
+  if (solve_done(a.st)) return;
+  const int w = threadIdx.x % W, q = threadIdx.x / W;
+  const int m = a.m;
+  const int kx = bx * W + w;
+  const bool colok = kx < m;           // tiles may overhang the last column
+  const bool col0 = (kx == 0);
+  const bool flags = a.rowflag != nullptr;
+  const uint8_t* fl8 = reinterpret_cast<const uint8_t*>(lds_fl);
+  double th[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) th[s] = colok ? pt.theta[(size_t)(q + s * TC) * (m + 1) + kx] : 0.0;
+  float2 acc[P];
+#pragma unroll
+  for (int s = 0; s < P; ++s) acc[s] = make_float2(0.f, 0.f);
+  const int j0 = by * a.planes_per_chunk;
+  const int j1 = min(a.nz, j0 + a.planes_per_chunk);
+  auto next_plane = [&](int j) {
+    if (a.planeflag != nullptr)
+      while (j < j1 && a.planeflag[j] == 0) ++j;
+    return j;
+  };
+  auto load_flagword = [&](int j) -> uint32_t {
+    return reinterpret_cast<const uint32_t*>(a.rowflag + (size_t)j * NY)[threadIdx.x];
+  };
+  float2 nv[P];  // tile of the next plane, in flight
+  auto load_tile = [&](int j) {
+    const float2* src = a.t + (size_t)j * NY * m + kx;
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int y = q + s * TC;
+      const bool on = colok && (!flags || fl8[y] != 0);
+      nv[s] = on ? src[(size_t)y * m] : make_float2(0.f, 0.f);
+    }
+  };
+  int j = next_plane(j0);
+  int jn = j < j1 ? next_plane(j + 1) : j1;
+  uint32_t flw = 0;  // flag dword of plane jn (threads < NFW)
+  if (j < j1) {
+    if (flags) {
+      if (threadIdx.x < NFW) lds_fl[threadIdx.x] = load_flagword(j);
+      __syncthreads();
+    }
+    load_tile(j);
+    if (flags && jn < j1 && threadIdx.x < NFW) flw = load_flagword(jn);
+    __syncthreads();  // the flags of j are read before the loop overwrites them
+  }
+  while (j < j1) {
+#pragma unroll
+    for (int s = 0; s < P; ++s) lds[(q + s * TC) * W + w] = nv[s];
+    if (flags && jn < j1 && threadIdx.x < NFW) lds_fl[threadIdx.x] = flw;
+    const int jnn = jn < j1 ? next_plane(jn + 1) : j1;
+    if (flags && jnn < j1 && threadIdx.x < NFW) flw = load_flagword(jnn);
+    __syncthreads();
+    if (jn < j1) load_tile(jn);
+    fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+    const double2 zc = pt.zc[j];
+#pragma unroll
+    for (int s = 0; s < P; ++s) {
+      const int y = q + s * TC;
+      const float2 v = lds[y * W + w];
+      const float c = phase_cos(zc.x, zc.y, th[s]);
+      if (!col0) {
+        acc[s].x += c * v.x;
+        acc[s].y += c * v.y;
+      } else {
+        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float2 vn = cconj(lds[((NY - y) % NY) * W]);
+        const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
+        acc[s].x += ca * v.x + cb * vn.x;
+        acc[s].y += ca * v.y + cb * vn.y;
+      }
+    }
+    __syncthreads();
+    j = jn;
+    jn = jnn;
   }
   if (!colok) return;
   float2* dst = a.gp + (size_t)by * NY * m + kx;
@@ -710,10 +812,27 @@ __device__ __forceinline__ void batch_entry(const Args* __restrict__ args, Batch
 RIHVR_ENTRY_T(k_rows_r2c, rows_r2c_body, RowsR2CArgs, M, kRowsPerBlock(M) * kRowThreads(M))
 RIHVR_ENTRY_T(k_rows_c2r, rows_c2r_body, RowsC2RArgs, M, kRowsPerBlock(M) * kRowThreads(M))
 RIHVR_ENTRY_T(k_adj_rows, adj_rows_body, AdjRowsArgs, M, kRowsPerBlock(M) * kRowThreads(M))
-RIHVR_ENTRY_T(k_fwd_cols, fwd_cols_body, FwdColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
+// Column kernels: adjacent column tiles read the two halves of the same
+// 128-byte lines, so their blocks are placed on the same XCD (shared L2).
+#define RIHVR_ENTRY_COLS(NAME, BODY, ARGS, TP, NT)                                                \
+  template <int TP>                                                                               \
+  __global__ void __launch_bounds__(NT) NAME(ARGS a) {                                            \
+    const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);      \
+    BODY<TP>(a, t % gridDim.x, t / gridDim.x);                                                    \
+  }                                                                                               \
+  template <int TP>                                                                               \
+  __global__ void __launch_bounds__(NT) NAME##_b(const ARGS* __restrict__ args,                   \
+                                                 BatchMap map) {                                  \
+    ARGS a;                                                                                       \
+    int bx, by;                                                                                   \
+    batch_entry(args, map, a, bx, by);                                                            \
+    BODY<TP>(a, bx, by);                                                                          \
+  }
+RIHVR_ENTRY_COLS(k_fwd_cols, fwd_cols_body, FwdColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
 RIHVR_ENTRY_T(k_holo_cols_inv, holo_cols_inv_body, HoloColsInvArgs, NY, kColW(NY) * (NY / kColP(NY)))
-RIHVR_ENTRY_T(k_adj_cols, adj_cols_body, AdjColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
+RIHVR_ENTRY_COLS(k_adj_cols, adj_cols_body, AdjColsArgs, NY, kColW(NY) * (NY / kColP(NY)))
 #undef RIHVR_ENTRY_T
+#undef RIHVR_ENTRY_COLS
 
 __global__ void __launch_bounds__(kObjThreads) k_obj(ObjArgs a) { obj_body(a, blockIdx.x, blockIdx.y); }
 __global__ void __launch_bounds__(kObjThreads) k_obj_b(const ObjArgs* __restrict__ args,

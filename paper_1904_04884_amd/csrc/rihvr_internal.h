@@ -18,6 +18,18 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
   return reinterpret_cast<T*>(((uint64_t)hi << 32) | lo);
 }
 
+// Workgroups are dispatched round-robin over the 8 XCDs in order of their
+// linear id, and each XCD has its own L2.  xcd_tile maps the linear id to a
+// work index such that every XCD gets one contiguous run of indices, so that
+// neighbouring tiles (which share halo rows or cache lines) run on the same
+// XCD at about the same time.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t n) {
+  constexpr uint32_t kXcds = 8;
+  const uint32_t q = n / kXcds, r = n % kXcds;   // XCD k runs q + (k < r) indices
+  const uint32_t k = id % kXcds, j = id / kXcds;
+  return k * q + min(k, r) + j;
+}
+
 // One of three buffers by a runtime slot index, chosen by selects among values
 // already read (an indexed local array would be placed in scratch memory).
 template <class T>

@@ -373,18 +373,8 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
 template <int H, bool BATCHED>
 constexpr int tv_min_blocks() { return 1; }
 
-// Workgroups are dispatched round-robin over the 8 XCDs in order of their
-// linear id, and each XCD has its own L2.  Tiles overlap by their halo, so the
-// linear id is mapped to a tile index that gives every XCD one contiguous run
-// of tiles (x fastest): tiles running side by side on an XCD share their halo
-// rows and columns through its L2.  A bijection of [0, n).
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t n) {
-  constexpr uint32_t kXcds = 8;
-  const uint32_t q = n / kXcds, r = n % kXcds;   // XCD k runs q + (k < r) tiles
-  const uint32_t k = id % kXcds, j = id / kXcds;
-  return k * q + min(k, r) + j;
-}
-
+// Tiles overlap by their halo: xcd_tile gives every XCD one contiguous run of
+// tiles (x fastest), so tiles running side by side share halos in its L2.
 template <int H>
 __global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, false>())) k_tv_pass(TvPassArgs A) {
   const uint32_t n = gridDim.x * gridDim.y * gridDim.z;
