@@ -546,32 +546,67 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
   const int nx = a.nx, ny = a.ny, nz = a.nz;
   const long nrows = (long)ny * nz;
   double s_acc = 0.0, t_acc = 0.0;
+  // Each thread takes four consecutive voxels of a row (nx is a multiple of 4;
+  // volumes are only 8-byte aligned, so they are read as float2 pairs).  The
+  // rows of the block are unrolled so that all their loads are in flight
+  // together; rows longer than 4 x kObjThreads take several chunks.
+  constexpr int CH = kObjThreads * 4;
+  const int i0 = threadIdx.x * 4;
+  const int ilast = i0 < nx ? i0 + ((nx - 1 - i0) / CH) * CH : -1;  // this thread's last chunk
+  auto ld4 = [](const float* p) {
+    const float2 u = *reinterpret_cast<const float2*>(p);
+    const float2 w = *reinterpret_cast<const float2*>(p + 2);
+    return make_float4(u.x, u.y, w.x, w.y);
+  };
+  const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
+  auto reduce4 = [&](int i, float4 v, float vx, float4 vy, float4 vz, bool hy, bool hz) {
+    const float a4[5] = {v.x, v.y, v.z, v.w, vx};
+    const float b4[4] = {vy.x, vy.y, vy.z, vy.w};
+    const float c4[4] = {vz.x, vz.y, vz.z, vz.w};
+    float ss = 0.f, tt = 0.f;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float gx = (i + k + 1 < nx) ? a4[k + 1] - a4[k] : 0.f;
+      const float gy = hy ? b4[k] - a4[k] : 0.f;
+      const float gz = hz ? c4[k] - a4[k] : 0.f;
+      ss += a4[k];
+      // per-voxel norm in FP32 (relative error ~1e-7), running sums in FP64
+      tt += sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+    }
+    s_acc += (double)ss;
+    t_acc += (double)tt;
+  };
+  float4 v[kObjRows], vy[kObjRows], vz[kObjRows];
+  float vx[kObjRows];
+  bool on[kObjRows], hy[kObjRows], hz[kObjRows];
+#pragma unroll
   for (int rr = 0; rr < kObjRows; ++rr) {
     const long row = (long)bx * kObjRows + rr;
-    if (row >= nrows) break;
-    const int z = (int)(row / ny), y = (int)(row % ny);
-    const bool has_y = y + 1 < ny, has_z = z + 1 < nz;
-    bool any = true;
-    bool f0 = true, fy = has_y, fz = has_z;
-    if (a.rowflag != nullptr) {
+    on[rr] = row < nrows && ilast >= 0;
+    const int z = row < nrows ? (int)(row / ny) : 0, y = row < nrows ? (int)(row % ny) : 0;
+    hy[rr] = y + 1 < ny;
+    hz[rr] = z + 1 < nz;
+    bool f0 = on[rr], fy = on[rr] && hy[rr], fz = on[rr] && hz[rr];
+    if (a.rowflag != nullptr && on[rr]) {
       f0 = a.rowflag[row] != 0;
-      fy = has_y && a.rowflag[row + 1] != 0;
-      fz = has_z && a.rowflag[row + ny] != 0;
-      any = f0 || fy || fz;
+      fy = fy && a.rowflag[row + 1] != 0;
+      fz = fz && a.rowflag[row + ny] != 0;
     }
-    if (!any) continue;
-    const float* r0 = x + (size_t)row * nx;
-    for (int i = threadIdx.x; i < nx; i += kObjThreads) {
-      const float v = f0 ? r0[i] : 0.f;
-      const float vx = (f0 && i + 1 < nx) ? r0[i + 1] : 0.f;
-      const float gx = (i + 1 < nx) ? vx - v : 0.f;
-      const float gy = has_y ? ((fy ? r0[i + nx] : 0.f) - v) : 0.f;
-      const float gz = has_z ? ((fz ? r0[(size_t)ny * nx + i] : 0.f) - v) : 0.f;
-      s_acc += (double)v;
-      // per-voxel norm in FP32 (relative error ~1e-7), sums in FP64
-      t_acc += (double)sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+    const float* r0 = x + (size_t)(row < nrows ? row : 0) * nx;
+    v[rr] = vy[rr] = vz[rr] = zero;
+    vx[rr] = 0.f;
+    if (!on[rr]) continue;
+    for (int i = i0; i <= ilast; i += CH) {
+      v[rr] = f0 ? ld4(r0 + i) : zero;
+      vx[rr] = (f0 && i + 4 < nx) ? r0[i + 4] : 0.f;
+      vy[rr] = fy ? ld4(r0 + nx + i) : zero;
+      vz[rr] = fz ? ld4(r0 + (size_t)ny * nx + i) : zero;
+      if (i != ilast) reduce4(i, v[rr], vx[rr], vy[rr], vz[rr], hy[rr], hz[rr]);
     }
   }
+#pragma unroll
+  for (int rr = 0; rr < kObjRows; ++rr)
+    if (on[rr]) reduce4(ilast, v[rr], vx[rr], vy[rr], vz[rr], hy[rr], hz[rr]);
   s_acc = block_sum<kObjThreads>(s_acc, red[0]);
   __syncthreads();
   t_acc = block_sum<kObjThreads>(t_acc, red[1]);

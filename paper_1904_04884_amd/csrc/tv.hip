@@ -163,9 +163,11 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   // Arrival of the previous dual c3 at plane a for fused step l: u(a), then
   // the dual step at plane a - 1 (which needs u(a) for its z-difference).
   auto arrive = [&](int l, int a, int par, float (&c3)[Q][3]) {
+    float un[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) un[q] = vring(a, q);  // thread-private: read before the barrier
     s_py[l][par][wv][lane] = c3[Q - 1][1];
     __syncthreads();
-    float un[Q];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       const float pxm = dpp_from_left(c3[q][0]);
@@ -173,7 +175,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
       d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
       d += c3[q][2] - Pp[l][q][2];
-      un[q] = fmaf(tau, d, vring(a, q));
+      un[q] = fmaf(tau, d, un[q]);
     }
     if (a > zs) {
 #pragma unroll
@@ -247,12 +249,15 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         }
       }
     } else {
+      float vm[Q];
+#pragma unroll
+      for (int q = 0; q < Q; ++q) vm[q] = vring(m, q);  // thread-private: read before the barrier
       s_py[H][par][wv][lane] = c3[Q - 1][1];
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rx = plane_rsrc(xo, m, sz);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        float u = vring(m, q);
+        float u = vm[q];
         if (tau != 0.f) {
           const float pxm = dpp_from_left(c3[q][0]);
           const float pym = (q > 0) ? c3[q - 1][1] : s_py[H][par][wv > 0 ? wv - 1 : 0][lane];
