@@ -193,6 +193,125 @@ def run_batched(args, torch, rihvr, scenes):
     }
 
 
+def frame_hologram(torch, plan, g, idx, val, noise):
+    lin = np.ravel_multi_index((idx[:, 0], idx[:, 1], idx[:, 2]), g.shape)
+    xt = torch.zeros(g.shape, dtype=torch.float32, device="cuda")
+    xt.view(-1)[torch.from_numpy(lin).cuda()] = torch.from_numpy(val.astype(np.float32)).cuda()
+    b = plan.forward(xt) + torch.from_numpy(noise.astype(np.float32)).cuda()
+    del xt
+    return b.contiguous()
+
+
+def run_compare(args, torch, rihvr, scenes):
+    """Warm-started batched solves against plain per-frame FISTA (cold start,
+    dense, no graph, one frame at a time), both to objective gap 1e-4 on the
+    same uneven Burgers-vortex frames; the network is trained on another seed of
+    the series.  Plan creation, autotuning, references and training are
+    reported separately and are outside both clocks."""
+    from paper_1904_04884_amd import warmstart
+    cfg = scenes.config_c2()
+    K = cfg.inner_iters
+    t_setup = time.perf_counter()
+    frames = burgers_frames(scenes, args.compare, seed=args.seed)
+    plans, bs = [], []
+    for g, idx, val, noise in frames:
+        p = rihvr.Plan(g)
+        plans.append(p)
+        bs.append(frame_hologram(torch, p, g, idx, val, noise))
+    nvox = sum(g.nx * g.ny * g.nz for g, _, _, _ in frames)
+    # references (restarted FISTA), not timed
+    f_refs = []
+    for p, b in zip(plans, bs):
+        f_refs.append(p.solve(b, cfg.l1, cfg.tv, args.cmp_ref_iters, K, flags=rihvr.RI_SOLVE_RESTART,
+                              report=True)[1]["objective_min"])
+    log(f"compare: {len(frames)} frames, {nvox / 1e9:.2f} G voxels; references done "
+        f"({time.perf_counter() - t_setup:.1f} s)")
+    # warm-start network on another seed of the series
+    t0 = time.perf_counter()
+    tframes = burgers_frames(scenes, args.cmp_train, seed=args.seed + 1000)
+    tplans = [rihvr.Plan(g) for g, _, _, _ in tframes]
+    ws = warmstart.WarmStart(tplans[0], levels=4, base=16, seed=args.seed)
+    pairs = []
+    for p, (g, idx, val, noise) in zip(tplans, tframes):
+        pairs.append(ws.make_pair(frame_hologram(torch, p, g, idx, val, noise), cfg.l1, cfg.tv,
+                                  args.ws_pair_iters, K, plan=p)[0])
+    curve = ws.train(pairs, steps=args.ws_steps, crop=(32, 64, 64), lr=1e-3,
+                     log_every=max(1, args.ws_steps // 5))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    del pairs
+    for p in tplans:
+        p.close()
+    log(f"compare: network trained on {len(tframes)} frames in {t_train:.1f} s")
+    tuned = 0
+    if not args.no_autotune:
+        import tempfile
+        cache = os.path.join(tempfile.mkdtemp(prefix="rihvr_tune_"), "tune.jsonl")
+        for p in plans:
+            tuned += 0 if p.autotune(K, cache)["from_cache"] else 1
+
+    def plain():
+        its = []
+        for p, b, f in zip(plans, bs, f_refs):
+            _, r, _ = p.solve(b, cfg.l1, cfg.tv, args.max_iters, K, f_ref=f, gap_tol=args.gap, check_every=5,
+                              flags=rihvr.RI_SOLVE_DENSE | rihvr.RI_SOLVE_NO_GRAPH)
+            its.append(r["iters"])
+        return its
+
+    def warm_batched(warm=True):
+        xs, params, used = [], [], []
+        for p, b, f in zip(plans, bs, f_refs):
+            x1, sc, f0, fs = ws.propose(b, cfg.l1, cfg.tv, K, plan=p) if warm else (None, 1.0, 0.0, 0.0)
+            ok = x1 is not None and fs < f0
+            used.append(bool(ok))
+            xs.append(x1 if ok else torch.empty(p.shape, dtype=torch.float32, device="cuda"))
+            params.append(p.solve_params(cfg.l1, cfg.tv, args.max_iters, K, gap_tol=args.gap, f_ref=f,
+                                         init=rihvr.RI_INIT_GIVEN if ok else rihvr.RI_INIT_ZERO, check_every=5,
+                                         x0_scale=sc if ok else 1.0))
+        handles = [p.handle for p in plans]
+        nbytes = rihvr.ri_workspace_size_batched(len(plans), handles, params)
+        wsb = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        reps = (rihvr.ri_solve_report * len(plans))()
+        st = rihvr.ri_solve_batched(len(plans), handles, params, [b.data_ptr() for b in bs],
+                                    [x.data_ptr() for x in xs], wsb.data_ptr(), wsb.numel(),
+                                    torch.cuda.current_stream().cuda_stream, reps)
+        assert st == rihvr.RI_OK, rihvr.ri_last_error()
+        return [r.iters for r in reps], [bool(r.converged) for r in reps], used
+
+    plain()  # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_plain = plain()
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    warm_batched(False)  # warm-up (graph, allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it_cold_b, conv_cold_b, _ = warm_batched(False)
+    torch.cuda.synchronize()
+    t_cold_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    it_warm_b, conv_warm_b, used = warm_batched(True)
+    torch.cuda.synchronize()
+    t_warm_b = time.perf_counter() - t0
+    for p in plans:
+        p.close()
+    n = len(frames)
+    out = {
+        "metric": "holograms/s to objective gap 1e-4: warm-started batched vs plain per-frame FISTA",
+        "frames": n, "voxels": nvox, "gap": args.gap,
+        "plain_holograms_per_s": n / t_plain, "cold_batched_holograms_per_s": n / t_cold_b,
+        "warm_batched_holograms_per_s": n / t_warm_b, "speedup_vs_plain": t_plain / t_warm_b,
+        "plain_iters": it_plain, "cold_batched_iters": it_cold_b, "warm_batched_iters": it_warm_b,
+        "converged": all(conv_cold_b) and all(conv_warm_b), "proposal_used": used,
+        "train_frames": len(tframes), "train_s": t_train, "loss_curve": curve, "autotuned_shapes": tuned,
+        "sizes": [[g.nx, g.nz] for g, _, _, _ in frames],
+    }
+    log(f"plain {n / t_plain:.3f} holo/s, cold batched {n / t_cold_b:.3f}, warm batched {n / t_warm_b:.3f} "
+        f"({t_plain / t_warm_b:.2f}x)")
+    return out
+
+
 def run_warmstart(args, torch, rihvr, scenes):
     """Iterations to gap 1e-4, cold vs learned warm start, on held-out scenes."""
     from paper_1904_04884_amd import warmstart
@@ -261,6 +380,10 @@ def main():
     ap.add_argument("--batched", type=int, default=0, help="run the batched uneven-frame mode with this many frames")
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start evaluation mode")
+    ap.add_argument("--compare", type=int, default=0,
+                    help="warm-started batched solves vs plain per-frame FISTA on this many uneven frames")
+    ap.add_argument("--cmp-train", type=int, default=8, help="training frames for --compare")
+    ap.add_argument("--cmp-ref-iters", type=int, default=600, help="restarted reference iterations for --compare")
     ap.add_argument("--ws-size", type=int, default=256)
     ap.add_argument("--ws-planes", type=int, default=64)
     ap.add_argument("--ws-pairs", type=int, default=48)
@@ -268,6 +391,8 @@ def main():
     ap.add_argument("--ws-steps", type=int, default=1500)
     ap.add_argument("--ws-eval", type=int, default=4)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
+    ap.add_argument("--restart", action="store_true",
+                    help="timed solves use function-value restart of the momentum (FISTA variant; not the default)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="fixed launch shapes tv_levels,tv_blocks,col_blocks (no autotuning; for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -289,6 +414,9 @@ def main():
         return
     if args.warmstart:
         print(json.dumps(run_warmstart(args, torch, rihvr, scenes)), flush=True)
+        return
+    if args.compare:
+        print(json.dumps(run_compare(args, torch, rihvr, scenes)), flush=True)
         return
     cfg = scenes.config_c2()
     g = scenes.geometry_c2()
@@ -315,6 +443,7 @@ def main():
     log(f"reference: {args.ref_iters} restarted iterations, F_ref = {f_ref:.9g} ({time.perf_counter() - t0:.1f} s)")
 
     def one_solve(flags=0):
+        flags |= rihvr.RI_SOLVE_RESTART if args.restart else 0
         return plan.solve(b, cfg.l1, cfg.tv, args.max_iters, cfg.inner_iters, f_ref=f_ref, gap_tol=args.gap,
                           check_every=args.check_every, flags=flags)
 

@@ -95,6 +95,8 @@ typedef struct {
   int32_t check_every;      /* host reads the device stop flag every this many iterations (>= 1) */
   uint32_t flags;           /* RI_SOLVE_* */
   int32_t nonneg;           /* 1: x >= 0 (the problem above); 0: signed soft threshold */
+  double x0_scale;          /* RI_INIT_GIVEN: start from x0_scale * x_inout (scaled in place);
+                               0 is read as 1; must be finite and >= 0 */
 } ri_solve_params;
 
 #define RI_NUM_PHASES 6     /* forward, hologram, adjoint, prox, objective, other */

@@ -695,6 +695,8 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
     return fail(RI_ERR_INVALID_ARG, "l1 and tv must be finite and >= 0");
   if (sp->max_iters < 0 || sp->inner_iters < 0) return fail(RI_ERR_INVALID_ARG, "iteration counts must be >= 0");
   if (sp->init != RI_INIT_ZERO && sp->init != RI_INIT_GIVEN) return fail(RI_ERR_INVALID_ARG, "init must be ZERO or GIVEN");
+  if (!(sp->x0_scale >= 0) || !std::isfinite(sp->x0_scale))
+    return fail(RI_ERR_INVALID_ARG, "x0_scale must be finite and >= 0");
   if (sp->f_ref > 0 && !(sp->gap_tol >= 0)) return fail(RI_ERR_INVALID_ARG, "gap_tol must be >= 0");
   if (sp->flags & ~(RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH | RI_SOLVE_RESTART | RI_SOLVE_TIMING))
     return fail(RI_ERR_INVALID_ARG, "unknown solve flags 0x%x", sp->flags);
@@ -722,6 +724,8 @@ static hipError_t enqueue_setup(const SolveCtx& c, const ri_solve_params* sp, hi
   if (sp->init == RI_INIT_ZERO) {
     if ((e = launch_fill_f32(c.vol[0], nvox, 0.f, s)) != hipSuccess) return e;
   } else {
+    if (sp->x0_scale != 0.0 && sp->x0_scale != 1.0)
+      if ((e = launch_scale_f32(c.vol[0], nvox, (float)sp->x0_scale, s)) != hipSuccess) return e;
     if ((e = launch_flags_from_x(c.vol[0], p->g.nx, p->g.ny, p->g.nz, rowflag, planeflag, s)) != hipSuccess) return e;
   }
   if ((e = launch_copy_f32(c.vol[2], c.vol[0], nvox, s)) != hipSuccess) return e;

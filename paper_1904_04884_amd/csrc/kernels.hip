@@ -742,6 +742,13 @@ static int grid_for(size_t n) {
   return (int)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
 }
 
+__global__ void k_scale_f32(float* p, size_t n, float v) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) p[i] *= v;
+}
+hipError_t launch_scale_f32(float* p, size_t n, float v, hipStream_t s) {
+  hipLaunchKernelGGL(k_scale_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(n)), dim3(256), 0, s, p, n, v);
   return hipGetLastError();

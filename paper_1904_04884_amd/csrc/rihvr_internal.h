@@ -222,6 +222,7 @@ hipError_t launch_state_init(SolveState* st, const StateInit& init, hipStream_t 
 
 // Utility kernels
 hipError_t launch_fill_f32(float* p, size_t n, float v, hipStream_t s);
+hipError_t launch_scale_f32(float* p, size_t n, float v, hipStream_t s);  // p *= v
 hipError_t launch_fill_u8(uint8_t* p, size_t n, uint8_t v, hipStream_t s);
 hipError_t launch_copy_f32(float* dst, const float* src, size_t n, hipStream_t s);
 // Set row / plane flags of a volume from its contents (flags must be cleared).

@@ -64,7 +64,8 @@ class ri_prox_params(C.Structure):
 class ri_solve_params(C.Structure):
     _fields_ = [("l1", C.c_double), ("tv", C.c_double), ("max_iters", C.c_int32), ("inner_iters", C.c_int32),
                 ("gap_tol", C.c_double), ("f_ref", C.c_double), ("init", C.c_int32),
-                ("check_every", C.c_int32), ("flags", C.c_uint32), ("nonneg", C.c_int32)]
+                ("check_every", C.c_int32), ("flags", C.c_uint32), ("nonneg", C.c_int32),
+                ("x0_scale", C.c_double)]
 
 
 class ri_solve_report(C.Structure):
@@ -374,12 +375,13 @@ class Plan:
         return out
 
     def solve_params(self, l1, tv, max_iters, inner_iters, gap_tol=0.0, f_ref=0.0, init=RI_INIT_ZERO,
-                     check_every=10, flags=0, nonneg=True) -> ri_solve_params:
+                     check_every=10, flags=0, nonneg=True, x0_scale=1.0) -> ri_solve_params:
         return ri_solve_params(float(l1), float(tv), int(max_iters), int(inner_iters), float(gap_tol),
-                               float(f_ref), int(init), int(check_every), int(flags), 1 if nonneg else 0)
+                               float(f_ref), int(init), int(check_every), int(flags), 1 if nonneg else 0,
+                               float(x0_scale))
 
     def solve(self, b, l1, tv, max_iters, inner_iters, x=None, gap_tol=0.0, f_ref=0.0, check_every=10,
-              flags=0, nonneg=True, report=True, raise_on_error=True):
+              flags=0, nonneg=True, report=True, raise_on_error=True, x0_scale=1.0):
         torch = self.torch
         self._chk(b, (self.geom.ny, self.geom.nx))
         init = RI_INIT_ZERO
@@ -389,7 +391,8 @@ class Plan:
             self._chk(x, self.shape)
             init = RI_INIT_GIVEN
         ws, n = self.workspace(RI_OP_SOLVE)
-        sp = self.solve_params(l1, tv, max_iters, inner_iters, gap_tol, f_ref, init, check_every, flags, nonneg)
+        sp = self.solve_params(l1, tv, max_iters, inner_iters, gap_tol, f_ref, init, check_every, flags, nonneg,
+                               x0_scale)
         rep = ri_solve_report() if report else None
         st = ri_solve(self.handle, sp, b.data_ptr(), x.data_ptr(), ws.data_ptr(), ws.numel(),
                       _stream_handle(torch), rep)

@@ -58,6 +58,7 @@ int main(void) {
   F(ri_geometry, pixel_um) F(ri_geometry, flags)
   F(ri_prox_params, inner_iters) F(ri_prox_params, nonneg)
   F(ri_solve_params, gap_tol) F(ri_solve_params, init) F(ri_solve_params, flags) F(ri_solve_params, nonneg)
+  F(ri_solve_params, x0_scale)
   F(ri_solve_report, objective) F(ri_solve_report, phase_ms) F(ri_solve_report, phase_launches)
   F(ri_tuning, tv_blocks) F(ri_tuning, col_blocks)
   F(ri_autotune_report, from_cache) F(ri_autotune_report, candidates) F(ri_autotune_report, default_ms)

@@ -278,6 +278,25 @@ def test_solve_warm_start_and_gap_stop(torch_cuda, plans, c1_problem):
     assert rep_w["iters"] == 0 and rep_w["objective"] == pytest.approx(F_ref, rel=1e-5)
 
 
+def test_x0_scale_equals_scaled_start(torch_cuda, plans, c1_problem):
+    """A given start scaled by the solve (x0_scale) equals the same start scaled
+    beforehand (scaling by 2 is exact), and 0 reads as 1."""
+    torch = torch_cuda
+    sc, b, _ = c1_problem
+    g, cfg = sc.geometry, sc.config
+    p = plans(g)
+    rng = np.random.default_rng(21)
+    x0 = np.maximum(rng.standard_normal(g.shape), 0.0) * 0.01
+    xa, ra, _ = p.solve(to_dev(torch, b), cfg.l1, cfg.tv, 6, cfg.inner_iters, x=to_dev(torch, x0), x0_scale=2.0)
+    xb, rb, _ = p.solve(to_dev(torch, b), cfg.l1, cfg.tv, 6, cfg.inner_iters, x=to_dev(torch, 2.0 * x0))
+    assert torch.equal(xa, xb) and ra["objective"] == rb["objective"]
+    xc, _, _ = p.solve(to_dev(torch, b), cfg.l1, cfg.tv, 6, cfg.inner_iters, x=to_dev(torch, x0), x0_scale=0.0)
+    xd, _, _ = p.solve(to_dev(torch, b), cfg.l1, cfg.tv, 6, cfg.inner_iters, x=to_dev(torch, x0))
+    assert torch.equal(xc, xd)
+    with pytest.raises(rihvr.RihvrError):
+        p.solve(to_dev(torch, b), cfg.l1, cfg.tv, 6, cfg.inner_iters, x=to_dev(torch, x0), x0_scale=-1.0)
+
+
 def test_scale_covariance(torch_cuda, plans, c1_problem):
     torch = torch_cuda
     sc, b, _ = c1_problem
