@@ -372,23 +372,20 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
 #undef RIHVR_TV_BODY
 }
 
-// Register budget: the two-deep pipeline fits 128 VGPRs (two blocks of eight
-// waves per CU); the deeper ones, and the batched entry (which also holds the
-// frame lookup), keep their full register file (one block per CU).
-template <int H, bool BATCHED>
-constexpr int tv_min_blocks() { return 1; }
+// The second launch-bounds argument is the minimum number of waves per SIMD
+// the register allocation must allow: 12-wave blocks need 3 (<= 170 VGPRs,
+// one block per CU), which every fusion depth fits.
+constexpr int kTvWavesPerSimd = (kTvWaves + 3) / 4;
 
-// Tiles overlap by their halo: xcd_tile gives every XCD one contiguous run of
-// tiles (x fastest), so tiles running side by side share halos in its L2.
 template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, false>())) k_tv_pass(TvPassArgs A) {
+__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass(TvPassArgs A) {
   const uint32_t n = gridDim.x * gridDim.y * gridDim.z;
   const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), n);
   tv_pass_entry<H>(A, t % A.gx, (t / A.gx) % A.gy, t / (A.gx * A.gy));
 }
 
 template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64, (tv_min_blocks<H, true>())) k_tv_pass_b(const TvPassArgs* __restrict__ args,
+__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(const TvPassArgs* __restrict__ args,
                                                                                   BatchMap map) {
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
   int lo = 0, hi = map.n;  // largest f with offs[f] <= b

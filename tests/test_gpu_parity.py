@@ -37,7 +37,8 @@ def geom(nx, ny, nz, **kw):
     return scenes.geometry_c1().with_(nx=nx, ny=ny, nz=nz, **kw)
 
 
-SHAPES = [(128, 128, 32), (48, 96, 5), (96, 48, 7), (64, 192, 3), (16, 16, 1), (256, 64, 9), (192, 24, 4)]
+SHAPES = [(128, 128, 32), (48, 96, 5), (96, 48, 7), (64, 192, 3), (16, 16, 1), (256, 64, 9), (192, 24, 4),
+          (32, 512, 3), (16, 1024, 2)]
 
 
 @pytest.fixture(scope="module")
@@ -337,6 +338,32 @@ def test_batched_matches_single(torch_cuda, plans, graph):
     assert rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs],
                                   [x.data_ptr() for x in xs], ws.data_ptr(), nbytes - 1,
                                   torch.cuda.current_stream().cuda_stream, None) == rihvr.RI_ERR_WORKSPACE_TOO_SMALL
+
+
+def test_batched_given_scaled_starts_match_single(torch_cuda, plans):
+    """Frames started from given volumes scaled by the solve (x0_scale), mixed
+    with cold frames, equal their per-frame solves exactly."""
+    torch = torch_cuda
+    gs = [geom(64, 64, 8), geom(48, 96, 5), geom(96, 96, 7)]
+    scales = [0.5, 1.0, 3.0]
+    rng = np.random.default_rng(15)
+    bs = [to_dev(torch, rng.standard_normal((g.ny, g.nx))) for g in gs]
+    x0s = [to_dev(torch, 0.01 * np.maximum(rng.standard_normal(g.shape), 0.0)) for g in gs]
+    ps = [plans(g) for g in gs]
+    given = [True, False, True]
+    singles = [p.solve(b, 0.05, 0.02, 5, 4, x=x0.clone() if gv else None, x0_scale=sc)[0].clone()
+               for p, b, x0, sc, gv in zip(ps, bs, x0s, scales, given)]
+    params = [p.solve_params(0.05, 0.02, 5, 4, init=rihvr.RI_INIT_GIVEN if gv else rihvr.RI_INIT_ZERO,
+                             x0_scale=sc) for p, sc, gv in zip(ps, scales, given)]
+    handles = [p.handle for p in ps]
+    ws = torch.empty(rihvr.ri_workspace_size_batched(len(ps), handles, params), dtype=torch.uint8, device="cuda")
+    xs = [x0.clone() if gv else torch.empty(p.shape, dtype=torch.float32, device="cuda")
+          for p, x0, gv in zip(ps, x0s, given)]
+    st = rihvr.ri_solve_batched(len(ps), handles, params, [b.data_ptr() for b in bs], [x.data_ptr() for x in xs],
+                                ws.data_ptr(), ws.numel(), torch.cuda.current_stream().cuda_stream, None)
+    assert st == rihvr.RI_OK, rihvr.ri_last_error()
+    for a, sgl in zip(xs, singles):
+        assert torch.equal(a, sgl)
 
 
 def test_batched_gap_stop_per_frame(torch_cuda, plans):
