@@ -45,7 +45,7 @@ def prox_bytes_per_voxel(passes: int) -> float:
 def measured_traffic(tuning):
     """HBM bytes per k_tv_pass dispatch from the committed rocprofv3 counter
     summary, or None if the kernel source changed since the counters were taken
-    or the plan runs with other launch shapes than the profiled run."""
+    or the plan runs the TV pass with another launch shape than the profiled run."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_tv_pass_c2_hbm_counters.md")
     src = os.path.join(ROOT, "paper_1904_04884_amd", "csrc", "tv.hip")
@@ -58,8 +58,8 @@ def measured_traffic(tuning):
         digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
         if kv.get("tv_source_sha256") != digest:
             return None
-        want = "%d,%d,%d" % (tuning["tv_levels"], tuning["tv_blocks"], tuning["col_blocks"])
-        if kv.get("tuning") != want:
+        want = "%d,%d" % (tuning["tv_levels"], tuning["tv_blocks"])   # the TV pass's launch shape
+        if kv.get("tv_tuning") != want:
             return None
         return float(kv["traffic_bytes_per_dispatch"])
     except (OSError, KeyError, ValueError):

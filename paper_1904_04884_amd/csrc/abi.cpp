@@ -246,7 +246,7 @@ struct Layout {
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
 
 // Candidate launch shapes of the autotuner (distinct grids only are timed).
-static const int kTvBlockCands[] = {768, 1536, 3072, 6144};
+static const int kTvBlockCands[] = {256, 512, 768, 1536, 3072, 6144};
 static const int kColBlockCands[] = {128, 256, 512, 1024, 2048};
 static const int kColTuneMax = 2048;
 
@@ -1353,6 +1353,7 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
 
   // column chunking: forward + adjoint
   std::vector<int> seen;
+  std::vector<std::pair<int, double>> col_ms;
   double col_best = 0.0, col_dflt = 0.0;
   int col_choice = dflt.col_blocks;
   for (int c : kColBlockCands) {
@@ -1368,13 +1369,18 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
       return e == hipSuccess ? enqueue_adjoint(p, L, ws, hy, xo, s) : e;
     }, &ms));
     ++rep.candidates;
+    col_ms.push_back({c, ms});
     if (c == dflt.col_blocks) col_dflt = ms;
-    if (col_best == 0.0 || ms < col_best) { col_best = ms; col_choice = c; }
   }
-  if (col_best > 0.99 * col_dflt) { col_best = col_dflt; col_choice = dflt.col_blocks; }
+  // keep the default unless a candidate beats it by 1 %, and a later candidate
+  // only if it beats the kept one by 1 % (timing noise does not flip choices)
+  col_best = col_dflt;
+  for (const auto& cm : col_ms)
+    if (cm.second < 0.99 * col_best) { col_best = cm.second; col_choice = cm.first; }
 
   // TV prox: fusion depth x z-chunking
   double tv_best = 0.0, tv_dflt = 0.0;
+  std::vector<std::pair<std::pair<int, int>, double>> tv_ms;
   int lv_choice = dflt.tv_levels, tb_choice = dflt.tv_blocks;
   std::vector<std::pair<int, int>> seen_tv;
   for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
@@ -1401,11 +1407,13 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
       double ms = 0.0;
       HIP_TRY(time_calls(s, [&]() -> hipError_t { return launch_prox(a, s, nullptr); }, &ms));
       ++rep.candidates;
+      tv_ms.push_back({{H, b}, ms});
       if (is_dflt) tv_dflt = ms;
-      if (tv_best == 0.0 || ms < tv_best) { tv_best = ms; lv_choice = H; tb_choice = b; }
     }
   }
-  if (tv_best > 0.99 * tv_dflt) { tv_best = tv_dflt; lv_choice = dflt.tv_levels; tb_choice = dflt.tv_blocks; }
+  tv_best = tv_dflt;
+  for (const auto& tm : tv_ms)
+    if (tm.second < 0.99 * tv_best) { tv_best = tm.second; lv_choice = tm.first.first; tb_choice = tm.first.second; }
 
   const ri_tuning best{lv_choice, tb_choice, col_choice};
   rep.default_ms = col_dflt + tv_dflt;
