@@ -28,104 +28,127 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
   return (uint16_t)(u >> 16);
 }
 
-// tap t of a 3x3x3 stencil -> (dz, dy, dx) in {-1, 0, 1}
-__device__ __forceinline__ void tap3(int t, int& dz, int& dy, int& dx) {
-  dz = t / 9 - 1;
-  dy = (t / 3) % 3 - 1;
-  dx = t % 3 - 1;
+// Row coordinates of one lane, computed once: the source voxel of a tap is
+// then found with adds and compares only (no 64-bit division per k-step).
+struct GgRow {
+  int x, y, z;
+  bool ok;
+};
+__device__ __forceinline__ GgRow gg_row(const GatherGemmArgs& a, long r, long nrows) {
+  GgRow g;
+  g.ok = r < nrows;
+  const long rr = g.ok ? r : 0;
+  const long hw = (long)a.W * a.H;
+  g.z = (int)(rr / hw);
+  const int rem = (int)(rr - (long)g.z * hw);
+  g.y = rem / a.W;
+  g.x = rem - g.y * a.W;
+  return g;
 }
 
-// Source voxel (linear index at the source resolution) of row r for tap t, or -1.
-__device__ __forceinline__ long gg_source(const GatherGemmArgs& a, long r, int t) {
+// Source voxel (linear index at the source resolution) of a row for tap t, or -1.
+__device__ __forceinline__ long gg_source(const GatherGemmArgs& a, const GgRow& g, int t) {
   const int D = a.D, H = a.H, W = a.W;  // row grid
-  const int x = (int)(r % W), y = (int)((r / W) % H), z = (int)(r / ((long)W * H));
   switch (a.mode) {
     case GG_CONV3_FWD:
     case GG_CONV3_BWD: {
-      int dz, dy, dx;
-      tap3(t, dz, dy, dx);
+      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;  // tap t of the 3x3x3 stencil
       if (a.mode == GG_CONV3_BWD) { dz = -dz; dy = -dy; dx = -dx; }
-      const int zz = z + dz, yy = y + dy, xx = x + dx;
+      const int zz = g.z + dz, yy = g.y + dy, xx = g.x + dx;
       if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) return -1;
       return ((long)zz * H + yy) * W + xx;
     }
     case GG_UP_FWD:
     case GG_POINT:
-      return r;
+      return ((long)g.z * H + g.y) * W + g.x;
     case GG_UP_BWD: {
-      // row r is coarse voxel (z, y, x); tap t = dz*4 + dy*2 + dx selects the fine voxel
-      const int zz = 2 * z + (t >> 2), yy = 2 * y + ((t >> 1) & 1), xx = 2 * x + (t & 1);
+      // row (z, y, x) is a coarse voxel; tap t = dz*4 + dy*2 + dx selects the fine voxel
+      const int zz = 2 * g.z + (t >> 2), yy = 2 * g.y + ((t >> 1) & 1), xx = 2 * g.x + (t & 1);
       return ((long)zz * (2 * H) + yy) * (2 * W) + xx;
     }
   }
   return -1;
 }
 
-// Block: 4 wavefronts x 16 rows = 64 rows; every wavefront computes all NB
-// column tiles of its rows.
-template <int NB>
+// Block: 4 wavefronts x (16 RT) rows; every wavefront computes all NB column
+// tiles of its RT row tiles, so a B fragment (weights) feeds RT MFMAs and an A
+// fragment (gathered activations) feeds NB.  The reduction index k = t C + c
+// advances by 32 per step with t, c updated incrementally.
+template <int NB, int RT>
 __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const long row0 = (long)blockIdx.x * 64 + wv * 16;
+  const long row0 = ((long)blockIdx.x * 4 + wv) * (16 * RT);
   const long nrows = (long)a.D * a.H * a.W;
-  const long ra = row0 + (lane & 15);   // A row of this lane
   const int kq = (lane >> 4) * 8;       // reduction offset of this lane within a 32-chunk
   const int K = a.T * a.C;
-  f32x4 acc[NB];
+  GgRow rows[RT];
 #pragma unroll
-  for (int j = 0; j < NB; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int i = 0; i < RT; ++i) rows[i] = gg_row(a, row0 + i * 16 + (lane & 15), nrows);
+  f32x4 acc[RT][NB];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const uint16_t* __restrict__ src = a.src;
   const uint16_t* __restrict__ wt = a.wt;
+  int t = kq / a.C, c = kq - (kq / a.C) * a.C;
   for (int k0 = 0; k0 < K; k0 += 32) {
-    const int k = k0 + kq;
-    bf16x8 av;
-    uint4 araw = make_uint4(0, 0, 0, 0);
-    int t = 0, c = 0;
-    const bool kin = k < K;
-    if (kin) {
-      t = k / a.C;
-      c = k - t * a.C;
-      if (ra < nrows) {
-        const long sv = gg_source(a, ra, t);
+    const bool kin = k0 + kq < K;
+    bf16x8 av[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      uint4 araw = make_uint4(0, 0, 0, 0);
+      if (kin && rows[i].ok) {
+        const long sv = gg_source(a, rows[i], t);
         if (sv >= 0) araw = *reinterpret_cast<const uint4*>(src + sv * a.src_cs + a.src_c0 + c);
       }
+      av[i] = __builtin_bit_cast(bf16x8, araw);
     }
-    av = __builtin_bit_cast(bf16x8, araw);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       uint4 braw = make_uint4(0, 0, 0, 0);
       if (kin) braw = *reinterpret_cast<const uint4*>(wt + ((size_t)t * a.Npad + j * 16 + (lane & 15)) * a.C + c);
-      acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, __builtin_bit_cast(bf16x8, braw), acc[j], 0, 0, 0);
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, braw);
+#pragma unroll
+      for (int i = 0; i < RT; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv, acc[i][j], 0, 0, 0);
+    }
+    c += 32;
+    while (c >= a.C) {
+      c -= a.C;
+      ++t;
     }
   }
-  // epilogue: rows 4 (lane / 16) + i, column 16 j + lane % 16
+  // epilogue: rows 4 (lane / 16) + i of each row tile, column 16 j + lane % 16
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const int n = j * 16 + (lane & 15);
-    if (n >= a.N) continue;
+  for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long r = row0 + (lane >> 4) * 4 + i;
-      if (r >= nrows) continue;
-      float v = acc[j][i];
-      long dvox = r;
-      int dch = n;
-      if (a.mode == GG_UP_FWD) {
-        // column n = d * Cout + co writes fine voxel 2 q + d, channel co
-        const int d = n / a.up_cout, co = n - d * a.up_cout;
-        const int x = (int)(r % a.W), y = (int)((r / a.W) % a.H), z = (int)(r / ((long)a.W * a.H));
-        dvox = ((long)(2 * z + (d >> 2)) * (2 * a.H) + 2 * y + ((d >> 1) & 1)) * (2 * a.W) + 2 * x + (d & 1);
-        dch = co;
-      }
-      if (a.bias) v += a.bias[dch];
-      if (a.relu) v = fmaxf(v, 0.f);
-      const size_t o = (size_t)dvox * a.dst_cs + a.dst_c0 + dch;
-      if (a.out_f32) {
-        float* d = reinterpret_cast<float*>(a.dst);
-        d[o] = a.accumulate ? d[o] + v : v;
-      } else {
-        uint16_t* d = reinterpret_cast<uint16_t*>(a.dst);
-        d[o] = f2bf(a.accumulate ? bf2f(d[o]) + v : v);
+    for (int j = 0; j < NB; ++j) {
+      const int n = j * 16 + (lane & 15);
+      if (n >= a.N) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long r = row0 + rt * 16 + (lane >> 4) * 4 + i;
+        if (r >= nrows) continue;
+        float v = acc[rt][j][i];
+        long dvox = r;
+        int dch = n;
+        if (a.mode == GG_UP_FWD) {
+          // column n = d * Cout + co writes fine voxel 2 q + d, channel co
+          const int d = n / a.up_cout, co = n - d * a.up_cout;
+          const GgRow g = gg_row(a, r, nrows);
+          dvox = ((long)(2 * g.z + (d >> 2)) * (2 * a.H) + 2 * g.y + ((d >> 1) & 1)) * (2 * a.W) + 2 * g.x + (d & 1);
+          dch = co;
+        }
+        if (a.bias) v += a.bias[dch];
+        if (a.relu) v = fmaxf(v, 0.f);
+        const size_t o = (size_t)dvox * a.dst_cs + a.dst_c0 + dch;
+        if (a.out_f32) {
+          float* d = reinterpret_cast<float*>(a.dst);
+          d[o] = a.accumulate ? d[o] + v : v;
+        } else {
+          uint16_t* d = reinterpret_cast<uint16_t*>(a.dst);
+          d[o] = f2bf(a.accumulate ? bf2f(d[o]) + v : v);
+        }
       }
     }
   }
@@ -182,7 +205,7 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
       uint16_t sv = 0;
       if (r < r1 && c < a.C) {
         long svox = r;
-        if (a.mode == GG_CONV3_FWD) svox = gg_source(ga, r, t);
+        if (a.mode == GG_CONV3_FWD) svox = gg_source(ga, gg_row(ga, r, r + 1), t);
         if (svox >= 0) sv = a.s[(size_t)svox * a.s_cs + a.s_c0 + c];
       }
       ss[rr][c] = sv;
@@ -364,15 +387,17 @@ static int ew_grid(size_t n) {
 
 hipError_t launch_gather_gemm(const GatherGemmArgs& a, hipStream_t s) {
   const long nrows = (long)a.D * a.H * a.W;
-  const dim3 g((unsigned)((nrows + 63) / 64));
+  // row tiles per wave: enough MFMAs per loaded fragment without exceeding the
+  // accumulator budget (RT * NB <= 8 tiles of 16 x 16)
+  auto grid = [&](int rt) { return dim3((unsigned)((nrows + 64 * rt - 1) / (64 * rt))); };
   switch (a.Npad / 16) {
-    case 1: hipLaunchKernelGGL(k_gather_gemm<1>, g, dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL(k_gather_gemm<2>, g, dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL(k_gather_gemm<4>, g, dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL(k_gather_gemm<8>, g, dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL(k_gather_gemm<16>, g, dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL(k_gather_gemm<32>, g, dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL(k_gather_gemm<64>, g, dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_gather_gemm<1, 4>), grid(4), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_gather_gemm<2, 4>), grid(4), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL((k_gather_gemm<4, 2>), grid(2), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_gather_gemm<8, 1>), grid(1), dim3(256), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_gather_gemm<16, 1>), grid(1), dim3(256), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_gather_gemm<32, 1>), grid(1), dim3(256), 0, s, a); break;
+    case 64: hipLaunchKernelGGL((k_gather_gemm<64, 1>), grid(1), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
