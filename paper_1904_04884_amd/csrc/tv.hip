@@ -10,15 +10,17 @@
 //
 // Temporal blocking.  A dual step at voxel i reads the previous dual at
 // offsets in {-1, 0, 1} per axis, so L fused steps need an L-voxel halo.  A
-// block owns a 64 x (8 Q) tile in (x, y) -- one wavefront lane per x, Q rows of
-// y per lane, 8 wavefronts stacked in y -- and streams through z.  The L steps
+// block owns a 64 x (W Q) tile in (x, y) -- one wavefront lane per x, Q = 4
+// rows of y per lane, W = 12 wavefronts stacked in y -- and streams through z
+// (one block per CU at up to 170 VGPRs).  The L steps
 // form a pipeline along z: step l consumes the dual of step l-1 one plane
 // behind it and keeps in registers, per point, the previous plane's dual and
 // primal values.  Neighbours along x move with DPP wave shifts, along y through
 // registers within a lane and through double-buffered LDS rows between
-// wavefronts (one barrier per step and plane).  Points within L of the tile
-// edge are computed but not stored; tiles overlap by 2L.  The z-range is cut
-// into chunks with an L+1 plane margin so that the grid fills the device.
+// wavefronts (one barrier per step and plane).  A kernel compiled for up to H
+// fused steps has an H-voxel halo: points within H of the tile edge are
+// computed but not stored, and tiles overlap by 2H.  The z-range is cut into
+// chunks with an L+1 plane margin so that the grid fills the device.
 //
 // Boundaries: the z-component of the dual is exactly zero on the last plane
 // (its z-difference is zero there, from p = 0 on) and the state below the first
