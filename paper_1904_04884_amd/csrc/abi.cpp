@@ -271,9 +271,16 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
   const size_t hspec = m * ny * sizeof(float2);
   chunking(p, col_blocks > 0 ? col_blocks : p->tune.col_blocks, &L.nchunk, &L.ppc);
   size_t off = 256;  // slack so the base can be aligned up
+  // Successive buffers are staggered by 37 x 256 bytes (cycling over 16): the
+  // volumes are powers of two in size, and buffers a whole number of GiB apart
+  // send the same-index accesses of kernels that stream several of them at once
+  // (the TV pass reads v and three dual planes and writes three) to the same
+  // memory channels.  Any stagger that is not a multiple of 2 MiB helps; this
+  // one made the prox 5 % faster at 1024^2 x 256.
+  int nbuf = 0;
   auto take = [&](size_t bytes) {
     size_t o = off;
-    off = align_up(off + bytes);
+    off = align_up(off + bytes) + (size_t)(++nbuf % 16) * 37 * 256;
     return o;
   };
   if (op == RI_OP_FORWARD || op == RI_OP_SOLVE) {
