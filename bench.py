@@ -59,9 +59,10 @@ def measured_traffic(tuning):
         if kv.get("tv_source_sha256") != digest:
             return None
         want = "%d,%d" % (tuning["tv_levels"], tuning["tv_blocks"])   # the TV pass's launch shape
-        if kv.get("tv_tuning") != want:
-            return None
-        return float(kv["traffic_bytes_per_dispatch"])
+        if kv.get("tv_tuning") == want:
+            return float(kv["traffic_bytes_per_dispatch"])
+        other = kv.get("traffic_bytes_per_dispatch[%s]" % want)       # further profiled shapes
+        return float(other) if other is not None else None
     except (OSError, KeyError, ValueError):
         return None
 
