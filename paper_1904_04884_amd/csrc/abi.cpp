@@ -237,10 +237,10 @@ struct Layout {
   size_t spec = 0, gp = 0, gi = 0, th = 0;                 // spectra (float2)
   size_t ax0 = 0, ax1 = 0;                                 // holograms (float)
   size_t rowflag = 0, planeflag = 0;                       // bytes
-  size_t pdfit = 0, psum = 0, ptv = 0, hist = 0;           // doubles
+  size_t pdfit = 0, psum = 0, ptv = 0, qsum = 0, qtv = 0, hist = 0;  // doubles
   size_t state = 0;
   int nchunk = 1, ppc = 1;
-  int n_dfit = 0, n_obj = 0;
+  int n_dfit = 0, n_obj = 0, n_prox = 0;  // n_prox: bound over every TV tuning
 };
 
 static size_t align_up(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -308,6 +308,9 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
     L.pdfit = take((size_t)L.n_dfit * sizeof(double));
     L.psum = take((size_t)L.n_obj * sizeof(double));
     L.ptv = take((size_t)L.n_obj * sizeof(double));
+    L.n_prox = tv_blocks_bound((int)nx, (int)ny, (int)nz);
+    L.qsum = take((size_t)L.n_prox * sizeof(double));
+    L.qtv = take((size_t)L.n_prox * sizeof(double));
     L.hist = take((size_t)kHistCap * sizeof(double));
     L.state = take(sizeof(SolveState));
   }
@@ -560,6 +563,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   oa.rowflag = rowflag;
   oa.psum = at<double>(c.ws, L.psum);
   oa.ptv = at<double>(c.ws, L.ptv);
+  oa.first_only = 1;
   oa.st = c.st;
   // A x_it (skipping empty rows and planes unless dense)
   RowsR2CArgs& ra = I.fwd_rows;
@@ -604,6 +608,9 @@ static IterArgs iteration_args(const SolveCtx& c) {
   sa.psum = at<double>(c.ws, L.psum);
   sa.ptv = at<double>(c.ws, L.ptv);
   sa.n_obj = L.n_obj;
+  sa.qsum = at<double>(c.ws, L.qsum);
+  sa.qtv = at<double>(c.ws, L.qtv);
+  sa.n_prox = tv_pass_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks);
   sa.hist = at<double>(c.ws, L.hist);
   RowsR2CArgs& rr = I.resid;
   rr.ax0 = at<float>(c.ws, L.ax0);
@@ -642,6 +649,8 @@ static IterArgs iteration_args(const SolveCtx& c) {
   for (int k = 0; k < 3; ++k) pa.pb[k] = at<float>(c.ws, L.pb[k]);
   pa.rowflag = rowflag;
   pa.planeflag = planeflag;
+  pa.psum = at<double>(c.ws, L.qsum);
+  pa.ptv = at<double>(c.ws, L.qtv);
   pa.nx = nx; pa.ny = ny; pa.nz = nz;
   pa.inner_iters = c.inner;
   pa.nonneg = c.nonneg;

@@ -538,6 +538,7 @@ constexpr int kObjThreads = 256;
 __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
   __shared__ double red[2][16];
   if (solve_done(a.st)) return;
+  if (a.first_only && a.st != nullptr && a.st->it > 0) return;
   const float* x = a.x0;
   if (a.st != nullptr) {
     // runs before the scalar kernel of the iteration: the iterate is slot it % 3
@@ -627,9 +628,14 @@ __device__ __forceinline__ void scalars_body(const ScalarArgs& a, int, int) {
   if (st->done) return;
   double d = 0.0, s = 0.0, t = 0.0;
   for (int i = threadIdx.x; i < a.n_dfit; i += kScalarThreads) d += a.pdfit[i];
-  for (int i = threadIdx.x; i < a.n_obj; i += kScalarThreads) {
-    s += a.psum[i];
-    t += a.ptv[i];
+  // sum(x_it) and TV(x_it): from the prox that produced x_it, or for x_0 from k_obj
+  const bool from_prox = a.qsum != nullptr && st->it > 0;
+  const double* ps = from_prox ? a.qsum : a.psum;
+  const double* pt = from_prox ? a.qtv : a.ptv;
+  const int n_obj = from_prox ? a.n_prox : a.n_obj;
+  for (int i = threadIdx.x; i < n_obj; i += kScalarThreads) {
+    s += ps[i];
+    t += pt[i];
   }
   d = block_sum<kScalarThreads>(d, red[0]);
   __syncthreads();

@@ -192,6 +192,7 @@ struct ObjArgs {
   const uint8_t* rowflag;     // nullable: skip rows whose neighbourhood is empty
   double* psum; double* ptv;  // [nblocks]
   const SolveState* st;
+  int first_only;             // solver: only x_0 (later iterates are summed by the prox)
   int gx, gy;
 };
 dim3 grid_obj(int nx, int ny, int nz);
@@ -204,7 +205,8 @@ hipError_t launch_obj_batched(const ObjArgs* args, BatchMap map, int nblocks, hi
 struct ScalarArgs {
   SolveState* st;
   const double* pdfit; int n_dfit;
-  const double* psum; const double* ptv; int n_obj;
+  const double* psum; const double* ptv; int n_obj;      // objective partials of x_0
+  const double* qsum; const double* qtv; int n_prox;     // ... of x_it, it > 0 (prox final pass)
   double* hist;   // [kHistCap]
   int gx, gy;
 };
@@ -246,6 +248,7 @@ struct ProxArgs {
   float* pa[3];        // dual components px, py, pz (ping)
   float* pb[3];        // dual components (pong)
   uint8_t* rowflag; uint8_t* planeflag;  // nullable: set where x != 0
+  double* psum; double* ptv;             // nullable: per-block sum(x), TV(x) of the result
   int nx, ny, nz;
   int inner_iters;
   int nonneg;
@@ -260,6 +263,9 @@ hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
 int prox_passes(int inner_iters, double tau, int levels);
 // Planes per block of a pass for the given tuning (distinct values = distinct grids).
 int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks);
+// Blocks of one pass for the given tuning, and a bound over every tuning.
+int tv_pass_blocks(int nx, int ny, int nz, int levels, int blocks);
+int tv_blocks_bound(int nx, int ny, int nz);
 
 // Batched prox: the argument structs of every pass of every frame are built on
 // the host (prox_pass_args) and uploaded; launch p runs pass p of all frames.

@@ -49,6 +49,7 @@ struct TvPassArgs {
   const float* pin[3];            // dual read by the first step (ignored when first)
   float* pout[3];                 // dual written by the last step (unless final)
   uint8_t* rowflag; uint8_t* planeflag;  // final pass: set where x != 0 (nullable)
+  double* psum; double* ptv;      // final pass: per-block sum(x) and TV(x) of the stored x (nullable)
   const SolveState* st;
   int nx, ny, nz;
   int levels;                     // fused dual steps in this pass (<= H, <= H-1 when final)
@@ -82,15 +83,26 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, f
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
 }
 
-// Pass body.  EDGE: the tile touches the volume boundary, so every access and
-// every difference is masked; interior tiles (most of them) skip the masks.
-// FIRST: the incoming dual is zero (nothing is read).  FINAL: the last pass
-// (primal recovery and output) instead of storing the dual.
+// Pass body.  H: the halo (tile geometry); LV: register slots for fused steps
+// (H, or H - 1 on the final pass, which fuses at most H - 1).  EDGE: the tile
+// touches the volume boundary, so every access and every difference is masked;
+// interior tiles (most of them) skip the masks.  FIRST: the incoming dual is
+// zero (nothing is read).  FINAL: the last pass (primal recovery and output)
+// instead of storing the dual.
+//
+// With psum / ptv set, the final pass also sums x and its isotropic TV (forward
+// differences, zero at the last index of each axis) over the points it stores.
+// The differences of a plane need the next plane, so a plane's terms are taken
+// when the next one is output (the last plane of the volume after the loop);
+// the x+1 neighbour comes by a wave shift, the y+1 neighbour from the next row
+// of the lane or, for the last row, from the next wave through LDS.  Every
+// neighbour lies in the computed tile: the final pass fuses at most H - 1
+// steps, so x is exact one point beyond the stored region.
 
-template <int H, bool EDGE, bool FIRST, bool FINAL>
+template <int H, int LV, bool EDGE, bool FIRST, bool FINAL>
 __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int bz,
                                              float (*s_py)[2][kTvWaves][64], float (*s_ut)[2][kTvWaves][64],
-                                             float* s_v) {
+                                             float* s_v, float (*s_x)[kTvWaves][64], double (*s_red)[kTvWaves]) {
   constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
   const float* __restrict__ v = uniform_ptr(A.v ? A.v : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->prev));
@@ -124,9 +136,9 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     offs[q] = ys[q] ? off[q] : kTvOff;
   }
   // per fused step: previous plane's dual (3) and primal (1); final stage: previous p_z
-  float Pp[H][Q][3], Up[H][Q], PzF[Q];
+  float Pp[LV][Q][3], Up[LV][Q], PzF[Q];
 #pragma unroll
-  for (int l = 0; l < H; ++l)
+  for (int l = 0; l < LV; ++l)
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
       Pp[l][q][0] = Pp[l][q][1] = Pp[l][q][2] = 0.f;
@@ -134,6 +146,33 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     }
 #pragma unroll
   for (int q = 0; q < Q; ++q) PzF[q] = 0.f;
+  // objective pieces (final pass): x of the previous output plane, FP64 sums
+  const bool obj = FINAL && A.psum != nullptr;
+  float Xp[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) Xp[q] = 0.f;
+  double s_acc = 0.0, t_acc = 0.0;
+  // terms of the plane held in Xp; xn: the next plane (hz: it exists), slot:
+  // the LDS slot holding the first row of every wave of the Xp plane
+  auto accumulate = [&](const float (&xn)[Q], bool hz, int slot) {
+    float ss = 0.f, tt = 0.f;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const float x0 = Xp[q];
+      const float xr = dpp_from_right(x0);
+      const float xu = (q < Q - 1) ? Xp[q + 1] : s_x[slot][wv < NW - 1 ? wv + 1 : wv][lane];
+      const float gx = xhi ? xr - x0 : 0.f;
+      const float gy = yhi[q] ? xu - x0 : 0.f;
+      const float gz = hz ? xn[q] - x0 : 0.f;
+      // per-voxel norm in FP32 (the hardware square root, within 1 ulp, not
+      // the correctly rounded sequence), running sums in FP64
+      const float t = __builtin_amdgcn_sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
+      ss += ys[q] ? x0 : 0.f;
+      tt += ys[q] ? t : 0.f;
+    }
+    s_acc += (double)ss;
+    t_acc += (double)tt;
+  };
 
   // Input planes are prefetched two ahead into two register sets used in
   // turn (the z loop is unrolled by two so that each set keeps its registers
@@ -257,6 +296,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       s_py[H][par][wv][lane] = c3[Q - 1][1];
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rx = plane_rsrc(xo, m, sz);
+      float xs[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         float u = vm[q];
@@ -275,6 +315,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         } else {
           xv = copysignf(fmaxf(fabsf(u) - A.thr, 0.f), u);
         }
+        xs[q] = xv;
         const bool st = zstore && ys[q];
         if (zstore) buf_st(rx, offs[q], xv);
         if (A.rowflag != nullptr) {
@@ -284,6 +325,13 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
             A.planeflag[m] = 1;
           }
         }
+      }
+      if (obj) {
+        // plane m - 1 is complete now; its first rows went to slot par ^ 1
+        if (m - 1 >= zb && m - 1 < ze) accumulate(xs, true, par ^ 1);
+        s_x[par][wv][lane] = xs[0];  // read after the next output's barrier
+#pragma unroll
+        for (int q = 0; q < Q; ++q) Xp[q] = xs[q];
       }
     }
   };
@@ -303,7 +351,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     }
     if (a1 + 2 < zl) load_plane(P, a1 + 2);
 #pragma unroll
-    for (int l = 0; l < H; ++l) {
+    for (int l = 0; l < LV; ++l) {
       if (l >= L) break;
       const int a = a1 - l;
       if (a < zs) break;                  // this and the later steps are idle
@@ -330,7 +378,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
 #pragma unroll
     for (int q = 0; q < Q; ++q) c3[q][0] = c3[q][1] = c3[q][2] = 0.f;
 #pragma unroll
-    for (int l = 0; l < H; ++l) {
+    for (int l = 0; l < LV; ++l) {
       if (l >= L) break;
       const int a = a1 - l;
       if (a > zl) continue;               // already flushed
@@ -341,6 +389,35 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     const int m = a1 - L;
     if (m >= zs && m < zl) output(m, par, c3);
   }
+  if constexpr (FINAL) {
+    if (obj) {
+      if (ze == nz) {
+        // the last plane of the volume: no plane above it (its z-difference is 0)
+        __syncthreads();
+        accumulate(Xp, false, (nsteps - 1) & 1);
+      }
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        s_acc += __shfl_xor(s_acc, off, 64);
+        t_acc += __shfl_xor(t_acc, off, 64);
+      }
+      if (lane == 0) {
+        s_red[0][wv] = s_acc;
+        s_red[1][wv] = t_acc;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double s = 0.0, t = 0.0;
+        for (int w = 0; w < NW; ++w) {
+          s += s_red[0][w];
+          t += s_red[1][w];
+        }
+        const size_t blk = (size_t)bx + (size_t)A.gx * ((size_t)by + (size_t)A.gy * bz);
+        A.psum[blk] = s;
+        A.ptv[blk] = t;
+      }
+    }
+  }
 }
 
 template <int H>
@@ -348,12 +425,15 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
   __shared__ float s_py[H + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step, parity
   __shared__ float s_ut[H][2][kTvWaves][64];      // top-row u per wave, per step, parity
   __shared__ float s_v[(H + 1) * kTvQ * kTvWaves * 64];  // v ring, thread-private
+  __shared__ float s_x[2][kTvWaves][64];          // final pass: first-row x per wave, parity
+  __shared__ double s_red[2][kTvWaves];           // final pass: per-wave sums
   if (A.st != nullptr && A.st->done) return;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;
   const int x0 = bx * IX - H, y0 = by * IY - H;
   // interior tile: every point of the region and its +-1 neighbours lie inside
   const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
-#define RIHVR_TV_BODY(E, F, FIN) tv_pass_body<H, E, F, FIN>(A, bx, by, bz, s_py, s_ut, s_v)
+#define RIHVR_TV_BODY(E, F, FIN) \
+  tv_pass_body<H, (FIN) ? H - 1 : H, E, F, FIN>(A, bx, by, bz, s_py, s_ut, s_v, s_x, s_red)
   if (A.final_) {
     if (A.first) {
       if (interior) RIHVR_TV_BODY(false, true, true);
@@ -423,6 +503,20 @@ int prox_passes(int inner_iters, double tau, int levels) {
 
 size_t tv_pass_args_size() { return sizeof(TvPassArgs); }
 
+int tv_pass_blocks(int nx, int ny, int nz, int levels, int blocks) {
+  dim3 g;
+  int zc = 0;
+  pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks, &g, &zc);
+  return (int)(g.x * g.y * g.z);
+}
+
+int tv_blocks_bound(int nx, int ny, int nz) {
+  // the most tiles (deepest halo) times the most z chunks pass_grid makes
+  const int tx = (nx + (kTvRX - 2 * kTvLevelsMax) - 1) / (kTvRX - 2 * kTvLevelsMax);
+  const int ty = (ny + (kTvRY - 2 * kTvLevelsMax) - 1) / (kTvRY - 2 * kTvLevelsMax);
+  return tx * ty * std::max(1, nz / 16);
+}
+
 int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks) {
   dim3 g;
   int zc = 0;
@@ -446,6 +540,8 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   for (int k = 0; k < 3; ++k) a.vol[k] = pa.vol[k];
   a.rowflag = pa.rowflag;
   a.planeflag = pa.planeflag;
+  a.psum = pa.psum;
+  a.ptv = pa.ptv;
   a.st = pa.st;
   a.nx = pa.nx; a.ny = pa.ny; a.nz = pa.nz;
   a.nonneg = pa.nonneg;

@@ -10,7 +10,7 @@ import json
 import numpy as np
 import pytest
 
-from oracle import optics, prox
+from oracle import fista, optics, prox
 from paper_1904_04884_amd import rihvr, scenes
 
 pytestmark = pytest.mark.gpu
@@ -150,7 +150,8 @@ def test_batched_mixed_tunings_match_single(torch_cuda, plan_of, graph):
     iters = [6, 4, 6, 9, 5]
     rng = np.random.default_rng(17)
     bs = [to_dev(torch, rng.standard_normal((p.geom.ny, p.geom.nx))) for p in ps]
-    singles = [p.solve(b, 0.05, 0.02, k, 5)[0].clone() for p, b, k in zip(ps, bs, iters)]
+    runs = [p.solve(b, 0.05, 0.02, k, 5) for p, b, k in zip(ps, bs, iters)]
+    singles = [r[0].clone() for r in runs]
     flags = 0 if graph else rihvr.RI_SOLVE_NO_GRAPH
     params = [p.solve_params(0.05, 0.02, k, 5, flags=flags) for p, k in zip(ps, iters)]
     handles = [p.handle for p in ps]
@@ -165,3 +166,37 @@ def test_batched_mixed_tunings_match_single(torch_cuda, plan_of, graph):
     for a, sgl in zip(xs, singles):
         assert torch.equal(a, sgl)
     assert [r.iters for r in reps] == iters
+    assert [r.objective for r in reps] == [r[1]["objective"] for r in runs]
+
+
+@pytest.mark.parametrize("shape,tuning", [
+    ((64, 48, 6), dict(tv_levels=2, tv_blocks=64)),
+    ((96, 48, 7), dict(tv_levels=3)),
+    ((192, 96, 40), dict(tv_levels=4, tv_blocks=6144)),
+    ((192, 96, 40), dict(tv_levels=4, tv_blocks=64)),
+    ((128, 128, 20), dict(tv_levels=3, tv_blocks=768)),
+])
+def test_objective_terms_summed_by_the_prox(torch_cuda, plan_of, shape, tuning):
+    """From the first iterate after x_0 on, sum(x) and TV(x) come from the final
+    TV pass (FP64 partials per block over the points each tile stores, the
+    differences of a tile's last row and plane taken from its halo).  The
+    regularizer part of the reported objective, F - 1/2||A x - b||^2 with the
+    data term recomputed from the library's own A x, equals the oracle's
+    l1 sum(x) + tv TV(x) of the same x: interior and edge tiles, one and
+    several z chunks, every fusion depth."""
+    torch = torch_cuda
+    g = geom(*shape)
+    p = plan_of(g, **tuning)
+    rng = np.random.default_rng(7)
+    xt = np.where(rng.random(g.shape) < 0.01, rng.uniform(0.5, 1.0, g.shape), 0.0)
+    b = optics.forward(g, xt).astype(np.float32)
+    b64 = b.astype(np.float64)
+    l1, tv = 0.02, 0.05
+    for iters in (1, 3):
+        x, rep, _ = p.solve(to_dev(torch, b), l1, tv, iters, 5)
+        assert rep["iters"] == iters
+        d = 0.5 * float(((to_host(p.forward(x)) - b64) ** 2).sum())
+        _, s, t = fista.objective_terms(g, to_host(x), b64, l1, tv)
+        reg = l1 * s + tv * t
+        assert reg > 0.05 * rep["objective"]   # the check sees the regularizer
+        assert rep["objective"] - d == pytest.approx(reg, rel=2e-6), (iters, rep["objective"] - d, reg)
