@@ -35,11 +35,12 @@ __host__ __device__ constexpr int kRowsPerBlock(int m) {
 }
 // Column transforms: points per thread, and columns per tile such that a block
 // has at most 512 threads (256 VGPRs per lane available, no spills) and the tile
-// plus one spare column fits the 160 KiB of LDS.
+// plus three column-sized tables (a column buffer, the twiddles, the Nyquist
+// column's theta) and 4 KiB of flags fit the 160 KiB of LDS.
 __host__ __device__ constexpr int kColP(int ny) { return (ny % 3 == 0) ? 12 : (ny >= 2048 ? 16 : 8); }
 __host__ __device__ constexpr int kColW(int ny) {
   int w = 16;
-  while (w > 1 && ((ny / kColP(ny)) * w > 512 || (size_t)ny * (w + 1) * 8 > 160 * 1024)) w /= 2;
+  while (w > 1 && ((ny / kColP(ny)) * w > 512 || (size_t)ny * (w + 3) * 8 + 4096 > 160 * 1024)) w /= 2;
   return w;
 }
 
@@ -220,6 +221,38 @@ __device__ __forceinline__ void rows_c2r_body(const RowsC2RArgs& a, int bx, int 
 }
 
 // ---------------------------------------------------------------------------
+// Column-kernel helpers.  The column transforms run once per plane with the
+// same twiddles, so each block copies the table into LDS once: read from
+// global memory inside the passes, every twiddle load also waits for the
+// prefetched tile of the next plane (vector loads complete in order).  For the
+// same reason the tile loads are branch-free buffer loads: a load whose lane
+// is switched off by a row flag takes an offset past the end of the plane's
+// buffer descriptor and returns zero.
+// ---------------------------------------------------------------------------
+constexpr unsigned kColOff = 0x80000000u;   // past every plane descriptor: reads 0
+constexpr int kColPlaneFlags = 2048;        // plane flags of a chunk staged in LDS
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t spec_rsrc(const float2* plane, size_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<float2*>(plane), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float2 buf_ld2(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  const auto u = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+  return make_float2(__uint_as_float(u[0]), __uint_as_float(u[1]));
+}
+template <int NY>
+__device__ __forceinline__ void stage_twiddles(float2* s_tw, const float2* __restrict__ tw) {
+  for (int i = threadIdx.x; i < NY; i += blockDim.x) s_tw[i] = tw[i];
+}
+// theta of the Nyquist column (kx = m), which column 0 pairs with; only the
+// block holding column 0 needs it.
+template <int NY>
+__device__ __forceinline__ void stage_theta_nyquist(double* s_thn, const double* __restrict__ theta, int m,
+                                                    bool needed) {
+  if (needed)
+    for (int i = threadIdx.x; i < NY; i += blockDim.x) s_thn[i] = theta[(size_t)i * (m + 1) + m];
+}
+
+// ---------------------------------------------------------------------------
 // Forward column pass with the propagation filter and the sum over planes.
 // Block: W columns x TC threads per column (TC = NY / P).
 // ---------------------------------------------------------------------------
@@ -236,12 +269,17 @@ __device__ __forceinline__ void fwd_cols_body_direct(const FwdColsArgs& a, int b
   const PlanTables& pt = a.pt;
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
+  __shared__ float2 s_tw[NY];
+  __shared__ double s_thn[NY];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
   const int kx = bx * W + w;
   const bool colok = kx < m;           // tiles may overhang the last column
   const bool col0 = (kx == 0);
+  // first read after the loop's first barrier
+  stage_twiddles<NY>(s_tw, pt.tw_col);
+  stage_theta_nyquist<NY>(s_thn, pt.theta, m, bx == 0);
   double th[P];
 #pragma unroll
   for (int s = 0; s < P; ++s) th[s] = colok ? pt.theta[(size_t)(q + s * TC) * (m + 1) + kx] : 0.0;
@@ -260,7 +298,7 @@ __device__ __forceinline__ void fwd_cols_body_direct(const FwdColsArgs& a, int b
       lds[y * W + w] = on ? src[(size_t)y * m] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+    fft_lds<NY, P, W, 1, false>(lds + w, q, s_tw);
     const double2 zc = pt.zc[j];
 #pragma unroll
     for (int s = 0; s < P; ++s) {
@@ -271,7 +309,7 @@ __device__ __forceinline__ void fwd_cols_body_direct(const FwdColsArgs& a, int b
         acc[s].x += c * v.x;
         acc[s].y += c * v.y;
       } else {
-        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float cn = phase_cos(zc.x, zc.y, s_thn[y]);
         const float2 vn = cconj(lds[((NY - y) % NY) * W]);
         const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
         acc[s].x += ca * v.x + cb * vn.x;
@@ -298,6 +336,9 @@ __device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int 
   static_assert(W * TC >= NFW, "one flag dword per thread");
   __shared__ float2 lds[NY * W];
   __shared__ uint32_t lds_fl[NFW];
+  __shared__ float2 s_tw[NY];
+  __shared__ double s_thn[NY];
+  __shared__ uint8_t s_pf[kColPlaneFlags];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
@@ -314,23 +355,35 @@ __device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int 
   for (int s = 0; s < P; ++s) acc[s] = make_float2(0.f, 0.f);
   const int j0 = by * a.planes_per_chunk;
   const int j1 = min(a.nz, j0 + a.planes_per_chunk);
+  // the chunk's plane flags (planes past the staged range count as occupied)
+  const bool pflags = a.planeflag != nullptr;
+  if (pflags)
+    for (int i = threadIdx.x; i < min(j1 - j0, kColPlaneFlags); i += blockDim.x) s_pf[i] = a.planeflag[j0 + i];
+  stage_twiddles<NY>(s_tw, pt.tw_col);
+  stage_theta_nyquist<NY>(s_thn, pt.theta, m, bx == 0);
+  __syncthreads();
   auto next_plane = [&](int j) {
-    if (a.planeflag != nullptr)
-      while (j < j1 && a.planeflag[j] == 0) ++j;
+    if (pflags)
+      while (j < j1 && j - j0 < kColPlaneFlags && s_pf[j - j0] == 0) ++j;
     return j;
   };
   auto load_flagword = [&](int j) -> uint32_t {
     return reinterpret_cast<const uint32_t*>(a.rowflag + (size_t)j * NY)[threadIdx.x];
   };
   float2 nv[P];  // tile of the next plane, in flight
+  const size_t plane_bytes = (size_t)NY * m * sizeof(float2);
   auto load_tile = [&](int j) {
-    const float2* src = a.t + (size_t)j * NY * m + kx;
+    const __amdgpu_buffer_rsrc_t r = spec_rsrc(a.t + (size_t)j * NY * m, plane_bytes);
+    // offsets first (the flag bytes are read even when unused), then the loads
+    unsigned o[P];
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const int y = q + s * TC;
-      const bool on = colok && (!flags || fl8[y] != 0);
-      nv[s] = on ? src[(size_t)y * m] : make_float2(0.f, 0.f);
+      const bool on = colok & (!flags | (fl8[y] != 0));
+      o[s] = on ? (unsigned)((y * m + kx) * sizeof(float2)) : kColOff;
     }
+#pragma unroll
+    for (int s = 0; s < P; ++s) nv[s] = buf_ld2(r, o[s]);
   };
   int j = next_plane(j0);
   int jn = j < j1 ? next_plane(j + 1) : j1;
@@ -352,7 +405,7 @@ __device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int 
     if (flags && jnn < j1 && threadIdx.x < NFW) flw = load_flagword(jnn);
     __syncthreads();
     if (jn < j1) load_tile(jn);
-    fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+    fft_lds<NY, P, W, 1, false>(lds + w, q, s_tw);
     const double2 zc = pt.zc[j];
 #pragma unroll
     for (int s = 0; s < P; ++s) {
@@ -363,7 +416,7 @@ __device__ __forceinline__ void fwd_cols_body(const FwdColsArgs& a, int bx, int 
         acc[s].x += c * v.x;
         acc[s].y += c * v.y;
       } else {
-        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float cn = phase_cos(zc.x, zc.y, s_thn[y]);
         const float2 vn = cconj(lds[((NY - y) % NY) * W]);
         const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
         acc[s].x += ca * v.x + cb * vn.x;
@@ -421,19 +474,23 @@ __device__ __forceinline__ void adj_cols_body(const AdjColsArgs& a, int bx, int 
   constexpr int P = kColP(NY), TC = NY / P, W = kColW(NY);
   __shared__ float2 lds[NY * W];
   __shared__ float2 r0[NY];
+  __shared__ float2 s_tw[NY];
+  __shared__ double s_thn[NY];
   if (solve_done(a.st)) return;
   const int w = threadIdx.x % W, q = threadIdx.x / W;
   const int m = a.m;
   const int kx = bx * W + w;
   const bool colok = kx < m;
   const bool col0 = (kx == 0);
+  stage_twiddles<NY>(s_tw, pt.tw_col);
+  stage_theta_nyquist<NY>(s_thn, pt.theta, m, bx == 0);
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const int y = q + s * TC;
     lds[y * W + w] = colok ? a.th[(size_t)y * m + kx] : make_float2(0.f, 0.f);
   }
   __syncthreads();
-  fft_lds<NY, P, W, 1, false>(lds + w, q, pt.tw_col);
+  fft_lds<NY, P, W, 1, false>(lds + w, q, s_tw);
   float2 rh[P];
   double th[P];
 #pragma unroll
@@ -456,7 +513,7 @@ __device__ __forceinline__ void adj_cols_body(const AdjColsArgs& a, int bx, int 
       if (!col0) {
         v = cscale(rh[s], c);
       } else {
-        const float cn = phase_cos(zc.x, zc.y, pt.theta[(size_t)y * (m + 1) + m]);
+        const float cn = phase_cos(zc.x, zc.y, s_thn[y]);
         const float2 vn = cconj(r0[(NY - y) % NY]);
         const float ca = 0.5f * (c + cn), cb = 0.5f * (c - cn);
         v = make_float2(ca * rh[s].x + cb * vn.x, ca * rh[s].y + cb * vn.y);
@@ -464,7 +521,7 @@ __device__ __forceinline__ void adj_cols_body(const AdjColsArgs& a, int bx, int 
       lds[y * W + w] = v;
     }
     __syncthreads();
-    fft_lds<NY, P, W, 1, true>(lds + w, q, pt.tw_col);
+    fft_lds<NY, P, W, 1, true>(lds + w, q, s_tw);
     float2* dst = a.u + (size_t)j * NY * m + kx;
     if (colok) {
 #pragma unroll
@@ -861,16 +918,19 @@ RIHVR_ENTRY_T(k_rows_r2c, rows_r2c_body, RowsR2CArgs, M, kRowsPerBlock(M) * kRow
 RIHVR_ENTRY_T(k_rows_c2r, rows_c2r_body, RowsC2RArgs, M, kRowsPerBlock(M) * kRowThreads(M))
 RIHVR_ENTRY_T(k_adj_rows, adj_rows_body, AdjRowsArgs, M, kRowsPerBlock(M) * kRowThreads(M))
 // Column kernels: adjacent column tiles read the two halves of the same
-// 128-byte lines, so their blocks are placed on the same XCD (shared L2).
+// 128-byte lines, so their blocks are placed on the same XCD (shared L2).  With
+// 8 points per thread the register file is held to 128 VGPRs (4 waves per
+// SIMD: two 8-wave blocks per CU); the larger point counts take what they need.
+__host__ __device__ constexpr int kColWavesPerSimd(int ny) { return kColP(ny) <= 8 ? 4 : 1; }
 #define RIHVR_ENTRY_COLS(NAME, BODY, ARGS, TP, NT)                                                \
   template <int TP>                                                                               \
-  __global__ void __launch_bounds__(NT) NAME(ARGS a) {                                            \
+  __global__ void __launch_bounds__(NT, kColWavesPerSimd(TP)) NAME(ARGS a) {                      \
     const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * blockIdx.y, gridDim.x * gridDim.y);      \
     BODY<TP>(a, t % gridDim.x, t / gridDim.x);                                                    \
   }                                                                                               \
   template <int TP>                                                                               \
-  __global__ void __launch_bounds__(NT) NAME##_b(const ARGS* __restrict__ args,                   \
-                                                 BatchMap map) {                                  \
+  __global__ void __launch_bounds__(NT, kColWavesPerSimd(TP)) NAME##_b(const ARGS* __restrict__ args, \
+                                                                      BatchMap map) {             \
     ARGS a;                                                                                       \
     int bx, by;                                                                                   \
     batch_entry(args, map, a, bx, by);                                                            \
