@@ -59,6 +59,14 @@ struct TvPassArgs {
   int gx, gy;                     // tiles along x and y (the grid of one frame)
 };
 
+// A register copy the compiler keeps (an identity DPP move).  The prefetched
+// plane is copied out of its registers before they are reloaded; left to
+// itself, the compiler renames the consumer onto the loaded registers, loads
+// the next plane into fresh ones and moves them back at the loop's back edge,
+// which waits for every load in flight.
+__device__ __forceinline__ float vcopy(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xE4, 0xf, 0xf, false));
+}
 __device__ __forceinline__ float dpp_from_left(float v) {   // lane i <- lane i-1 (0 at lane 0)
   return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x138, 0xf, 0xf, true));
 }
@@ -344,10 +352,10 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     float c3[Q][3];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      vring(a1, q) = P.v[q];
-      c3[q][0] = FIRST ? 0.f : P.p[q][0];
-      c3[q][1] = FIRST ? 0.f : P.p[q][1];
-      c3[q][2] = FIRST ? 0.f : P.p[q][2];
+      vring(a1, q) = vcopy(P.v[q]);
+      c3[q][0] = FIRST ? 0.f : vcopy(P.p[q][0]);
+      c3[q][1] = FIRST ? 0.f : vcopy(P.p[q][1]);
+      c3[q][2] = FIRST ? 0.f : vcopy(P.p[q][2]);
     }
     if (a1 + 2 < zl) load_plane(P, a1 + 2);
 #pragma unroll
