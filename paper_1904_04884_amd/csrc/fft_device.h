@@ -116,9 +116,25 @@ __host__ __device__ constexpr int points_per_thread(int L) {
   return (L % 3 == 0) ? (L >= 12 ? 12 : L) : (L >= 8 ? 8 : L);
 }
 
+// Ordering point between the LDS writes and reads of a transform: a block
+// barrier, or, when each transform lies inside one wavefront (WAVE), only an
+// ordering of that wave's LDS accesses (the LDS executes one wave's operations
+// in issue order), so that waves holding different transforms never wait for
+// each other.
+template <bool WAVE>
+__device__ __forceinline__ void lds_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One Stockham pass.  `buf` holds the transform with element e at buf[e*S].
 // `tw` is a table exp(-2 pi i m / (L*TWS)), m in [0, L*TWS), read with stride TWS.
-template <int R, int L, int P, int S, int TWS, int p, bool INV>
+template <int R, int L, int P, int S, int TWS, int p, bool INV, bool WAVE>
 __device__ __forceinline__ void stockham_pass(float2* buf, int t, const float2* __restrict__ tw) {
   constexpr int T = L / P;
   constexpr int NB = P / R;
@@ -130,7 +146,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int t, const float2* 
 #pragma unroll
     for (int r = 0; r < R; ++r) v[b][r] = buf[(i + r * (L / R)) * S];
   }
-  __syncthreads();
+  lds_sync<WAVE>();
 #pragma unroll
   for (int b = 0; b < NB; ++b) {
     const int i = t + b * T;
@@ -147,25 +163,25 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int t, const float2* 
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[(j + r * p) * S] = v[b][r];
   }
-  __syncthreads();
+  lds_sync<WAVE>();
 }
 
-template <int L, int P, int S, int TWS, int p, int rem, bool INV>
+template <int L, int P, int S, int TWS, int p, int rem, bool INV, bool WAVE>
 __device__ __forceinline__ void stockham_rest(float2* buf, int t, const float2* __restrict__ tw) {
   if constexpr (rem > 1) {
     constexpr int R = next_radix(rem, P);
-    stockham_pass<R, L, P, S, TWS, p, INV>(buf, t, tw);
-    stockham_rest<L, P, S, TWS, p * R, rem / R, INV>(buf, t, tw);
+    stockham_pass<R, L, P, S, TWS, p, INV, WAVE>(buf, t, tw);
+    stockham_rest<L, P, S, TWS, p * R, rem / R, INV, WAVE>(buf, t, tw);
   }
 }
 
-// Full in-LDS transform of length L (unscaled).  Every thread of the block must
-// call it (it contains barriers); thread t in [0, L/P) of each transform owns
-// P points per pass.
-template <int L, int P, int S, int TWS, bool INV>
+// Full in-LDS transform of length L (unscaled).  Every thread of the block (of
+// the wave, with WAVE) must call it; thread t in [0, L/P) of each transform
+// owns P points per pass.
+template <int L, int P, int S, int TWS, bool INV, bool WAVE = false>
 __device__ __forceinline__ void fft_lds(float2* buf, int t, const float2* __restrict__ tw) {
   static_assert(valid_len(L), "length must be 2^a or 3*2^a");
-  stockham_rest<L, P, S, TWS, 1, L, INV>(buf, t, tw);
+  stockham_rest<L, P, S, TWS, 1, L, INV, WAVE>(buf, t, tw);
 }
 
 }  // namespace rihvr

@@ -33,6 +33,9 @@ __host__ __device__ constexpr int kRowThreads(int m) { return m / points_per_thr
 __host__ __device__ constexpr int kRowsPerBlock(int m) {
   return kRowThreads(m) >= 256 ? 1 : 256 / kRowThreads(m);
 }
+// Row transforms of at most 64 threads lie inside one wavefront each: their
+// passes order LDS within the wave, with no block barrier.
+__host__ __device__ constexpr bool kRowWave(int m) { return kRowThreads(m) <= 64; }
 // Column transforms: points per thread, and columns per tile such that a block
 // has at most 512 threads (256 VGPRs per lane available, no spills) and the tile
 // plus three column-sized tables (a column buffer, the twiddles, the Nyquist
@@ -94,10 +97,15 @@ __device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int 
   constexpr int P = points_per_thread(M), T = M / P, ROWS = kRowsPerBlock(M);
   __shared__ float2 lds[ROWS][M];
   if (solve_done(a.st)) return;
+  constexpr bool WAVE = kRowWave(M);
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int row = bx * ROWS + r;
   const bool active = row < a.nrows && (a.rowflag == nullptr || a.rowflag[row] != 0);
-  if (!__syncthreads_or(active)) return;
+  if constexpr (WAVE) {
+    if (__ballot(active) == 0) return;   // no row of this wave is occupied
+  } else {
+    if (!__syncthreads_or(active)) return;
+  }
   float2* buf = lds[r];
   if (a.mode != 1) {
     const float* xin = a.x;
@@ -126,8 +134,8 @@ __device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int 
       buf[e] = v;
     }
   }
-  __syncthreads();
-  fft_lds<M, P, 1, 2, false>(buf, t, tw);
+  lds_sync<WAVE>();
+  fft_lds<M, P, 1, 2, false, WAVE>(buf, t, tw);
   if (!active) return;  // no barriers below
   float2* dst = a.out + (size_t)row * M;
 #pragma unroll
@@ -151,7 +159,7 @@ __device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int 
 // ---------------------------------------------------------------------------
 // Packed C2R of rows (scaled).  Inverse of k_rows_r2c up to the scale.
 // ---------------------------------------------------------------------------
-template <int M>
+template <int M, bool WAVE>
 __device__ __forceinline__ void c2r_prepare(float2* buf, int t, const float2* __restrict__ tw) {
   constexpr int P = points_per_thread(M), T = M / P;
   float2 zt[P];
@@ -168,10 +176,10 @@ __device__ __forceinline__ void c2r_prepare(float2* buf, int t, const float2* __
       zt[s] = make_float2(sum.x - wd.y, sum.y + wd.x);  // sum + i wd
     }
   }
-  __syncthreads();
+  lds_sync<WAVE>();
 #pragma unroll
   for (int s = 0; s < P; ++s) buf[t + s * T] = zt[s];
-  __syncthreads();
+  lds_sync<WAVE>();
 }
 
 template <int M>
@@ -191,9 +199,9 @@ __device__ __forceinline__ void rows_c2r_body(const RowsC2RArgs& a, int bx, int 
     const int e = t + s * T;
     buf[e] = active ? src[e] : make_float2(0.f, 0.f);
   }
-  __syncthreads();
-  c2r_prepare<M>(buf, t, tw);
-  fft_lds<M, P, 1, 2, true>(buf, t, tw);
+  lds_sync<kRowWave(M)>();
+  c2r_prepare<M, kRowWave(M)>(buf, t, tw);
+  fft_lds<M, P, 1, 2, true, kRowWave(M)>(buf, t, tw);
   if (a.mode == 0) {
     if (!active) return;
     float2* dst = reinterpret_cast<float2*>(a.out) + (size_t)row * M;
@@ -554,9 +562,9 @@ __device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int 
     const int e = t + s * T;
     buf[e] = active ? src[e] : make_float2(0.f, 0.f);
   }
-  __syncthreads();
-  c2r_prepare<M>(buf, t, tw);
-  fft_lds<M, P, 1, 2, true>(buf, t, tw);
+  lds_sync<kRowWave(M)>();
+  c2r_prepare<M, kRowWave(M)>(buf, t, tw);
+  fft_lds<M, P, 1, 2, true, kRowWave(M)>(buf, t, tw);
   if (!active) return;
   if (a.mode == 0) {
     float2* dst = reinterpret_cast<float2*>(a.out) + (size_t)row * M;
