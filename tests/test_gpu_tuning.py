@@ -170,6 +170,8 @@ def test_batched_mixed_tunings_match_single(torch_cuda, plan_of, graph):
 
 
 @pytest.mark.parametrize("shape,tuning", [
+    ((64, 32, 1), dict(tv_levels=4)),
+    ((48, 64, 2), dict(tv_levels=3)),
     ((64, 48, 6), dict(tv_levels=2, tv_blocks=64)),
     ((96, 48, 7), dict(tv_levels=3)),
     ((192, 96, 40), dict(tv_levels=4, tv_blocks=6144)),
