@@ -13,6 +13,8 @@
 //   A (16 x 32): row l % 16, reduction elements 8 (l / 16) .. 8 (l / 16) + 7
 //   B (32 x 16): column l % 16, reduction elements 8 (l / 16) .. + 7
 //   D (16 x 16): rows 4 (l / 16) .. 4 (l / 16) + 3, column l % 16
+#include <type_traits>
+
 #include "unet_internal.h"
 
 namespace rihvr {
@@ -47,34 +49,46 @@ __device__ __forceinline__ GgRow gg_row(const GatherGemmArgs& a, long r, long nr
 }
 
 // Source voxel (linear index at the source resolution) of a row for tap t, or -1.
-__device__ __forceinline__ long gg_source(const GatherGemmArgs& a, const GgRow& g, int t) {
+template <int MODE>
+__device__ __forceinline__ long gg_source_m(const GatherGemmArgs& a, const GgRow& g, int t) {
   const int D = a.D, H = a.H, W = a.W;  // row grid
+  if constexpr (MODE == GG_CONV3_FWD || MODE == GG_CONV3_BWD) {
+    int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;  // tap t of the 3x3x3 stencil
+    if constexpr (MODE == GG_CONV3_BWD) { dz = -dz; dy = -dy; dx = -dx; }
+    const int zz = g.z + dz, yy = g.y + dy, xx = g.x + dx;
+    if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) return -1;
+    return ((long)zz * H + yy) * W + xx;
+  } else if constexpr (MODE == GG_UP_BWD) {
+    // row (z, y, x) is a coarse voxel; tap t = dz*4 + dy*2 + dx selects the fine voxel
+    const int zz = 2 * g.z + (t >> 2), yy = 2 * g.y + ((t >> 1) & 1), xx = 2 * g.x + (t & 1);
+    return ((long)zz * (2 * H) + yy) * (2 * W) + xx;
+  } else {  // GG_UP_FWD, GG_POINT
+    return ((long)g.z * H + g.y) * W + g.x;
+  }
+}
+__device__ __forceinline__ long gg_source(const GatherGemmArgs& a, const GgRow& g, int t) {
   switch (a.mode) {
-    case GG_CONV3_FWD:
-    case GG_CONV3_BWD: {
-      int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;  // tap t of the 3x3x3 stencil
-      if (a.mode == GG_CONV3_BWD) { dz = -dz; dy = -dy; dx = -dx; }
-      const int zz = g.z + dz, yy = g.y + dy, xx = g.x + dx;
-      if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) return -1;
-      return ((long)zz * H + yy) * W + xx;
-    }
+    case GG_CONV3_FWD: return gg_source_m<GG_CONV3_FWD>(a, g, t);
+    case GG_CONV3_BWD: return gg_source_m<GG_CONV3_BWD>(a, g, t);
+    case GG_UP_BWD: return gg_source_m<GG_UP_BWD>(a, g, t);
     case GG_UP_FWD:
-    case GG_POINT:
-      return ((long)g.z * H + g.y) * W + g.x;
-    case GG_UP_BWD: {
-      // row (z, y, x) is a coarse voxel; tap t = dz*4 + dy*2 + dx selects the fine voxel
-      const int zz = 2 * g.z + (t >> 2), yy = 2 * g.y + ((t >> 1) & 1), xx = 2 * g.x + (t & 1);
-      return ((long)zz * (2 * H) + yy) * (2 * W) + xx;
-    }
+    case GG_POINT: return gg_source_m<GG_POINT>(a, g, t);
   }
   return -1;
 }
 
+// Load target of switched-off lanes (zero-initialised device memory): operand
+// loads are selects of an address, never branches, so that the loads of the
+// next reduction step stay in flight under the MFMAs of this one.
+__device__ uint4 g_gg_zero;
+
 // Block: 4 wavefronts x (16 RT) rows; every wavefront computes all NB column
 // tiles of its RT row tiles, so a B fragment (weights) feeds RT MFMAs and an A
 // fragment (gathered activations) feeds NB.  The reduction index k = t C + c
-// advances by 32 per step with t, c updated incrementally.
-template <int NB, int RT>
+// advances by 32 per step with t, c updated incrementally.  The operands of
+// step k + 32 are loaded while the MFMAs of step k run (two register sets used
+// in turn; B is prefetched too while it is small).
+template <int NB, int RT, int MODE>
 __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const long row0 = ((long)blockIdx.x * 4 + wv) * (16 * RT);
@@ -89,34 +103,63 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
   for (int i = 0; i < RT; ++i)
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const uint16_t* __restrict__ src = a.src;
+  const uint16_t* __restrict__ src = a.src + a.src_c0;
   const uint16_t* __restrict__ wt = a.wt;
-  int t = kq / a.C, c = kq - (kq / a.C) * a.C;
-  for (int k0 = 0; k0 < K; k0 += 32) {
-    const bool kin = k0 + kq < K;
-    bf16x8 av[RT];
-#pragma unroll
-    for (int i = 0; i < RT; ++i) {
-      uint4 araw = make_uint4(0, 0, 0, 0);
-      if (kin && rows[i].ok) {
-        const long sv = gg_source(a, rows[i], t);
-        if (sv >= 0) araw = *reinterpret_cast<const uint4*>(src + sv * a.src_cs + a.src_c0 + c);
-      }
-      av[i] = __builtin_bit_cast(bf16x8, araw);
+  const uint4* zero = &g_gg_zero;
+  constexpr bool PB = NB <= 4;   // B prefetched with A
+  constexpr int NBP = PB ? NB : 1;
+  struct Step {                  // operand position of one reduction step
+    int t, c;
+    bool kin;
+  };
+  auto next = [&](Step st) {
+    st.c += 32;
+    while (st.c >= a.C) {
+      st.c -= a.C;
+      ++st.t;
     }
+    st.kin = st.t * a.C + st.c < K;
+    return st;
+  };
+  auto ld_a = [&](int i, const Step& st) -> uint4 {
+    const long sv = gg_source_m<MODE>(a, rows[i], st.t);
+    const bool on = st.kin && rows[i].ok && sv >= 0;
+    return *(on ? reinterpret_cast<const uint4*>(src + sv * a.src_cs + st.c) : zero);
+  };
+  auto ld_b = [&](int j, const Step& st) -> uint4 {
+    return *(st.kin ? reinterpret_cast<const uint4*>(wt + ((size_t)st.t * a.Npad + j * 16 + (lane & 15)) * a.C + st.c)
+                    : zero);
+  };
+  // set X holds the operands of the current step, set Y those of the next
+  uint4 xa[RT], ya[RT], xb[NBP], yb[NBP];
+  auto load = [&](uint4 (&sa)[RT], uint4 (&sb)[NBP], const Step& st) {
+#pragma unroll
+    for (int i = 0; i < RT; ++i) sa[i] = ld_a(i, st);
+    if constexpr (PB) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) sb[j] = ld_b(j, st);
+    }
+  };
+  auto mma = [&](const uint4 (&sa)[RT], const uint4 (&sb)[NBP], const Step& st) {
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      uint4 braw = make_uint4(0, 0, 0, 0);
-      if (kin) braw = *reinterpret_cast<const uint4*>(wt + ((size_t)t * a.Npad + j * 16 + (lane & 15)) * a.C + c);
-      const bf16x8 bv = __builtin_bit_cast(bf16x8, braw);
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, PB ? sb[j] : ld_b(j, st));
 #pragma unroll
-      for (int i = 0; i < RT; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv, acc[i][j], 0, 0, 0);
+      for (int i = 0; i < RT; ++i)
+        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, sa[i]), bv, acc[i][j], 0, 0, 0);
     }
-    c += 32;
-    while (c >= a.C) {
-      c -= a.C;
-      ++t;
-    }
+  };
+  Step cur{kq / a.C, kq - (kq / a.C) * a.C, kq < K};
+  load(xa, xb, cur);
+  // two steps per trip; a trailing step past K reads zeros and adds nothing
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const Step s1 = next(cur);
+    load(ya, yb, s1);
+    mma(xa, xb, cur);
+    const Step s2 = next(s1);
+    load(xa, xb, s2);
+    mma(ya, yb, s1);
+    cur = s2;
   }
   // epilogue: rows 4 (lane / 16) + i of each row tile, column 16 j + lane % 16
 #pragma unroll
@@ -390,17 +433,32 @@ hipError_t launch_gather_gemm(const GatherGemmArgs& a, hipStream_t s) {
   // row tiles per wave: enough MFMAs per loaded fragment without exceeding the
   // accumulator budget (RT * NB <= 8 tiles of 16 x 16)
   auto grid = [&](int rt) { return dim3((unsigned)((nrows + 64 * rt - 1) / (64 * rt))); };
+  auto by_mode = [&](auto nb, auto rt) -> hipError_t {
+    constexpr int NB = decltype(nb)::value, RT = decltype(rt)::value;
+    const dim3 g = grid(RT);
+    switch (a.mode) {
+      case GG_CONV3_FWD: hipLaunchKernelGGL((k_gather_gemm<NB, RT, GG_CONV3_FWD>), g, dim3(256), 0, s, a); break;
+      case GG_CONV3_BWD: hipLaunchKernelGGL((k_gather_gemm<NB, RT, GG_CONV3_BWD>), g, dim3(256), 0, s, a); break;
+      case GG_UP_BWD: hipLaunchKernelGGL((k_gather_gemm<NB, RT, GG_UP_BWD>), g, dim3(256), 0, s, a); break;
+      case GG_UP_FWD:
+      case GG_POINT: hipLaunchKernelGGL((k_gather_gemm<NB, RT, GG_POINT>), g, dim3(256), 0, s, a); break;
+      default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  };
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  using I4 = std::integral_constant<int, 4>;
   switch (a.Npad / 16) {
-    case 1: hipLaunchKernelGGL((k_gather_gemm<1, 4>), grid(4), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_gather_gemm<2, 4>), grid(4), dim3(256), 0, s, a); break;
-    case 4: hipLaunchKernelGGL((k_gather_gemm<4, 2>), grid(2), dim3(256), 0, s, a); break;
-    case 8: hipLaunchKernelGGL((k_gather_gemm<8, 1>), grid(1), dim3(256), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_gather_gemm<16, 1>), grid(1), dim3(256), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_gather_gemm<32, 1>), grid(1), dim3(256), 0, s, a); break;
-    case 64: hipLaunchKernelGGL((k_gather_gemm<64, 1>), grid(1), dim3(256), 0, s, a); break;
+    case 1: return by_mode(I1{}, I4{});
+    case 2: return by_mode(I2{}, I4{});
+    case 4: return by_mode(I4{}, I2{});
+    case 8: return by_mode(std::integral_constant<int, 8>{}, I1{});
+    case 16: return by_mode(std::integral_constant<int, 16>{}, I1{});
+    case 32: return by_mode(std::integral_constant<int, 32>{}, I1{});
+    case 64: return by_mode(std::integral_constant<int, 64>{}, I1{});
     default: return hipErrorInvalidValue;
   }
-  return hipGetLastError();
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, int taps, hipStream_t s) {
