@@ -121,10 +121,46 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
     st.kin = st.t * a.C + st.c < K;
     return st;
   };
-  auto ld_a = [&](int i, const Step& st) -> uint4 {
-    const long sv = gg_source_m<MODE>(a, rows[i], st.t);
-    const bool on = st.kin && rows[i].ok && sv >= 0;
-    return *(on ? reinterpret_cast<const uint4*>(src + sv * a.src_cs + st.c) : zero);
+  // 3x3x3 modes: per row, the address of its own voxel and a mask of the taps
+  // whose source voxel lies inside the grid, so that a step costs one shared
+  // tap offset per lane and a bit test and an add per row
+  constexpr bool CONV3 = MODE == GG_CONV3_FWD || MODE == GG_CONV3_BWD;
+  constexpr int SGN = MODE == GG_CONV3_BWD ? -1 : 1;
+  const uint16_t* rbase[RT];
+  uint32_t tmask[RT];
+  if constexpr (CONV3) {
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const GgRow& g = rows[i];
+      rbase[i] = src + (((long)g.z * a.H + g.y) * a.W + g.x) * a.src_cs;
+      uint32_t mz = 0, my = 0, mx = 0;  // bit d + 1 set: offset d in -1..1 stays inside
+#pragma unroll
+      for (int d = -1; d <= 1; ++d) {
+        const int e = SGN * d;
+        mz |= (g.z + e >= 0 && g.z + e < a.D) ? 1u << (d + 1) : 0u;
+        my |= (g.y + e >= 0 && g.y + e < a.H) ? 1u << (d + 1) : 0u;
+        mx |= (g.x + e >= 0 && g.x + e < a.W) ? 1u << (d + 1) : 0u;
+      }
+      uint32_t m = 0;
+#pragma unroll
+      for (int t = 0; t < 27; ++t)
+        if (((mz >> (t / 9)) & (my >> ((t / 3) % 3)) & (mx >> (t % 3)) & 1u) != 0) m |= 1u << t;
+      tmask[i] = g.ok ? m : 0u;
+    }
+  }
+  auto tap_offset = [&](int t) -> long {  // source voxel of tap t relative to the row's voxel, in elements
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    return (long)(SGN * ((dz * a.H + dy) * a.W + dx)) * a.src_cs;
+  };
+  auto ld_a = [&](int i, const Step& st, long toff) -> uint4 {
+    if constexpr (CONV3) {
+      const bool on = st.kin && ((tmask[i] >> (st.t & 31)) & 1u) != 0;   // kin implies t < 27
+      return *(on ? reinterpret_cast<const uint4*>(rbase[i] + toff + st.c) : zero);
+    } else {
+      const long sv = gg_source_m<MODE>(a, rows[i], st.t);
+      const bool on = st.kin && rows[i].ok && sv >= 0;
+      return *(on ? reinterpret_cast<const uint4*>(src + sv * a.src_cs + st.c) : zero);
+    }
   };
   auto ld_b = [&](int j, const Step& st) -> uint4 {
     return *(st.kin ? reinterpret_cast<const uint4*>(wt + ((size_t)st.t * a.Npad + j * 16 + (lane & 15)) * a.C + st.c)
@@ -133,8 +169,9 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
   // set X holds the operands of the current step, set Y those of the next
   uint4 xa[RT], ya[RT], xb[NBP], yb[NBP];
   auto load = [&](uint4 (&sa)[RT], uint4 (&sb)[NBP], const Step& st) {
+    const long toff = CONV3 ? tap_offset(st.t) : 0;
 #pragma unroll
-    for (int i = 0; i < RT; ++i) sa[i] = ld_a(i, st);
+    for (int i = 0; i < RT; ++i) sa[i] = ld_a(i, st, toff);
     if constexpr (PB) {
 #pragma unroll
       for (int j = 0; j < NB; ++j) sb[j] = ld_b(j, st);
