@@ -67,6 +67,18 @@ def measured_traffic(tuning):
         return None
 
 
+def empty_tile_frac(torch, x, tile):
+    """Fraction of tile x tile blocks of the (z, y, x) volume's planes that hold
+    no non-zero voxel (the rows and planes the solver itself skips are in the
+    report; this is the coarser unit a tiled skip would use)."""
+    nz, ny, nx = x.shape
+    ty, tx = ny // tile, nx // tile
+    if ty == 0 or tx == 0:
+        return None
+    occ = x[:, :ty * tile, :tx * tile].reshape(nz, ty, tile, tx, tile).ne(0).any(dim=4).any(dim=2)
+    return 1.0 - float(occ.float().mean())
+
+
 def build_scene(torch, rihvr, scenes, plan, seed):
     g = scenes.geometry_c2()
     sc = scenes.scene_c2(seed=seed)
@@ -466,7 +478,10 @@ def main():
     converged = bool(rep["converged"])
 
     # per-phase device times (HIP events on the solve's stream), same solve
-    _, rep_t, _ = one_solve(flags=rihvr.RI_SOLVE_TIMING)
+    x_t, rep_t, _ = one_solve(flags=rihvr.RI_SOLVE_TIMING)
+    tile_frac = empty_tile_frac(torch, x_t, 32)   # diagnostic of the solution's sparsity, not timed
+    log(f"solution: empty fraction of planes {rep_t['empty_plane_frac']:.3f}, rows {rep_t['empty_row_frac']:.3f}, 32x32 tiles {tile_frac:.3f}")
+    del x_t
     ph = rep_t["phase_ms"]
     nl = rep_t["phase_launches"]
     n_prox = max(rep_t["iters"], 1)
@@ -541,6 +556,7 @@ def main():
         "voxel_iters_per_s": nvox * mean_iters * value,
         "f_ref": f_ref,
         "empty_row_frac": rep["empty_row_frac"],
+        "empty_tile32_frac": tile_frac,
         "empty_plane_frac": rep["empty_plane_frac"],
         "phase_ms_per_iter": phase_ms_per_iter,
         "roofline": roofline,
