@@ -236,7 +236,7 @@ struct Layout {
   size_t vol1 = 0, vol2 = 0, pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};  // volumes (float)
   size_t spec = 0, gp = 0, gi = 0, th = 0;                 // spectra (float2)
   size_t ax0 = 0, ax1 = 0;                                 // holograms (float)
-  size_t rowflag = 0, planeflag = 0;                       // bytes
+  size_t rowflag = 0, planeflag = 0, rowflag_prev = 0;     // bytes
   size_t pdfit = 0, psum = 0, ptv = 0, qsum = 0, qtv = 0, hist = 0;  // doubles
   size_t state = 0;
   int nchunk = 1, ppc = 1;
@@ -302,6 +302,7 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
     L.ax0 = take(nx * ny * sizeof(float));
     L.ax1 = take(nx * ny * sizeof(float));
     L.rowflag = take(ny * nz);
+    L.rowflag_prev = take(ny * nz);
     L.planeflag = take(nz);
     L.n_dfit = (int)((ny + rows_per_block((int)m) - 1) / rows_per_block((int)m));
     L.n_obj = obj_blocks((int)nx, (int)ny, (int)nz);
@@ -636,6 +637,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   ar.ny = ny;
   ar.x0 = c.vol[0]; ar.x1 = c.vol[1]; ar.x2 = c.vol[2];
   ar.rowflag = rowflag;
+  ar.rowflag_prev = c.dense ? nullptr : at<uint8_t>(c.ws, L.rowflag_prev);
   ar.planeflag = planeflag;
   ar.st = c.st;
   ar.step = c.step;
@@ -737,6 +739,9 @@ static hipError_t enqueue_setup(const SolveCtx& c, const ri_solve_params* sp, hi
   uint8_t* planeflag = at<uint8_t>(c.ws, c.L.planeflag);
   if ((e = launch_fill_u8(rowflag, (size_t)p->g.ny * p->g.nz, 0, s)) != hipSuccess) return e;
   if ((e = launch_fill_u8(planeflag, (size_t)p->g.nz, 0, s)) != hipSuccess) return e;
+  // x_{-1} is the start itself; its row flags are not known yet: every row may be occupied
+  if ((e = launch_fill_u8(at<uint8_t>(c.ws, c.L.rowflag_prev), (size_t)p->g.ny * p->g.nz, 1, s)) != hipSuccess)
+    return e;
   if (sp->init == RI_INIT_ZERO) {
     if ((e = launch_fill_f32(c.vol[0], nvox, 0.f, s)) != hipSuccess) return e;
   } else {

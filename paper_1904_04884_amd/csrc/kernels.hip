@@ -555,6 +555,13 @@ __device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int 
   const int r = threadIdx.x / T, t = threadIdx.x % T;
   const int row = bx * ROWS + r;
   const bool active = row < a.nrows;
+  // gradient step: a row of x_k or x_{k-1} whose flag is clear is all zero and
+  // is not read (flags read here, before the row's transform; cleared below)
+  bool fc = true, fp = true;
+  if (a.mode == 1 && a.rowflag_prev != nullptr && active) {
+    fc = a.rowflag[row] != 0;
+    fp = a.rowflag_prev[row] != 0;
+  }
   float2* buf = lds[r];
   const float2* src = a.u + (size_t)row * M;
 #pragma unroll
@@ -581,13 +588,15 @@ __device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int 
   for (int s = 0; s < P; ++s) {
     const int e = t + s * T;
     const float2 g = buf[e];
-    const float2 c = xc[e], p = xp[e];
+    const float2 c = fc ? xc[e] : make_float2(0.f, 0.f);
+    const float2 p = fp ? xp[e] : make_float2(0.f, 0.f);
     float2 v;
     v.x = c.x + beta * (c.x - p.x) - gs * g.x;
     v.y = c.y + beta * (c.y - p.y) - gs * g.y;
     xp[e] = v;
   }
   if (t == 0) {
+    if (a.rowflag_prev != nullptr) a.rowflag_prev[row] = fc ? 1 : 0;  // x_k is x_{k-1} next time
     a.rowflag[row] = 0;
     if (row % a.ny == 0) a.planeflag[row / a.ny] = 0;
   }

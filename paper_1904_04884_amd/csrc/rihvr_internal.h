@@ -175,6 +175,8 @@ struct AdjRowsArgs {
   float* out;                     // mode 0
   float* x0; float* x1; float* x2; // mode 1: the three rotating volume buffers
   uint8_t* rowflag; uint8_t* planeflag;
+  uint8_t* rowflag_prev;          // mode 1, nullable: row flags of x_{k-1}; rows of x_k and
+                                  // x_{k-1} with a clear flag are not read; set to x_k's
   const SolveState* st;
   double step;
   int mode;
