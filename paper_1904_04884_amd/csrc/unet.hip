@@ -235,6 +235,126 @@ __global__ void __launch_bounds__(256) k_gather_gemm(GatherGemmArgs a) {
 }
 
 // ---------------------------------------------------------------------------
+// 3x3x3 layers from an LDS halo tile.  A block's rows are a 16 x 4 x RT box of
+// output voxels (x fastest; wavefront w takes y0 + w, row tile i takes z0 + i,
+// MFMA row m takes x0 + m).  The input box with a one-voxel halo, 18 x 6 x
+// (RT + 2) voxels of all C channels with zeros outside the grid, is staged in
+// LDS once, and every tap reads its A operand there at a fixed offset, instead
+// of gathering it from global memory nine to 27 times per voxel.
+// ---------------------------------------------------------------------------
+constexpr int kHbX = 18, kHbY = 6;  // halo box extent in x and y
+
+template <int NB, int RT, int MODE>
+__global__ void __launch_bounds__(256) k_conv3_lds(GatherGemmArgs a) {
+  extern __shared__ uint4 s_box4[];
+  uint16_t* s_box = reinterpret_cast<uint16_t*>(s_box4);  // [RT + 2][6][18][C]
+  constexpr int BZ = RT + 2;
+  constexpr int SGN = MODE == GG_CONV3_BWD ? -1 : 1;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int C = a.C;
+  const int x0 = blockIdx.x * 16, y0 = blockIdx.y * 4, z0 = blockIdx.z * RT;
+  const int cch = C / 8;  // 16-byte chunks per voxel
+  const int nchunk = kHbX * kHbY * BZ * cch;
+  for (int e = threadIdx.x; e < nchunk; e += 256) {
+    const int v = e / cch, q = e - v * cch;
+    const int bx = v % kHbX, by = (v / kHbX) % kHbY, bz = v / (kHbX * kHbY);
+    const int gx = x0 + bx - 1, gy = y0 + by - 1, gz = z0 + bz - 1;
+    uint4 val = make_uint4(0, 0, 0, 0);
+    if (gx >= 0 && gx < a.W && gy >= 0 && gy < a.H && gz >= 0 && gz < a.D)
+      val = *reinterpret_cast<const uint4*>(a.src + (((long)gz * a.H + gy) * a.W + gx) * a.src_cs + a.src_c0 +
+                                            q * 8);
+    s_box4[e] = val;  // chunk e is voxel v, channels 8q .. 8q + 7
+  }
+  __syncthreads();
+  const int lx = lane & 15;
+  const int kq = (lane >> 4) * 8;
+  const int K = 27 * C;
+  const uint16_t* __restrict__ wt = a.wt;
+  const uint4* zero = &g_gg_zero;
+  f32x4 acc[RT][NB];
+#pragma unroll
+  for (int i = 0; i < RT; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // the weights of step k + 32 are loaded while the MFMAs of step k run (two
+  // register sets used in turn); a trailing step past K reads zeros
+  struct Step {
+    int t, c;
+    bool kin;
+  };
+  auto next = [&](Step st) {
+    st.c += 32;
+    while (st.c >= C) {
+      st.c -= C;
+      ++st.t;
+    }
+    st.kin = st.t * C + st.c < K;  // t < 27
+    return st;
+  };
+  auto ld_b = [&](uint4 (&sb)[NB], const Step& st) {
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+      sb[j] = *(st.kin ? reinterpret_cast<const uint4*>(wt + ((size_t)st.t * a.Npad + j * 16 + lx) * C + st.c) : zero);
+  };
+  auto mma = [&](const uint4 (&sb)[NB], const Step& st) {
+    const int tt = st.kin ? st.t : 13;  // the centre tap keeps the LDS index inside the box
+    const int dz = SGN * (tt / 9 - 1), dy = SGN * ((tt / 3) % 3 - 1), dx = SGN * (tt % 3 - 1);
+    bf16x8 av[RT];
+#pragma unroll
+    for (int i = 0; i < RT; ++i) {
+      const int vi = ((i + 1 + dz) * kHbY + (wv + 1 + dy)) * kHbX + (lx + 1 + dx);
+      const uint4 raw = *reinterpret_cast<const uint4*>(s_box + (size_t)vi * C + st.c);
+      av[i] = __builtin_bit_cast(bf16x8, st.kin ? raw : make_uint4(0, 0, 0, 0));
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const bf16x8 bv = __builtin_bit_cast(bf16x8, sb[j]);
+#pragma unroll
+      for (int i = 0; i < RT; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[i], bv, acc[i][j], 0, 0, 0);
+    }
+  };
+  uint4 xb[NB], yb[NB];
+  Step cur{kq / C, kq - (kq / C) * C, kq < K};
+  ld_b(xb, cur);
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    const Step s1 = next(cur);
+    ld_b(yb, s1);
+    mma(xb, cur);
+    const Step s2 = next(s1);
+    ld_b(xb, s2);
+    mma(yb, s1);
+    cur = s2;
+  }
+  // epilogue: D row m = 4 (lane / 16) + i is voxel (x0 + m, y0 + wv, z0 + rt)
+  const int y = y0 + wv;
+#pragma unroll
+  for (int rt = 0; rt < RT; ++rt) {
+    const int z = z0 + rt;
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int n = j * 16 + lx;
+      if (n >= a.N) continue;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = x0 + (lane >> 4) * 4 + i;
+        if (x >= a.W || y >= a.H || z >= a.D) continue;
+        float v = acc[rt][j][i];
+        if (a.bias) v += a.bias[n];
+        if (a.relu) v = fmaxf(v, 0.f);
+        const size_t o = (size_t)(((long)z * a.H + y) * a.W + x) * a.dst_cs + a.dst_c0 + n;
+        if (a.out_f32) {
+          float* d = reinterpret_cast<float*>(a.dst);
+          d[o] = a.accumulate ? d[o] + v : v;
+        } else {
+          uint16_t* d = reinterpret_cast<uint16_t*>(a.dst);
+          d[o] = f2bf(a.accumulate ? bf2f(d[o]) + v : v);
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Weight gradient: dW[t][c][n] += sum_r S(r, t)[c] * G(r, t)[n]  (FP32 atomics;
 // [t][c][n] is the [tap][cin][cout] layout of the master weights).
 // Block: one tap, a chunk of rows and a group of up to 16 (n, c) output tiles;
@@ -465,8 +585,39 @@ static int ew_grid(size_t n) {
   return (int)(b > 16384 ? 16384 : (b == 0 ? 1 : b));
 }
 
+// Halo-box bytes of k_conv3_lds, or 0 when a layer does not take it (other
+// modes, more than 8 column tiles, rows narrower than a tile, or a box above
+// 64 KiB, which would leave fewer than two blocks per CU).
+static size_t conv3_lds_bytes(const GatherGemmArgs& a, int rt) {
+  if (a.mode != GG_CONV3_FWD && a.mode != GG_CONV3_BWD) return 0;
+  if (a.Npad / 16 > 8 || a.W < 16 || a.C % 8 != 0 || a.src_cs % 8 != 0 || a.src_c0 % 8 != 0) return 0;
+  const size_t bytes = (size_t)kHbX * kHbY * (rt + 2) * a.C * sizeof(uint16_t);
+  return bytes <= 64 * 1024 ? bytes : 0;
+}
+
 hipError_t launch_gather_gemm(const GatherGemmArgs& a, hipStream_t s) {
   const long nrows = (long)a.D * a.H * a.W;
+  {
+    const int nb = a.Npad / 16;
+    const int rt = nb <= 2 ? 4 : (nb == 4 ? 2 : 1);
+    const size_t lds = conv3_lds_bytes(a, rt);
+    if (lds > 0) {
+      const dim3 g((unsigned)((a.W + 15) / 16), (unsigned)((a.H + 3) / 4), (unsigned)((a.D + rt - 1) / rt));
+      const bool bwd = a.mode == GG_CONV3_BWD;
+#define RIHVR_CONV3(NB, RT)                                                                                    \
+  if (bwd) hipLaunchKernelGGL((k_conv3_lds<NB, RT, GG_CONV3_BWD>), g, dim3(256), lds, s, a);                   \
+  else hipLaunchKernelGGL((k_conv3_lds<NB, RT, GG_CONV3_FWD>), g, dim3(256), lds, s, a);
+      switch (nb) {
+        case 1: RIHVR_CONV3(1, 4) break;
+        case 2: RIHVR_CONV3(2, 4) break;
+        case 4: RIHVR_CONV3(4, 2) break;
+        case 8: RIHVR_CONV3(8, 1) break;
+        default: return hipErrorInvalidValue;
+      }
+#undef RIHVR_CONV3
+      return hipGetLastError();
+    }
+  }
   // row tiles per wave: enough MFMAs per loaded fragment without exceeding the
   // accumulator budget (RT * NB <= 8 tiles of 16 x 16)
   auto grid = [&](int rt) { return dim3((unsigned)((nrows + 64 * rt - 1) / (64 * rt))); };
