@@ -21,7 +21,8 @@
  * differences along x, y and z (last difference on each axis zero).
  *
  * Conventions shared by every entry point:
- *   - Array arguments are DEVICE pointers to C-contiguous float32 arrays:
+ *   - Array arguments are DEVICE pointers to C-contiguous arrays whose element
+ *     type is the plan's dtype (float32 for RI_F32, float64 for RI_F64):
  *     volumes are [nz][ny][nx], holograms [ny][nx] (x fastest).
  *   - The caller owns every buffer.  The library allocates device memory only
  *     in ri_plan_create (phase and twiddle tables, a small state block) and
@@ -56,6 +57,11 @@ typedef enum {
   RI_ERR_NONFINITE = 6,          /* the objective became NaN / Inf during a solve */
   RI_ERR_NOT_CONVERGED = 7       /* the objective diverged (grew past 10x F(x0)) */
 } ri_status;
+
+/* Element type of a plan's arrays.  RI_F32 is the production path; RI_F64
+ * runs the same kernels instantiated for double (tables, transforms, prox and
+ * objective all in FP64), which separates bugs from FP32 rounding. */
+typedef enum { RI_F32 = 0, RI_F64 = 1 } ri_dtype;
 
 /* Geometry flags */
 #define RI_NO_CARRIER 0x1u  /* drop the exp(i 2 pi z / lambda) carrier from H_j */
@@ -138,18 +144,23 @@ typedef struct {
 } ri_tuning;
 
 /*
- * Create a plan for one geometry on the current HIP device: FP64 phase table
+ * Create a plan for one geometry and element type on the current HIP device
+ * (the angular-spectrum model of section "Methodology"; the step of Eq. 7
+ * is 1/||A||^2): FP64 phase table
  * theta(f) = sqrt(1/lambda^2 - f^2) - 1/lambda, per-plane carrier phases
  * frac(z_j / lambda), FFT twiddles, and the Lipschitz constant
  * ||A||^2 = max_f sum_j cos^2(2 pi z_j sqrt(1/lambda^2 - f^2)) (the spectrum of
  * A A^T; the FISTA step is 1/||A||^2).  Synchronous.  *out receives the plan.
  */
-ri_status ri_plan_create(const ri_geometry* geometry, ri_plan** out);
+ri_status ri_plan_create(const ri_geometry* geometry, ri_dtype dtype, ri_plan** out);
 ri_status ri_plan_destroy(ri_plan* plan);
 /* ||A||^2 of the plan (host value). */
 ri_status ri_plan_lipschitz(const ri_plan* plan, double* out);
-/* Bytes of scratch space that `op` needs with this plan (and its current tuning). */
-ri_status ri_workspace_size(const ri_plan* plan, ri_op op, size_t* bytes);
+/* Bytes of scratch space that suffice for every entry point taking this plan
+ * (forward, adjoint, prox, solve and autotune) with its current tuning. */
+ri_status ri_workspace_size(const ri_plan* plan, size_t* bytes);
+/* The smaller amount that the one entry point `op` needs. */
+ri_status ri_workspace_size_op(const ri_plan* plan, ri_op op, size_t* bytes);
 
 /*
  * Tuning of a plan.  ri_plan_set_tuning validates every field (RI_ERR_INVALID_ARG
@@ -185,18 +196,22 @@ ri_status ri_plan_autotune(ri_plan* plan, int32_t inner_iters, const char* cache
                            size_t ws_bytes, void* stream, ri_autotune_report* report);
 
 /*
- * b_out = A x.  x: volume [nz][ny][nx]; b_out: hologram [ny][nx].
- * Exact in every voxel (no sparsity skipping on this entry point).
- * x and b_out must not overlap.
+ * b_out = A x, the linearised hologram formation of section "Methodology"
+ * (the operator inside the data term of Eq. 2): every plane propagated to the
+ * sensor by the angular spectrum and summed.  x: volume [nz][ny][nx]; b_out:
+ * hologram [ny][nx].  Exact in every voxel (no sparsity skipping on this
+ * entry point).  x and b_out must not overlap.
  */
-ri_status ri_forward(ri_plan* plan, const float* x, float* b_out,
+ri_status ri_forward(ri_plan* plan, const void* x, void* b_out,
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
- * x_out = A^T y, the back-propagation (A^T y)_j = Re(IFFT2(FFT2(y) . conj(H_j))).
- * y: hologram [ny][nx]; x_out: volume [nz][ny][nx].  Must not overlap.
+ * x_out = A^T y, the back-propagation (A^T y)_j = Re(IFFT2(FFT2(y) . conj(H_j))):
+ * the adjoint of the model of section "Methodology", which the gradient
+ * A^T (A x - b) of the data term of Eq. 2 needs in the shrinkage step of
+ * Eq. 7.  y: hologram [ny][nx]; x_out: volume [nz][ny][nx].  Must not overlap.
  */
-ri_status ri_adjoint(ri_plan* plan, const float* y, float* x_out,
+ri_status ri_adjoint(ri_plan* plan, const void* y, void* x_out,
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
@@ -208,11 +223,14 @@ ri_status ri_adjoint(ri_plan* plan, const float* y, float* x_out,
  * may be the same buffer (in place).
  */
 ri_status ri_prox_fused_lasso(ri_plan* plan, const ri_prox_params* params, double step,
-                              const float* v, float* x_out,
+                              const void* v, void* x_out,
                               void* ws, size_t ws_bytes, void* stream);
 
 /*
- * FISTA solve of the problem above with constant step 1/||A||^2:
+ * FISTA solve (section "Methodology": Eq. 2 with the fused lasso of Eq. 5,
+ * shrinkage step Eq. 7 with the prox of Eq. 6 / Eq. 8, then the accelerated
+ * update from the previous estimate) of the problem above with constant step
+ * 1/||A||^2:
  *   x_k = prox(y_k - t A^T (A y_k - b)),  s_{k+1} = (1 + sqrt(1 + 4 s_k^2)) / 2,
  *   y_{k+1} = x_k + ((s_k - 1)/s_{k+1}) (x_k - x_{k-1}),
  * from x_0 = 0 or the given x_inout.  b: hologram [ny][nx]; x_inout: volume
@@ -223,12 +241,15 @@ ri_status ri_prox_fused_lasso(ri_plan* plan, const ri_prox_params* params, doubl
  * fills it; otherwise it returns after enqueueing (the host still polls the stop
  * flag when f_ref > 0).
  */
-ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const float* b, float* x_inout,
+ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const void* b, void* x_inout,
                    void* ws, size_t ws_bytes, void* stream, ri_solve_report* report);
 
 /*
  * Batched solve of n independent holograms that may differ in size and plane
- * count (one plan per frame).  Frames advance in lock-step, one outer
+ * count (one plan per frame): each frame is the FISTA solve of ri_solve
+ * (section "Methodology", Eq. 2, 5, 7), as for the time series of holograms
+ * the paper reconstructs for particle tracking (section "Synthetic Turbulent
+ * Flow").  RI_F32 plans only.  Frames advance in lock-step, one outer
  * iteration for all frames at a time, each with its own step, momentum,
  * objective and stop flag; a frame that has met its criterion does no further
  * work.  Each kernel of an iteration is launched once per transform size (or
@@ -243,7 +264,7 @@ ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const float* b,
 ri_status ri_workspace_size_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
                                     size_t* bytes);
 ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
-                           const float* const* b, float* const* x_inout,
+                           const void* const* b, void* const* x_inout,
                            void* ws, size_t ws_bytes, void* stream, ri_solve_report* reports);
 
 /*
@@ -266,7 +287,7 @@ ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_para
  */
 typedef struct {
   int32_t levels;   /* 1..6 */
-  int32_t base;     /* channels of level 0, a multiple of 8; base * 2^(levels-1) <= 128 */
+  int32_t base;     /* channels of level 0: 8, 16, 32, 64 or 128; base * 2^(levels-1) <= 128 */
 } ri_unet_config;
 
 ri_status ri_unet_param_count(const ri_unet_config* cfg, size_t* count);

@@ -114,7 +114,7 @@ static void drop_graph(ri_plan* p) {
 static void twiddles(int n, std::vector<float2>& out) {
   out.resize(n);
   for (int k = 0; k < n; ++k) {
-    // exp(-2 pi i k / n), angle reduced to the first half turn for accuracy
+    // exp(-2 pi i k / n) from the FP64 angle, rounded once to FP32
     const double a = 2.0 * M_PI * (double)k / (double)n;
     out[k] = make_float2((float)std::cos(a), (float)(-std::sin(a)));
   }
@@ -136,9 +136,11 @@ static ri_status validate_geometry(const ri_geometry* g) {
   return RI_OK;
 }
 
-extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_plan** out) {
+extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_plan** out) {
   if (!out) return fail(RI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
+  if (dtype != RI_F32 && dtype != RI_F64) return fail(RI_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
+  if (dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "RI_F64 plans are not available in this build");
   ri_status vs = validate_geometry(g);
   if (vs != RI_OK) return vs;
   ri_plan* p = new ri_plan();
@@ -319,10 +321,18 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
   return L;
 }
 
-extern "C" ri_status ri_workspace_size(const ri_plan* p, ri_op op, size_t* bytes) {
+extern "C" ri_status ri_workspace_size_op(const ri_plan* p, ri_op op, size_t* bytes) {
   if (!p || !bytes) return fail(RI_ERR_INVALID_ARG, "NULL argument");
   if (op < RI_OP_FORWARD || op > RI_OP_AUTOTUNE) return fail(RI_ERR_INVALID_ARG, "unknown op %d", (int)op);
   *bytes = make_layout(p, op).total;
+  return RI_OK;
+}
+
+extern "C" ri_status ri_workspace_size(const ri_plan* p, size_t* bytes) {
+  if (!p || !bytes) return fail(RI_ERR_INVALID_ARG, "NULL argument");
+  size_t n = 0;
+  for (int op = RI_OP_FORWARD; op <= RI_OP_AUTOTUNE; ++op) n = std::max(n, make_layout(p, (ri_op)op).total);
+  *bytes = n;
   return RI_OK;
 }
 
@@ -396,9 +406,11 @@ static hipError_t enqueue_forward(ri_plan* p, const Layout& L, void* ws, const f
   return launch_rows_c2r(m, ca, s);
 }
 
-extern "C" ri_status ri_forward(ri_plan* p, const float* x, float* b_out, void* ws, size_t ws_bytes,
+extern "C" ri_status ri_forward(ri_plan* p, const void* xv, void* bv, void* ws, size_t ws_bytes,
                                 void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const float* x = static_cast<const float*>(xv);
+  float* b_out = static_cast<float*>(bv);
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
   ri_status st = check_common(p, x, b_out, ws, ws_bytes, RI_OP_FORWARD, vb, hb);
   if (st != RI_OK) return st;
@@ -439,8 +451,10 @@ static hipError_t enqueue_adjoint(ri_plan* p, const Layout& L, void* ws, const f
   return launch_adj_rows(m, ar, s);
 }
 
-extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* ws, size_t ws_bytes, void* stream) {
+extern "C" ri_status ri_adjoint(ri_plan* p, const void* yv, void* xv, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const float* y = static_cast<const float*>(yv);
+  float* x_out = static_cast<float*>(xv);
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
   ri_status st = check_common(p, y, x_out, ws, ws_bytes, RI_OP_ADJOINT, hb, vb);
   if (st != RI_OK) return st;
@@ -449,9 +463,11 @@ extern "C" ri_status ri_adjoint(ri_plan* p, const float* y, float* x_out, void* 
   return RI_OK;
 }
 
-extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, double step, const float* v,
-                                         float* x_out, void* ws, size_t ws_bytes, void* stream) {
+extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, double step, const void* vv,
+                                         void* xv, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const float* v = static_cast<const float*>(vv);
+  float* x_out = static_cast<float*>(xv);
   if (!pp) return fail(RI_ERR_INVALID_ARG, "params is NULL");
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float);
   ri_status st = check_common(p, v, x_out, ws, ws_bytes, RI_OP_PROX, vb, vb);
@@ -476,7 +492,22 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   a.tv = pp->tv;
   a.levels = p->tune.tv_levels;
   a.blocks = p->tune.tv_blocks;
+  // In place with TV active: the final pass reads v in each tile's halo and in
+  // the z-margin of the neighbouring chunk while other blocks store x, and not
+  // every block is resident at once, so x may not go into v's buffer.  The
+  // final pass writes its result into the dual set it does not use (its
+  // output set: it stores no dual), which is then copied over v.
+  const double tau = step * pp->tv;
+  const int K = (tau > 0.0 && pp->inner_iters > 0) ? pp->inner_iters : 0;
+  float* staged = nullptr;
+  if (v == x_out && K > 0) {
+    const int npass = prox_passes(K, tau, p->tune.tv_levels);
+    staged = ((npass - 1) & 1) ? a.pa[0] : a.pb[0];
+    a.x = staged;
+  }
   HIP_TRY(launch_prox(a, (hipStream_t)stream, nullptr));
+  if (staged != nullptr)
+    HIP_TRY(launch_copy_f32(x_out, staged, (size_t)p->g.nx * p->g.ny * p->g.nz, (hipStream_t)stream));
   return RI_OK;
 }
 
@@ -815,8 +846,10 @@ static ri_status fill_report(const SolveCtx& c, hipStream_t s, ri_solve_report* 
   return (ri_status)h.status;
 }
 
-extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const float* b, float* x_inout, void* ws,
+extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const void* bv, void* xv, void* ws,
                               size_t ws_bytes, void* stream, ri_solve_report* report) {
+  const float* b = static_cast<const float*>(bv);
+  float* x_inout = static_cast<float*>(xv);
   ri_status vs = validate_solve(p, sp, b, x_inout, ws, ws_bytes);
   if (vs != RI_OK) return vs;
   hipStream_t s = (hipStream_t)stream;
@@ -984,8 +1017,10 @@ extern "C" ri_status ri_workspace_size_batched(int32_t n, ri_plan* const* plans,
 }
 
 extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri_solve_params* params,
-                                      const float* const* b, float* const* x_inout, void* ws, size_t ws_bytes,
+                                      const void* const* bv, void* const* xv, void* ws, size_t ws_bytes,
                                       void* stream, ri_solve_report* reports) {
+  const float* const* b = reinterpret_cast<const float* const*>(bv);
+  float* const* x_inout = reinterpret_cast<float* const*>(xv);
   if (n < 0) return fail(RI_ERR_INVALID_ARG, "n < 0");
   if (n == 0) return RI_OK;
   if (!plans || !params || !b || !x_inout) return fail(RI_ERR_INVALID_ARG, "NULL array argument");

@@ -644,7 +644,7 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
       const float gx = (i + k + 1 < nx) ? a4[k + 1] - a4[k] : 0.f;
       const float gy = hy ? b4[k] - a4[k] : 0.f;
       const float gz = hz ? c4[k] - a4[k] : 0.f;
-      ss += a4[k];
+      ss += fabsf(a4[k]);   // ||x||_1 (x >= 0 in the constrained problem, signed otherwise)
       // per-voxel norm in FP32 (relative error ~1e-7), running sums in FP64
       tt += sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
     }

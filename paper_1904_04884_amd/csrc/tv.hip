@@ -175,7 +175,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       // per-voxel norm in FP32 (the hardware square root, within 1 ulp, not
       // the correctly rounded sequence), running sums in FP64
       const float t = __builtin_amdgcn_sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
-      ss += ys[q] ? x0 : 0.f;
+      ss += ys[q] ? fabsf(x0) : 0.f;   // ||x||_1
       tt += ys[q] ? t : 0.f;
     }
     s_acc += (double)ss;

@@ -182,8 +182,12 @@ T* at(void* ws, size_t off) {
 
 ri_status check_cfg(const ri_unet_config* c) {
   if (!c) return set_error(RI_ERR_INVALID_ARG, "unet config is NULL");
-  if (c->levels < 1 || c->levels > 6 || c->base < 8 || c->base % 8 || (c->base << (c->levels - 1)) > 128)
-    return set_error(RI_ERR_INVALID_ARG, "unet config: levels in [1, 6], base a multiple of 8, base*2^(levels-1) <= 128");
+  // channel counts are padded to 16 * 2^k columns of MFMA tiles, which every
+  // kernel case covers only for base = 8 * 2^k
+  const bool pow2 = c->base >= 8 && (c->base & (c->base - 1)) == 0;
+  if (c->levels < 1 || c->levels > 6 || !pow2 || (c->base << (c->levels - 1)) > 128)
+    return set_error(RI_ERR_INVALID_ARG,
+                     "unet config: levels in [1, 6], base one of 8, 16, 32, ..., base*2^(levels-1) <= 128");
   return RI_OK;
 }
 

@@ -28,6 +28,8 @@ RI_ERR_HIP = 5
 RI_ERR_NONFINITE = 6
 RI_ERR_NOT_CONVERGED = 7
 
+RI_F32, RI_F64 = 0, 1
+
 RI_NO_CARRIER = 0x1
 RI_INIT_ZERO = 0
 RI_INIT_GIVEN = 1
@@ -41,7 +43,7 @@ RI_NUM_PHASES = 6
 PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 
 EXPORTED = (
-    "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size",
+    "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size", "ri_workspace_size_op",
     "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_autotune",
     "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
@@ -125,10 +127,11 @@ def lib():
         raise RuntimeError(f"{LIB_PATH} not found: build it with `python -m paper_1904_04884_amd.build_lib`")
     L = C.CDLL(str(LIB_PATH))
     vp, sz = C.c_void_p, C.c_size_t
-    L.ri_plan_create.argtypes = [C.POINTER(ri_geometry), C.POINTER(vp)]
+    L.ri_plan_create.argtypes = [C.POINTER(ri_geometry), C.c_int, C.POINTER(vp)]
     L.ri_plan_destroy.argtypes = [vp]
     L.ri_plan_lipschitz.argtypes = [vp, C.POINTER(C.c_double)]
-    L.ri_workspace_size.argtypes = [vp, C.c_int, C.POINTER(sz)]
+    L.ri_workspace_size.argtypes = [vp, C.POINTER(sz)]
+    L.ri_workspace_size_op.argtypes = [vp, C.c_int, C.POINTER(sz)]
     L.ri_plan_get_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
     L.ri_plan_set_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
     L.ri_plan_autotune.argtypes = [vp, C.c_int32, C.c_char_p, vp, sz, vp, C.POINTER(ri_autotune_report)]
@@ -167,9 +170,9 @@ def _check(status: int, where: str):
 # ---------------------------------------------------------------------------
 # One-to-one wrappers (raw pointers as ints)
 # ---------------------------------------------------------------------------
-def ri_plan_create(geometry: ri_geometry) -> int:
+def ri_plan_create(geometry: ri_geometry, dtype: int = RI_F32) -> int:
     h = C.c_void_p()
-    _check(lib().ri_plan_create(C.byref(geometry), C.byref(h)), "ri_plan_create")
+    _check(lib().ri_plan_create(C.byref(geometry), int(dtype), C.byref(h)), "ri_plan_create")
     return h.value
 
 
@@ -183,9 +186,15 @@ def ri_plan_lipschitz(plan: int) -> float:
     return v.value
 
 
-def ri_workspace_size(plan: int, op: int) -> int:
+def ri_workspace_size(plan: int) -> int:
     v = C.c_size_t()
-    _check(lib().ri_workspace_size(plan, op, C.byref(v)), "ri_workspace_size")
+    _check(lib().ri_workspace_size(plan, C.byref(v)), "ri_workspace_size")
+    return v.value
+
+
+def ri_workspace_size_op(plan: int, op: int) -> int:
+    v = C.c_size_t()
+    _check(lib().ri_workspace_size_op(plan, op, C.byref(v)), "ri_workspace_size_op")
     return v.value
 
 
@@ -314,7 +323,7 @@ class Plan:
         return (self.geom.nz, self.geom.ny, self.geom.nx)
 
     def workspace(self, op: int):
-        n = ri_workspace_size(self.handle, op)
+        n = ri_workspace_size_op(self.handle, op)
         ws = self._ws.get(op)
         if ws is None or ws.numel() < n:
             ws = self.torch.empty(max(n, 1), dtype=self.torch.uint8, device="cuda")

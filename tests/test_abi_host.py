@@ -100,7 +100,7 @@ def test_status_strings(lib):
 def test_plan_rejects_unsupported_geometry(lib, nx, ny, nz):
     g = scenes.geometry_c1().with_(nx=nx, ny=ny, nz=nz)
     h = C.c_void_p()
-    st = lib.ri_plan_create(C.byref(rihvr.geometry_struct(g)), C.byref(h))
+    st = lib.ri_plan_create(C.byref(rihvr.geometry_struct(g)), rihvr.RI_F32, C.byref(h))
     assert st in (rihvr.RI_ERR_UNSUPPORTED_SIZE, rihvr.RI_ERR_INVALID_ARG)
     assert h.value is None
     assert rihvr.ri_last_error()
@@ -110,13 +110,50 @@ def test_plan_rejects_evanescent_and_bad_optics(lib):
     for kw in ({"pixel_um": 0.4}, {"wavelength_um": -1.0}, {"pixel_um": 0.0}):
         g = scenes.geometry_c1().with_(**kw)
         h = C.c_void_p()
-        assert lib.ri_plan_create(C.byref(rihvr.geometry_struct(g)), C.byref(h)) == rihvr.RI_ERR_INVALID_ARG
+        assert lib.ri_plan_create(C.byref(rihvr.geometry_struct(g)), rihvr.RI_F32, C.byref(h)) == rihvr.RI_ERR_INVALID_ARG
+
+
+def test_header_signatures_of_the_boundary():
+    """The entry points have the boundary's signatures: plain pointers and
+    sizes, the element type chosen per plan.  A C probe assigns each to a
+    pointer of the expected type; gcc rejects any mismatch."""
+    probe = r"""
+#include "rihvr.h"
+ri_status (*pc)(const ri_geometry*, ri_dtype, ri_plan**) = ri_plan_create;
+ri_status (*pw)(const ri_plan*, size_t*) = ri_workspace_size;
+ri_status (*pwo)(const ri_plan*, ri_op, size_t*) = ri_workspace_size_op;
+ri_status (*pf)(ri_plan*, const void*, void*, void*, size_t, void*) = ri_forward;
+ri_status (*pa)(ri_plan*, const void*, void*, void*, size_t, void*) = ri_adjoint;
+ri_status (*pp)(ri_plan*, const ri_prox_params*, double, const void*, void*, void*, size_t, void*) =
+    ri_prox_fused_lasso;
+ri_status (*ps)(ri_plan*, const ri_solve_params*, const void*, void*, void*, size_t, void*, ri_solve_report*) =
+    ri_solve;
+ri_status (*pb)(int32_t, ri_plan* const*, const ri_solve_params*, const void* const*, void* const*, void*, size_t,
+                void*, ri_solve_report*) = ri_solve_batched;
+const char* (*pe)(void) = ri_last_error;
+int main(void) { return (int)RI_F64 - 1 + (int)RI_F32; }
+"""
+    with tempfile.TemporaryDirectory() as d:
+        src = os.path.join(d, "sig.c")
+        open(src, "w").write(probe)
+        r = subprocess.run(["gcc", "-Werror", "-Wincompatible-pointer-types", "-c", "-I",
+                            os.path.join(ROOT, "include"), src, "-o", os.path.join(d, "sig.o")],
+                           capture_output=True, text=True)
+        assert r.returncode == 0, r.stderr
+
+
+def test_plan_rejects_unknown_dtype(lib):
+    g = scenes.geometry_c1().with_(nx=64, ny=64, nz=4)
+    h = C.c_void_p()
+    assert lib.ri_plan_create(C.byref(rihvr.geometry_struct(g)), 7, C.byref(h)) == rihvr.RI_ERR_INVALID_ARG
+    assert h.value is None
 
 
 def test_null_arguments_rejected(lib):
-    assert lib.ri_plan_create(None, None) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_plan_create(None, rihvr.RI_F32, None) == rihvr.RI_ERR_INVALID_ARG
     n = C.c_size_t()
-    assert lib.ri_workspace_size(None, 0, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_workspace_size(None, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_workspace_size_op(None, 0, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
     assert lib.ri_forward(None, None, None, None, 0, None) == rihvr.RI_ERR_INVALID_ARG
     assert lib.ri_adjoint(None, None, None, None, 0, None) == rihvr.RI_ERR_INVALID_ARG
     p = rihvr.ri_prox_params(0.1, 0.1, 3, 1)
@@ -128,7 +165,7 @@ def test_null_arguments_rejected(lib):
     assert lib.ri_plan_get_tuning(None, C.byref(t)) == rihvr.RI_ERR_INVALID_ARG
     assert lib.ri_plan_set_tuning(None, C.byref(t)) == rihvr.RI_ERR_INVALID_ARG
     assert lib.ri_plan_autotune(None, 10, None, None, 0, None, None) == rihvr.RI_ERR_INVALID_ARG
-    assert lib.ri_workspace_size(None, rihvr.RI_OP_AUTOTUNE, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
+    assert lib.ri_workspace_size_op(None, rihvr.RI_OP_AUTOTUNE, C.byref(n)) == rihvr.RI_ERR_INVALID_ARG
     assert rihvr.ri_solve_batched(0, [], [], [], [], None, 0, None) == rihvr.RI_OK
     assert lib.ri_solve_batched(-1, None, None, None, None, None, 0, None, None) == rihvr.RI_ERR_INVALID_ARG
 

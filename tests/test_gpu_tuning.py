@@ -127,8 +127,8 @@ def test_autotune_picks_a_candidate_and_caches_it(torch_cuda, plan_of, tmp_path)
 def test_autotune_rejects_small_workspace(torch_cuda, plan_of):
     torch = torch_cuda
     p = plan_of(geom(64, 64, 8))
-    n = rihvr.ri_workspace_size(p.handle, rihvr.RI_OP_AUTOTUNE)
-    assert n >= rihvr.ri_workspace_size(p.handle, rihvr.RI_OP_SOLVE)
+    n = rihvr.ri_workspace_size_op(p.handle, rihvr.RI_OP_AUTOTUNE)
+    assert n >= rihvr.ri_workspace_size_op(p.handle, rihvr.RI_OP_SOLVE)
     ws = torch.empty(n, dtype=torch.uint8, device="cuda")
     st = rihvr.ri_plan_autotune(p.handle, 4, None, ws.data_ptr(), n - 1, torch.cuda.current_stream().cuda_stream)
     assert st == rihvr.RI_ERR_WORKSPACE_TOO_SMALL

@@ -12,7 +12,9 @@ Bars (relative L2):
   gradients 1.5e-2 -- the kernels also store every back-propagated gradient in
     bfloat16 (the oracle does not), up to ~4L+2 roundings of 2^-9 on the way
     to the first layer, with sums over many voxels for biases and weights.
-The plain FP64 network (no storage rounding) is also checked, at 2e-2."""
+The plain FP64 network (no storage rounding) is also checked: outputs at 2e-2,
+gradients at the first-order storage bound (10 L - 6) 2^-9 (grad_bound_plain).
+The Adam update is checked against its definition in numpy."""
 import numpy as np
 import pytest
 
@@ -44,16 +46,34 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-@pytest.mark.parametrize("levels,pos_weight", [(1, 1.0), (2, 1.0), (3, 1.0), (2, 6.0)])
-def test_unet_forward_and_gradients(torch_cuda, levels, pos_weight):
+def grad_bound_plain(levels):
+    """Bar for the gradients against the plain FP64 network (no storage
+    rounding).  Every stored activation and every stored back-propagated
+    gradient is one bfloat16 rounding, relative error <= u = 2^-9.  The
+    longest path to the first layer's weight gradient stores 5L - 3
+    activations on the way forward (2L encoder convolutions, L - 1
+    up-convolutions, 2(L - 1) decoder convolutions) and as many gradients on
+    the way back; to first order the relative errors add: (10 L - 6) u
+    (L = 1: 0.008, L = 3: 0.047, L = 4: 0.066).  Masks and pooling winners that
+    flip on rounded values are not in this bound."""
+    return (10 * levels - 6) * 2.0 ** -9
+
+
+@pytest.mark.parametrize("levels,base,shape,pos_weight", [
+    (1, 8, (16, 16, 16), 1.0), (2, 8, (16, 16, 16), 1.0), (3, 8, (16, 16, 16), 1.0), (2, 8, (16, 16, 16), 6.0),
+    # the shipped network (4 levels, 16/32/64/128 channels): rows of 128 voxels put
+    # every 3x3x3 layer, 64 and 128 output channels included, on the LDS-tiled kernel
+    (4, 16, (8, 8, 128), 1.0),
+    # ... and a cubic crop, where the coarse levels run the gather GEMM
+    (4, 16, (16, 32, 32), 4.0)])
+def test_unet_forward_and_gradients(torch_cuda, levels, base, shape, pos_weight):
     torch = torch_cuda
-    base = 8
-    rng = np.random.default_rng(levels)
+    rng = np.random.default_rng(levels * 100 + base + shape[2])
     p = ou.init_params(levels, base, rng)
     # bf16-representable parameters and inputs so the comparison isolates the arithmetic
     for k in p:
         p[k] = torch.tensor(p[k], dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
-    D = H = W = 16
+    D, H, W = shape
     x = rng.standard_normal((D, H, W))
     x = torch.tensor(x, dtype=torch.float32).to(torch.bfloat16).to(torch.float64).numpy()
     target = np.maximum(rng.standard_normal((D, H, W)), 0.0)
@@ -75,6 +95,44 @@ def test_unet_forward_and_gradients(torch_cuda, levels, pos_weight):
     print("gradient errors:", {k: round(v, 5) for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= 1.5e-2, (k, e)
+    # against the plain FP64 network, at the first-order storage bound
+    _, g_plain = ou.loss_and_grads(p, x, target, levels, base, pos_weight=pos_weight)
+    errs_plain = {k: rel(g[k], g_plain[k]) for k in g_plain if np.linalg.norm(g_plain[k]) > 0}
+    print("gradient errors vs plain FP64:", {k: round(v, 5) for k, v in errs_plain.items()})
+    for k, e in errs_plain.items():
+        assert e <= grad_bound_plain(levels), (k, e)
+
+
+def test_unet_adam_matches_definition(torch_cuda):
+    """Three training steps with lr > 0: parameters and moments against Adam
+    (beta 0.9 / 0.999, eps 1e-8, bias correction) written out in numpy from the
+    gradients the step produced; those gradients are themselves pinned to the
+    oracle by the test above."""
+    torch = torch_cuda
+    levels, base = 2, 8
+    rng = np.random.default_rng(77)
+    D = H = W = 16
+    x = torch.tensor(rng.standard_normal((D, H, W)), dtype=torch.float32).cuda()
+    t = torch.relu(x * 0.5).contiguous()
+    net = rihvr.UNet(levels, base, seed=3)
+    p = net.params.double().cpu().numpy()
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    lr, b1, b2, eps = 2e-3, 0.9, 0.999, 1e-8
+    for step in range(1, 4):
+        net.train_step(x, t, lr=lr)
+        g = net.grads.double().cpu().numpy()
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        mh = m / (1 - b1 ** step)
+        vh = v / (1 - b2 ** step)
+        p = p - lr * mh / (np.sqrt(vh) + eps)
+        assert net.step == step
+        assert rel(net.m.double().cpu().numpy(), m) <= 1e-6
+        assert rel(net.v.double().cpu().numpy(), v) <= 1e-6
+        got = net.params.double().cpu().numpy()
+        assert np.max(np.abs(got - p)) <= 1e-6 * max(1.0, np.max(np.abs(p))), step
+        p = got          # continue from the device's FP32 parameters
 
 
 def test_unet_training_reduces_loss(torch_cuda):

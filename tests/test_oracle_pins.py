@@ -333,21 +333,106 @@ def test_objective_terms():
     assert F == pytest.approx(0.5 * (r * r).sum() + 0.3 * x.sum() + 0.2 * prox.tv3(x), rel=1e-14)
 
 
-def test_fista_momentum_sequence_and_restart_history():
-    g = small_geom(nx=16, ny=16, nz=3)
-    rng = np.random.default_rng(16)
-    b = rng.standard_normal((16, 16))
-    _, hist = fista.fista(g, b, 0.01, 0.01, 30, 5, history=True)
-    _, hist_r = fista.fista(g, b, 0.01, 0.01, 30, 5, restart=True, history=True)
-    # with restart the objective never increases
-    assert all(bb <= a * (1 + 1e-12) for a, bb in zip(hist_r, hist_r[1:])) or min(hist_r) <= min(hist)
-    assert hist_r[-1] <= hist[0]
+def _identity_scene():
+    """A = I (one plane at z = 0) and a checkerboard hologram of 1 and 0.05."""
+    g = small_geom(nx=16, ny=16, nz=1, z0_um=0.0)
+    yy, xx = np.mgrid[0:16, 0:16]
+    b = np.where((yy + xx) % 2 == 0, 1.0, 0.05)
+    return g, b
+
+
+def _golden_fista():
+    rows = [ln.split() for ln in open(os.path.join(GOLDEN, "fista_identity_operator.txt"))
+            if ln.strip() and not ln.startswith("#")]
+    return [(int(r[0]), float(r[1]), float(r[2])) for r in rows]
+
+
+def test_fista_iterates_hand_derived_identity_operator():
+    """FISTA's momentum and extrapolation against iterates derived by hand for
+    A = I, step 1/2 (tests/golden/fista_identity_operator.txt).  A slip such as
+    beta = (s_{k+1} - 1)/s_{k+1} changes x_2 already."""
+    g, b = _identity_scene()
+    on = b == 1.0
+    for k, x_plain, _ in _golden_fista():
+        if math.isnan(x_plain):
+            continue
+        x = fista.fista(g, b, 0.1, 0.0, k, 3, step=0.5)[0]
+        assert np.max(np.abs(x[on] - x_plain)) <= 1e-14, (k, x[on][0], x_plain)
+        assert np.max(np.abs(x[~on])) <= 1e-15, k      # thresholded to zero in every iteration
+
+
+def test_fista_restart_hand_derived_identity_operator():
+    """Function-value restart: the objective first increases at iterate 5 of
+    the same A = I problem; the momentum is then reset (s = 1, beta = 0)."""
+    g, b = _identity_scene()
+    on = b == 1.0
+    for k, _, x_restart in _golden_fista():
+        x = fista.fista(g, b, 0.1, 0.0, k, 3, step=0.5, restart=True)[0]
+        assert np.max(np.abs(x[on] - x_restart)) <= 1e-14, (k, x[on][0], x_restart)
+    # the history records F of every iterate; with restart it rises exactly once
+    _, hist = fista.fista(g, b, 0.1, 0.0, 7, 3, step=0.5, restart=True, history=True)
+    rises = [k + 1 for k in range(1, len(hist)) if hist[k] > hist[k - 1]]
+    assert rises == [5], rises
+
+
+# --- Detection (segmentation paragraph of "Methodology"; connectivity reading) ---
+def test_detect_corner_touching_voxels_form_one_object():
+    """26-connectivity: a voxel that touches a 4-voxel bar only at a corner
+    joins it into one 5-voxel object, which meets the minimum volume; under
+    6- or 18-connectivity both pieces would fall below it and vanish."""
+    x = np.zeros((6, 6, 7))
+    x[2, 2, 1:5] = 1.0          # bar of 4 voxels along x
+    x[3, 3, 5] = 1.0            # corner neighbour of (2, 2, 4)
+    c = detect.detect(x)
+    assert c.shape == (1, 3)
+    # centroid of the five unit voxels, by hand: z (2*4 + 3)/5, y (2*4 + 3)/5, x (1+2+3+4+5)/5
+    assert np.allclose(c[0], [11 / 5, 11 / 5, 3.0], atol=1e-15)
+
+
+def test_detect_minimum_volume_and_threshold():
+    x = np.zeros((8, 8, 8))
+    x[1, 1, 0:4] = 1.0          # 4 voxels: dropped
+    x[5, 5, 0:5] = 1.0          # 5 voxels: kept
+    c = detect.detect(x)
+    assert c.shape == (1, 3) and np.allclose(c[0], [5, 5, 2], atol=1e-15)
+    # voxels at exactly max/256 are below the (strict) threshold, just above it count
+    y = np.zeros((8, 8, 8))
+    y[4, 4, 0:4] = 1.0
+    y[4, 4, 4] = 1.0 / 256.0
+    assert detect.detect(y).shape == (0, 3)
+    y[4, 4, 4] = 1.0 / 256.0 * (1 + 1e-12)
+    assert detect.detect(y).shape == (1, 3)
+
+
+def test_detect_intensity_weighted_centroid():
+    """Centroid weighted by the voxel values, computed by hand:
+    x = (0*1 + 1*2 + 2*3 + 3*4 + 4*10) / 20 = 3, y = (1*18 + 2*2) / 20 = 1.1."""
+    x = np.zeros((4, 4, 6))
+    x[1, 1, 0:5] = [1.0, 2.0, 3.0, 4.0, 8.0]
+    x[1, 2, 4] = 2.0
+    c = detect.detect(x)
+    assert c.shape == (1, 3)
+    assert np.allclose(c[0], [1.0, 1.1, 3.0], atol=1e-15)
+
+
+def test_match_nearest_neighbour_within_radius():
+    truth = np.array([[0.0, 0.0, 0.0], [10.0, 10.0, 10.0], [20.0, 0.0, 0.0]])
+    found = np.array([[10.5, 10.0, 10.0], [0.0, 1.0, 0.0], [0.0, 0.0, 0.5], [20.0, 3.0, 0.0]])
+    pairs, errs = detect.match(found, truth, max_dist=2.0)
+    # (0,0,0) takes the closer of its two candidates; (20,0,0) has none within 2
+    assert sorted(pairs) == [(0, 2), (1, 0)]
+    assert np.allclose(sorted(np.abs(errs).sum(axis=1)), [0.5, 0.5])
 
 
 # --- P15: particle recovery at C1 (behaviour, not parity) ---------------------
 @pytest.mark.slow
-def test_p15_recovery_c1():
-    sc = scenes.scene_c1(seed=0)
+@pytest.mark.parametrize("seed", [0, 1])
+def test_p15_recovery_c1(seed):
+    """Behaviour, not parity: the 50 x 10-iteration C1 solve finds most particles
+    within one voxel.  Measured with the 2/256 threshold of the synthetic
+    turbulence study: seed 0 40/50 found, 17 false objects; seed 1 42/50, 11;
+    seed 2 44/50, 9.  The bar sits just below the worst of these."""
+    sc = scenes.scene_c1(seed=seed)
     g, cfg = sc.geometry, sc.config
     b = optics.forward(g, sc.dense()) + sc.noise
     x = fista.fista(g, b, cfg.l1, cfg.tv, cfg.outer_iters, cfg.inner_iters)
@@ -355,7 +440,9 @@ def test_p15_recovery_c1():
     pairs, errs = detect.match(found, sc.centers, max_dist=2.0)
     within = [e for e in errs if abs(e[0]) <= 1 and abs(e[1]) <= 1 and abs(e[2]) <= 1]
     ep = len(within) / len(sc.centers)
-    assert ep >= 0.75, (ep, len(found))
+    false_pos = len(found) - len(pairs)
+    assert ep >= 0.78, (ep, len(found))
+    assert false_pos <= 20, false_pos
 
 
 # --- U-Net oracle: layers against brute force, network gradient by finite differences ---
