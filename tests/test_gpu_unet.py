@@ -12,9 +12,13 @@ Bars (relative L2):
   gradients 1.5e-2 -- the kernels also store every back-propagated gradient in
     bfloat16 (the oracle does not), up to ~4L+2 roundings of 2^-9 on the way
     to the first layer, with sums over many voxels for biases and weights.
-The plain FP64 network (no storage rounding) is also checked: outputs at 2e-2,
-gradients at the first-order storage bound (10 L - 6) 2^-9 (grad_bound_plain).
-The Adam update is checked against its definition in numpy."""
+The plain FP64 network (no storage rounding) is also checked: outputs at 2e-2;
+gradients against the distance that bfloat16 storage alone puts between the
+two FP64 networks (grad_bound_plain).  A fixed bar does not hold there: a
+weight gradient is a sum over voxels whose terms cancel, so per-term storage
+errors of a few 2^-9 grow by the sum's condition number (measured 0.040 for
+the first layer of a 2-level network against a first-order (10 L - 6) 2^-9 =
+0.027).  The Adam update is checked against its definition in numpy."""
 import numpy as np
 import pytest
 
@@ -46,17 +50,16 @@ def rel(a, b):
     return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-30))
 
 
-def grad_bound_plain(levels):
-    """Bar for the gradients against the plain FP64 network (no storage
-    rounding).  Every stored activation and every stored back-propagated
-    gradient is one bfloat16 rounding, relative error <= u = 2^-9.  The
-    longest path to the first layer's weight gradient stores 5L - 3
-    activations on the way forward (2L encoder convolutions, L - 1
-    up-convolutions, 2(L - 1) decoder convolutions) and as many gradients on
-    the way back; to first order the relative errors add: (10 L - 6) u
-    (L = 1: 0.008, L = 3: 0.047, L = 4: 0.066).  Masks and pooling winners that
-    flip on rounded values are not in this bound."""
-    return (10 * levels - 6) * 2.0 ** -9
+def grad_bound_plain(e_storage):
+    """Bar for a gradient against the plain FP64 network.  e_storage is the
+    relative L2 distance between the FP64 network that stores its activations
+    in bfloat16 and the plain one (CPU only).  By the triangle inequality the
+    kernels sit within e_storage + e_kernel of the plain network, where
+    e_kernel is their distance to the storage-rounded oracle (measured
+    <= 2e-3, bar 1.5e-2).  The bar allows 25 % above the storage effect plus
+    5e-3: the kernels may add their own rounding (bfloat16 back-propagated
+    gradients, FP32 sums) but nothing of the size of the storage effect."""
+    return 1.25 * e_storage + 5e-3
 
 
 @pytest.mark.parametrize("levels,base,shape,pos_weight", [
@@ -95,12 +98,14 @@ def test_unet_forward_and_gradients(torch_cuda, levels, base, shape, pos_weight)
     print("gradient errors:", {k: round(v, 5) for k, v in errs.items()})
     for k, e in errs.items():
         assert e <= 1.5e-2, (k, e)
-    # against the plain FP64 network, at the first-order storage bound
+    # against the plain FP64 network, within what bfloat16 storage alone explains
     _, g_plain = ou.loss_and_grads(p, x, target, levels, base, pos_weight=pos_weight)
     errs_plain = {k: rel(g[k], g_plain[k]) for k in g_plain if np.linalg.norm(g_plain[k]) > 0}
+    e_storage = {k: rel(g_ref[k], g_plain[k]) for k in errs_plain}
     print("gradient errors vs plain FP64:", {k: round(v, 5) for k, v in errs_plain.items()})
+    print("storage effect (oracle vs oracle):", {k: round(v, 5) for k, v in e_storage.items()})
     for k, e in errs_plain.items():
-        assert e <= grad_bound_plain(levels), (k, e)
+        assert e <= grad_bound_plain(e_storage[k]), (k, e, e_storage[k])
 
 
 def test_unet_adam_matches_definition(torch_cuda):
