@@ -206,6 +206,21 @@ ri_status ri_forward(ri_plan* plan, const void* x, void* b_out,
                      void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * b_out = A x as ri_forward computes it (same kernels, same result), for
+ * callers that cannot allocate device memory or hand over a workspace: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  The scratch space lives in a fixed device array of
+ * ri_forward_noalloc_max_scratch() bytes (64 MiB) that each device the library
+ * runs on holds until the process ends; the call allocates nothing.  Sizes
+ * whose forward needs more scratch than that (ri_workspace_size_op with
+ * RI_OP_FORWARD, e.g. above about 512 x 512 x 64 planes) return
+ * RI_ERR_UNSUPPORTED_SIZE.  All calls on one device share the array: calls
+ * that overlap in time on one device (two streams, two threads) race.
+ */
+ri_status ri_forward_noalloc(ri_plan* plan, const void* x, void* b_out, void* stream);
+size_t ri_forward_noalloc_max_scratch(void);
+
+/*
  * x_out = A^T y, the back-propagation (A^T y)_j = Re(IFFT2(FFT2(y) . conj(H_j))):
  * the adjoint of the model of section "Methodology", which the gradient
  * A^T (A x - b) of the data term of Eq. 2 needs in the shrinkage step of

@@ -11,6 +11,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -416,6 +417,67 @@ extern "C" ri_status ri_forward(ri_plan* p, const void* xv, void* bv, void* ws, 
   if (st != RI_OK) return st;
   if (overlaps(x, vb, b_out, hb)) return fail(RI_ERR_INVALID_ARG, "x and b_out overlap");
   HIP_TRY(enqueue_forward(p, make_layout(p, RI_OP_FORWARD), ws, x, b_out, (hipStream_t)stream));
+  return RI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Forward model without a caller workspace, for callers that cannot allocate
+// (graph capture, serving loops).  Its scratch (the plane spectra, the
+// z-chunk partial spectra and the summed hologram spectrum of ri_forward) lives
+// in a fixed device array; every device the library runs on holds its own copy
+// until the process ends.  Calls on one device share that copy, so calls that
+// overlap on one device race; nothing in it needs clearing, since the forward
+// writes every scratch element it later reads.
+// ---------------------------------------------------------------------------
+constexpr size_t kStaticScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on device `dev` (current), looked up once per
+// device.  The array's name is only a host-side handle for the symbol.
+static ri_status static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(RI_ERR_INVALID_ARG, "device %d outside 0..%d", dev, kMaxDevices - 1);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(RI_ERR_HIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return RI_OK;
+}
+
+extern "C" size_t ri_forward_noalloc_max_scratch(void) { return kStaticScratchBytes; }
+
+extern "C" ri_status ri_forward_noalloc(ri_plan* p, const void* xv, void* bv, void* stream) {
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  const float* x = static_cast<const float*>(xv);
+  float* b_out = static_cast<float*>(bv);
+  if (!x || !b_out) return fail(RI_ERR_INVALID_ARG, "input or output pointer is NULL");
+  if (((uintptr_t)x & 7) || ((uintptr_t)b_out & 7))
+    return fail(RI_ERR_INVALID_ARG, "input and output must be 8-byte aligned");
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
+  if (overlaps(x, vb, b_out, hb)) return fail(RI_ERR_INVALID_ARG, "x and b_out overlap");
+  const Layout L = make_layout(p, RI_OP_FORWARD);
+  if (L.total > kStaticScratchBytes)
+    return fail(RI_ERR_UNSUPPORTED_SIZE,
+                "nx=%d ny=%d nz=%d needs %zu bytes of scratch; the allocation-free forward holds %zu "
+                "(use ri_forward with a workspace)",
+                p->g.nx, p->g.ny, p->g.nz, L.total, kStaticScratchBytes);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != p->device) return fail(RI_ERR_INVALID_ARG, "plan belongs to device %d, current device is %d", p->device, dev);
+  void* ws = nullptr;
+  const ri_status st = static_scratch(dev, &ws);
+  if (st != RI_OK) return st;
+  if (overlaps(ws, kStaticScratchBytes, x, vb) || overlaps(ws, kStaticScratchBytes, b_out, hb))
+    return fail(RI_ERR_INVALID_ARG, "an argument lies inside the library's scratch array");
+  HIP_TRY(enqueue_forward(p, L, ws, x, b_out, (hipStream_t)stream));
   return RI_OK;
 }
 

@@ -45,7 +45,7 @@ PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size", "ri_workspace_size_op",
     "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_autotune",
-    "ri_forward", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
+    "ri_forward", "ri_forward_noalloc", "ri_forward_noalloc_max_scratch", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
     "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
     "ri_unet_train_step",
@@ -136,6 +136,8 @@ def lib():
     L.ri_plan_set_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
     L.ri_plan_autotune.argtypes = [vp, C.c_int32, C.c_char_p, vp, sz, vp, C.POINTER(ri_autotune_report)]
     L.ri_forward.argtypes = [vp, vp, vp, vp, sz, vp]
+    L.ri_forward_noalloc.argtypes = [vp, vp, vp, vp]
+    L.ri_forward_noalloc_max_scratch.argtypes = []
     L.ri_adjoint.argtypes = [vp, vp, vp, vp, sz, vp]
     L.ri_prox_fused_lasso.argtypes = [vp, C.POINTER(ri_prox_params), C.c_double, vp, vp, vp, sz, vp]
     L.ri_solve.argtypes = [vp, C.POINTER(ri_solve_params), vp, vp, vp, sz, vp, C.POINTER(ri_solve_report)]
@@ -150,12 +152,13 @@ def lib():
     L.ri_unet_forward.argtypes = [cfgp, vp, vp, fp, vp, C.c_int32, C.c_int32, C.c_int32, vp, sz, vp]
     L.ri_unet_train_step.argtypes = [cfgp, vp, vp, vp, vp, C.c_int32, fp, vp, fp, vp, fp, C.c_int32, C.c_int32,
                                      C.c_int32, vp, vp, sz, vp]
+    L.ri_forward_noalloc_max_scratch.restype = C.c_size_t
     L.ri_status_string.argtypes = [C.c_int]
     L.ri_status_string.restype = C.c_char_p
     L.ri_last_error.argtypes = []
     L.ri_last_error.restype = C.c_char_p
     for name in EXPORTED:
-        if name not in ("ri_status_string", "ri_last_error"):
+        if name not in ("ri_status_string", "ri_last_error", "ri_forward_noalloc_max_scratch"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -216,6 +219,14 @@ def ri_plan_autotune(plan, inner_iters, cache_path, ws, ws_bytes, stream, report
 
 def ri_forward(plan, x, b_out, ws, ws_bytes, stream) -> int:
     return lib().ri_forward(plan, x, b_out, ws, ws_bytes, stream)
+
+
+def ri_forward_noalloc(plan, x, b_out, stream) -> int:
+    return lib().ri_forward_noalloc(plan, x, b_out, stream)
+
+
+def ri_forward_noalloc_max_scratch() -> int:
+    return int(lib().ri_forward_noalloc_max_scratch())
 
 
 def ri_adjoint(plan, y, x_out, ws, ws_bytes, stream) -> int:
