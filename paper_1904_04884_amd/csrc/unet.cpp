@@ -478,6 +478,6 @@ extern "C" ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params
   st = backward(n, params, target, pos_weight, grads, d, h, w, ws, B, s);
   if (st != RI_OK) return st;
   if (loss_out) UTRY(hipMemcpyAsync(loss_out, at<float>(ws, B.loss), sizeof(float), hipMemcpyDeviceToDevice, s));
-  if (lr > 0) UTRY(launch_adam(params, grads, adam_m, adam_v, n.nparams, lr, 0.9f, 0.999f, 1e-8f, step, s));
+  if (lr > 0) UTRY(launch_adam(params, grads, adam_m, adam_v, n.nparams, lr, 0.9, 0.999, 1e-8, step, s));
   return RI_OK;
 }

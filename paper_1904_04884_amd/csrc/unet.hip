@@ -15,6 +15,8 @@
 //   D (16 x 16): rows 4 (l / 16) .. 4 (l / 16) + 3, column l % 16
 #include <type_traits>
 
+#include <cmath>
+
 #include "unet_internal.h"
 
 namespace rihvr {
@@ -535,12 +537,14 @@ __global__ void k_mse(const float* y, const float* t, long n, float inv_n, float
 }
 
 // Adam on FP32 master weights
+// Adam.  a1 = 1 - b1, a2 = 1 - b2 and the bias corrections c1, c2 come from
+// the host in FP64 (1 - 0.999f in FP32 is off by 5e-5 relative).
 __global__ void k_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
-                       float eps, float c1, float c2) {
+                       float a1, float a2, float eps, float c1, float c2) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.f - b1) * gi;
-    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    const float mi = b1 * m[i] + a1 * gi;
+    const float vi = b2 * v[i] + a2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
     w[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
@@ -702,10 +706,11 @@ hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint1
   return hipGetLastError();
 }
 
-hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
-                       int step, hipStream_t s) {
-  const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
-  hipLaunchKernelGGL(k_adam, dim3(ew_grid(n)), dim3(256), 0, s, w, g, m, v, n, lr, b1, b2, eps, c1, c2);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, double b1, double b2,
+                       double eps, int step, hipStream_t s) {
+  const float c1 = (float)(1.0 - std::pow(b1, (double)step)), c2 = (float)(1.0 - std::pow(b2, (double)step));
+  hipLaunchKernelGGL(k_adam, dim3(ew_grid(n)), dim3(256), 0, s, w, g, m, v, n, lr, (float)b1, (float)b2,
+                     (float)(1.0 - b1), (float)(1.0 - b2), (float)eps, c1, c2);
   return hipGetLastError();
 }
 

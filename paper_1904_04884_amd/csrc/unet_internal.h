@@ -55,8 +55,8 @@ hipError_t launch_zero_u16(uint16_t* p, size_t n, hipStream_t s);
 hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long nvox, hipStream_t s);
 hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint16_t* g, int gcs, float* loss,
                       hipStream_t s);
-hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2, float eps,
-                       int step, hipStream_t s);
+hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, double b1, double b2,
+                       double eps, int step, hipStream_t s);
 hipError_t launch_pack(const float* w, int T, int cin, int cout, int transpose, int Npad, int Cpad, uint16_t* out,
                        hipStream_t s);
 hipError_t launch_pack_up_fwd(const float* u, int cin, int cout, uint16_t* out, hipStream_t s);
