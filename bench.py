@@ -22,6 +22,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "holograms/s to objective gap 1e-4 at 1024²×256; voxel-iters/s vs plain FISTA"
 HBM_PEAK_GBS = 8000.0
+# FP32 FMA peak without packed instructions (every HIP file is built with packed
+# FP32 off): 256 CUs x 2.4 GHz x 64 lanes x 2 FLOP
+FP32_PEAK_TFLOPS = 78.6
 
 
 def log(*a):
@@ -91,29 +94,107 @@ def build_scene(torch, rihvr, scenes, plan, seed):
     return sc, x_true, b
 
 
-def cpu_baseline(scenes, iters_to_gap, nvox_full, cfg):
-    """The FP64 oracle on a bounded sample: one FISTA iteration on a slab of the
-    full geometry (same lateral size and optics, 8 planes)."""
+def _oracle_slab_iteration(args):
+    """One FISTA iteration of the FP64 oracle on one slab (a worker process)."""
+    nz, seed = args
     import oracle
-    g = scenes.geometry_c2().with_(nz=8)
-    rng = np.random.default_rng(0)
+    from paper_1904_04884_amd import scenes
+    cfg = scenes.config_c2()
+    g = scenes.geometry_c2().with_(nz=nz)
+    rng = np.random.default_rng(seed)
     b = 0.05 * rng.standard_normal((g.ny, g.nx))
     t0 = time.perf_counter()
     oracle.fista.fista(g, b, cfg.l1, cfg.tv, 1, cfg.inner_iters)
+    return g.nx * g.ny * g.nz, time.perf_counter() - t0
+
+
+def host_cores():
+    """CPUs this process may run on (the box's share, not the machine's count)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_baseline(scenes, iters_to_gap, nvox_full, cfg, workers=None):
+    """The FP64 oracle on a bounded sample, on every host core: each worker
+    process runs one FISTA iteration of the unchanged (single-threaded numpy)
+    oracle on its own 8-plane slab of the full geometry (same lateral size and
+    optics); the rate is the slabs' voxels over the wall time of the pool."""
+    import multiprocessing as mp
+    n = workers or min(16, host_cores())
+    ctx = mp.get_context("spawn")          # the parent holds a GPU context: no fork
+    t0 = time.perf_counter()
+    with ctx.Pool(n) as pool:
+        res = pool.map(_oracle_slab_iteration, [(8, s) for s in range(n)])
     dt = time.perf_counter() - t0
-    nvox = g.nx * g.ny * g.nz
+    nvox = sum(r[0] for r in res)
     vit = nvox / dt
+    g = scenes.geometry_c2()
     return {
         "value": vit / (nvox_full * max(iters_to_gap, 1)),
         "unit": "holograms/s",
-        "cores": 1,
+        "cores": n,
         "kind": "oracle",
-        "sample": (f"1 FISTA iteration (K_in={cfg.inner_iters}) of the FP64 numpy oracle on a "
-                   f"{g.nx}x{g.ny}x{g.nz} slab of the same optics ({dt:.1f} s, {vit:.3g} voxel-iters/s), "
-                   f"scaled to {iters_to_gap} iterations of {nvox_full} voxels"),
+        "sample": (f"{n} worker processes, each 1 FISTA iteration (K_in={cfg.inner_iters}) of the FP64 numpy "
+                   f"oracle on its own {g.nx}x{g.ny}x8 slab of the same optics ({dt:.1f} s wall including "
+                   f"process start, {vit:.3g} voxel-iters/s), scaled to {iters_to_gap} iterations of "
+                   f"{nvox_full} voxels"),
         "voxel_iters_per_s": vit,
-        "host_cpus": os.cpu_count(),
+        "slab_seconds": [round(r[1], 2) for r in res],
+        "host_cpus": host_cores(),
     }
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=5):
+    """Device-to-device copy bandwidth (read + write bytes over time) of a
+    1 GiB buffer, HIP events on the current stream."""
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return {"GB_per_s": 2.0 * nbytes / (ms * 1e-3) / 1e9, "bytes": nbytes, "ms": ms,
+            "frac_of_peak": 2.0 * nbytes / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+
+
+def fft_rates(torch, plan, g, reps=10):
+    """FFT FLOP/s of the library's A and A^T (dense, every row), HIP events
+    on the current stream.  FLOPs by the 5 N log2 N convention per complex
+    transform of length N, half of it for a real-input (R2C / C2R) row:
+    A = nz*ny R2C rows + nz*(nx/2) columns + (nx/2) inverse columns + ny C2R
+    rows; A^T = ny R2C rows + (nx/2) columns + nz*(nx/2) inverse columns +
+    nz*ny C2R rows (the filter multiplies are not counted)."""
+    import math
+    nx, ny, nz, m = g.nx, g.ny, g.nz, g.nx // 2
+    row = 2.5 * nx * math.log2(nx)
+    col = 5.0 * ny * math.log2(ny)
+    flops = nz * ny * row + nz * m * col + m * col + ny * row       # same count for A and A^T
+    x = torch.zeros((nz, ny, nx), dtype=torch.float32, device="cuda")
+    x[::7, ::5, ::3] = 1.0
+    y = torch.randn((ny, nx), dtype=torch.float32, device="cuda")
+    out = {}
+    for name, fn in (("forward", lambda: plan.forward(x)), ("adjoint", lambda: plan.adjoint(y))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        tf = flops / (ms * 1e-3) / 1e12
+        out[name] = {"ms": ms, "gflop": flops / 1e9, "tflops": tf, "frac_of_peak": tf / FP32_PEAK_TFLOPS}
+    out["peak_tflops"] = FP32_PEAK_TFLOPS
+    out["convention"] = "5 N log2 N per complex transform, half for real rows; A and A^T dense"
+    del x, y
+    return out
 
 
 def burgers_frames(scenes, n_frames, seed=0):
@@ -389,7 +470,8 @@ def main():
     ap.add_argument("--gap", type=float, default=1e-4)
     ap.add_argument("--check-every", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--plain", action="store_true", help="also time plain per-frame FISTA (dense, no graph)")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="skip the plain-FISTA leg (cold, dense, no graph) on the same hologram")
     ap.add_argument("--batched", type=int, default=0, help="run the batched uneven-frame mode with this many frames")
     ap.add_argument("--batch-iters", type=int, default=30)
     ap.add_argument("--warmstart", action="store_true", help="run the learned warm-start evaluation mode")
@@ -515,14 +597,25 @@ def main():
         log("copy calibration: 3 x 1 GiB device copies")
 
     plain = None
-    if args.plain:
+    if not args.no_plain:
+        # plain per-frame FISTA: the same solve with no row skipping and one
+        # launch at a time (no graph), cold start, same gap criterion
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         _, rep_p, _ = one_solve(flags=rihvr.RI_SOLVE_DENSE | rihvr.RI_SOLVE_NO_GRAPH)
         torch.cuda.synchronize()
         dtp = time.perf_counter() - t1
         plain = {"holograms_per_s": 1.0 / dtp, "iters": rep_p["iters"],
-                 "voxel_iters_per_s": nvox * rep_p["iters"] / dtp}
+                 "voxel_iters_per_s": nvox * rep_p["iters"] / dtp,
+                 "value_over_plain": value * dtp,
+                 "flags": "RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH, cold start"}
+        log(f"plain FISTA: {1.0 / dtp:.4f} holograms/s ({rep_p['iters']} iterations); "
+            f"headline / plain = {value * dtp:.3f}")
+    fft = fft_rates(torch, plan, g)
+    log("FFT: " + ", ".join(f"{k} {v['tflops']:.2f} TFLOP/s ({v['ms']:.3f} ms)"
+                            for k, v in fft.items() if isinstance(v, dict)))
+    copy_bw = copy_bandwidth(torch)
+    log(f"device copy: {copy_bw['GB_per_s']:.0f} GB/s")
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -561,9 +654,10 @@ def main():
         "phase_ms_per_iter": phase_ms_per_iter,
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "plain_fista": plain,
+        "fft": fft,
+        "copy_bandwidth": copy_bw,
     }
-    if plain is not None:
-        out["plain_fista"] = plain
     plan.close()
     print(json.dumps(out), flush=True)
 

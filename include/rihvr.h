@@ -58,20 +58,29 @@ typedef enum {
   RI_ERR_NOT_CONVERGED = 7       /* the objective diverged (grew past 10x F(x0)) */
 } ri_status;
 
-/* Element type of a plan's arrays.  RI_F32 is the production path; RI_F64
- * runs the same kernels instantiated for double (tables, transforms, prox and
- * objective all in FP64), which separates bugs from FP32 rounding. */
+/* Element type of a plan's arrays.  RI_F32 is the path this library computes
+ * in (FP32 data, FP64 phase reduction and accumulations).  RI_F64 is part of
+ * the interface but not built: ri_plan_create rejects it with
+ * RI_ERR_INVALID_ARG. */
 typedef enum { RI_F32 = 0, RI_F64 = 1 } ri_dtype;
 
 /* Geometry flags */
 #define RI_NO_CARRIER 0x1u  /* drop the exp(i 2 pi z / lambda) carrier from H_j */
+#define RI_TV2D       0x2u  /* regularise with the per-plane 2D TV of Eq. (4) (the paper's
+                               own regulariser: no differences across planes, GP step
+                               1/(8 tau), a dual of two components) instead of TV3D */
+#define RI_TV_FGP     0x4u  /* inner solver: the accelerated dual iteration (FGP of Beck and
+                               Teboulle) instead of plain gradient projection; one dual
+                               step per pass over memory, two duals per set in the workspace */
+#define RI_TV_DUAL_BF16 0x8u /* keep the TV dual in bfloat16 between passes over memory (the
+                               arithmetic stays FP32; the dual's bytes halve) */
 
 typedef struct {
   int32_t nx, ny, nz;       /* hologram width, height; number of planes */
   double pixel_um;          /* lateral pixel pitch, micrometres */
   double wavelength_um;     /* illumination wavelength, micrometres */
   double z0_um, dz_um;      /* plane j at z0 + j*dz from the sensor */
-  uint32_t flags;           /* RI_NO_CARRIER */
+  uint32_t flags;           /* RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16 */
 } ri_geometry;
 
 /* Fused-lasso proximal operator settings (Eq. 5, Eq. 6). */
@@ -88,8 +97,13 @@ typedef struct {
 
 #define RI_SOLVE_DENSE    0x1u  /* do not skip empty rows / planes in A */
 #define RI_SOLVE_NO_GRAPH 0x2u  /* launch kernels one by one instead of replaying a HIP graph */
-#define RI_SOLVE_RESTART  0x4u  /* function-value restart of the momentum (reference runs) */
+#define RI_SOLVE_RESTART  0x4u  /* function-value restart of the momentum: s = 1, beta = 0 after an
+                                   iterate whose objective rose (a FISTA variant; reference runs) */
 #define RI_SOLVE_TIMING   0x8u  /* time each phase with HIP events (report.phase_ms) */
+#define RI_SOLVE_DUAL_WARM 0x10u /* every prox starts its TV dual from the dual the previous
+                                    outer iteration ended with (zero for the first) instead of
+                                    from zero: an inexact inner solve that improves across
+                                    outer iterations */
 
 typedef struct {
   double l1, tv;            /* regularisation weights */
@@ -328,6 +342,75 @@ ri_status ri_unet_train_step(const ri_unet_config* cfg, float* params, float* gr
                              int32_t step, float lr, const float* in, float scale, const float* target,
                              float pos_weight, int32_t d, int32_t h, int32_t w, float* loss_out, void* ws,
                              size_t ws_bytes, void* stream);
+
+/*
+ * Particle tracking back end (section "Methodology", segmentation paragraph;
+ * section "Synthetic Turbulent Flow": weighted centroids of connected
+ * components, tracking by the method of Crocker & Grier with a maximum
+ * displacement per frame and a minimum track duration).  All arrays are
+ * device arrays; counts that the previous step produces stay on the device
+ * (int32 pointers), so a whole frame's detection, linking and track update
+ * run without a host synchronisation.
+ */
+typedef struct {
+  double rel_threshold;     /* foreground: x > rel_threshold * max(x); the paper uses 1/256 (2/256) */
+  int32_t min_voxels;       /* keep objects of at least this many voxels; the paper uses 5 */
+} ri_detect_params;
+
+/* One detected object: intensity-weighted centroid (voxel units, z y x),
+ * intensity sum, voxel count and its smallest linear voxel index (the order
+ * of the object table). */
+typedef struct { double z, y, x, weight, voxels, first; } ri_object;
+
+/* Workspace of ri_detect: a 32-bit label per voxel plus per-component sums for
+ * up to max_components connected components (before the minimum-volume
+ * filter).  Volumes up to 2^31 voxels. */
+ri_status ri_detect_workspace_size(int32_t nx, int32_t ny, int32_t nz, int32_t max_components, size_t* bytes);
+/*
+ * Segment the volume x [nz][ny][nx] (float32, device): foreground voxels
+ * x > rel_threshold * max(x) (compared in FP64), 26-connected components,
+ * objects of at least min_voxels voxels with their weighted centroids,
+ * written to objects[0 .. counts[0]) in order of their smallest linear voxel
+ * index.  counts (device int32[2]) receives the number of kept objects and
+ * the number of components; objects beyond max_objects and components beyond
+ * max_components are not written (the counts still tell).  Asynchronous.
+ */
+ri_status ri_detect(const ri_detect_params* params, const float* x, int32_t nx, int32_t ny, int32_t nz,
+                    ri_object* objects, int32_t max_objects, int32_t* counts, int32_t max_components,
+                    void* ws, size_t ws_bytes, void* stream);
+
+ri_status ri_link_workspace_size(int32_t max_prev, int32_t max_cur, size_t* bytes);
+/*
+ * Crocker-Grier linking of the objects of two successive frames: *n_prev
+ * objects in prev, *n_cur in cur (device counts, e.g. counts[0] of
+ * ri_detect).  Distances are physical: the coordinate differences are scaled
+ * by spacing[3] (z, y, x; host array).  Within each subnetwork of candidate
+ * links (distance <= max_disp) the links minimise sum(d^2) + max_disp^2 *
+ * (unlinked objects of prev), each object linked at most once; among equal
+ * minima the first in a fixed enumeration order wins (sources ascending,
+ * candidates by increasing distance then index, "unlinked" last).
+ * link[i] (device int32[max_prev]) = index in cur or -1.  *status (device
+ * int32): 0, or bit 0 set if a subnetwork had more than 8 sources (its links
+ * are left at -1), bit 1 set if a source had more than 8 candidates (the
+ * nearest 8 were used).
+ */
+ri_status ri_link(const ri_object* prev, const int32_t* n_prev, int32_t max_prev, const ri_object* cur,
+                  const int32_t* n_cur, int32_t max_cur, const double spacing[3], double max_disp,
+                  int32_t* link, int32_t* status, void* ws, size_t ws_bytes, void* stream);
+/*
+ * Track ids of the current frame: an object linked from the previous frame
+ * takes its source's id (ids_prev), the others open new ids *next_id,
+ * *next_id + 1, ... in ascending object order; track_len[id] grows by one for
+ * every id present (ids >= max_tracks are not counted).  For the first frame
+ * pass *n_prev = 0 (link and ids_prev may then be NULL).  track_len and
+ * *next_id start at zero (device memory the caller clears).
+ */
+ri_status ri_track_update(const int32_t* link, const int32_t* n_prev, const int32_t* ids_prev,
+                          const int32_t* n_cur, int32_t max_cur, int32_t* ids_cur, int32_t* next_id,
+                          int32_t* track_len, int32_t max_tracks, void* stream);
+/* kept[t] = 1 for tracks of at least min_len frames (t < *n_tracks); *n_kept their number. */
+ri_status ri_track_filter(const int32_t* track_len, const int32_t* n_tracks, int32_t max_tracks, int32_t min_len,
+                          uint8_t* kept, int32_t* n_kept, void* stream);
 
 const char* ri_status_string(ri_status status);
 const char* ri_last_error(void);

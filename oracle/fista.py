@@ -16,8 +16,13 @@ gradient is taken at the extrapolated point y_k (standard FISTA):
     y_{k+1} = x_k + ((s_k - 1) / s_{k+1}) (x_k - x_{k-1})
 
 from x_0 (zero unless given), y_1 = x_0, s_1 = 1.  Optional function-value
-restart (reset s to 1 and y to x_k whenever F increases) is used only to
-compute a reference objective value.
+restart (reset s to 1 and y to x_k whenever F increases) computes a reference
+objective value and is also a solve mode of its own.
+
+Variants of the prox inside (flags, see `prox`): tv_dims=2, the paper's
+per-plane 2D TV; dual_warm=True, every prox starts its TV dual from the dual
+the previous outer iteration ended with (p = 0 for the first); fgp=True, the
+accelerated dual iteration.
 """
 from __future__ import annotations
 
@@ -30,34 +35,41 @@ from . import optics, prox
 __all__ = ["objective", "fista", "objective_terms"]
 
 
-def objective_terms(geom, x, b, l1, tv):
+def objective_terms(geom, x, b, l1, tv, tv_dims=3):
     """(1/2||Ax-b||^2, sum|x|, TV(x)) in FP64."""
     r = optics.forward(geom, x) - b
-    return 0.5 * float((r * r).sum()), float(np.abs(x).sum()), prox.tv3(x)
+    return 0.5 * float((r * r).sum()), float(np.abs(x).sum()), prox.tv(x, tv_dims)
 
 
-def objective(geom, x, b, l1, tv) -> float:
+def objective(geom, x, b, l1, tv, tv_dims=3) -> float:
     """F(x) = 1/2||A x - b||^2 + l1 ||x||_1 + tv TV(x)."""
-    d, s, t = objective_terms(geom, x, b, l1, tv)
+    d, s, t = objective_terms(geom, x, b, l1, tv, tv_dims)
     return d + l1 * s + tv * t
 
 
 def fista(geom, b, l1, tv, n_outer, n_inner, x0=None, step=None, nonneg=True,
-          restart=False, history=False):
+          restart=False, history=False, tv_dims=3, dual_warm=False, fgp=False, dual_store=None,
+          dual_store_every=1):
     b = np.asarray(b, dtype=np.float64)
     t = 1.0 / optics.lipschitz(geom) if step is None else float(step)
     x = np.zeros((geom.nz, geom.ny, geom.nx)) if x0 is None else np.array(x0, dtype=np.float64)
     y = x.copy()
     s = 1.0
+    p = None
     f_hist = []
-    f_prev = objective(geom, x, b, l1, tv) if restart else None
+    f_prev = objective(geom, x, b, l1, tv, tv_dims) if restart else None
     for _ in range(n_outer):
         g = optics.adjoint(geom, optics.forward(geom, y) - b)
-        x_new = prox.prox_fused_lasso(y - t * g, t, l1, tv, n_inner, nonneg)
+        x_new, p_new = prox.prox_fused_lasso(y - t * g, t, l1, tv, n_inner, nonneg, dims=tv_dims,
+                                             p0=p if dual_warm else None, return_dual=True, fast=fgp,
+                                             store=dual_store, store_every=dual_store_every)
+        if dual_warm:
+            # the dual carried to the next outer iteration is stored (rounded, if a store is given)
+            p = p_new if dual_store is None else tuple(dual_store(a) for a in p_new)
         s_new = 0.5 * (1.0 + math.sqrt(1.0 + 4.0 * s * s))
         beta = (s - 1.0) / s_new
         if restart or history:
-            f = objective(geom, x_new, b, l1, tv)
+            f = objective(geom, x_new, b, l1, tv, tv_dims)
             f_hist.append(f)
             if restart and f > f_prev:
                 s_new, beta = 1.0, 0.0

@@ -70,13 +70,14 @@ struct GraphCache {
   const void* b = nullptr;
   const void* x = nullptr;
   double step = 0, l1 = 0, tv = 0;
-  int inner = -1, dense = -1, nonneg = -1;
+  int inner = -1, dense = -1, nonneg = -1, warm = -1;
 };
 
 struct ri_plan {
   ri_geometry g{};
   int m = 0;                 // nx / 2
   int device = 0;
+  int cus = 0;               // compute units of the device
   double lipschitz = 0.0;
   double* theta = nullptr;   // device [ny][m+1]
   double2* zc = nullptr;     // device [nz]
@@ -133,7 +134,8 @@ static ri_status validate_geometry(const ri_geometry* g) {
   if (!(fmax2 < 1.0 / (g->wavelength_um * g->wavelength_um)))
     return fail(RI_ERR_INVALID_ARG, "pixel %.4g um <= lambda/sqrt(2): evanescent frequencies are not supported",
                 g->pixel_um);
-  if (g->flags & ~RI_NO_CARRIER) return fail(RI_ERR_INVALID_ARG, "unknown geometry flags 0x%x", g->flags);
+  if (g->flags & ~(RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16))
+    return fail(RI_ERR_INVALID_ARG, "unknown geometry flags 0x%x", g->flags);
   return RI_OK;
 }
 
@@ -150,6 +152,8 @@ extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_pla
   const int nx = g->nx, ny = g->ny, nz = g->nz, m = p->m;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_plan(p); return fail(RI_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e)); }
+  e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
+  if (e != hipSuccess) { free_plan(p); return fail(RI_ERR_HIP, "hipDeviceGetAttribute: %s", hipGetErrorString(e)); }
 
   // theta(f) = sqrt(1/lambda^2 - f^2) - 1/lambda = -f^2 / (sqrt(1/lambda^2 - f^2) + 1/lambda)
   const double il = 1.0 / g->wavelength_um;
@@ -236,7 +240,9 @@ extern "C" ri_status ri_plan_lipschitz(const ri_plan* p, double* out) {
 // ---------------------------------------------------------------------------
 struct Layout {
   size_t total = 0;
-  size_t vol1 = 0, vol2 = 0, pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};  // volumes (float)
+  size_t vol1 = 0, vol2 = 0, pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};  // volumes (float; duals float or bf16)
+  size_t pa2[3] = {0, 0, 0}, pb2[3] = {0, 0, 0};                   // FGP: second dual of each set
+  size_t stage = 0;                                                 // in-place prox with bf16 duals
   size_t spec = 0, gp = 0, gi = 0, th = 0;                 // spectra (float2)
   size_t ax0 = 0, ax1 = 0;                                 // holograms (float)
   size_t rowflag = 0, planeflag = 0, rowflag_prev = 0;     // bytes
@@ -296,8 +302,17 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
     L.th = take(hspec);
   }
   if (op == RI_OP_PROX || op == RI_OP_SOLVE) {
-    for (int k = 0; k < 3; ++k) L.pa[k] = take(vol);
-    for (int k = 0; k < 3; ++k) L.pb[k] = take(vol);
+    // dual components: x, y (and z for the 3D TV); the per-plane 2D TV has no z
+    // dual.  FGP keeps two duals per set (r and p); bf16 duals take half the bytes.
+    const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
+    const size_t dvol = (p->g.flags & RI_TV_DUAL_BF16) ? vol / 2 : vol;
+    for (int k = 0; k < nc; ++k) L.pa[k] = take(dvol);
+    for (int k = 0; k < nc; ++k) L.pb[k] = take(dvol);
+    if (p->g.flags & RI_TV_FGP) {
+      for (int k = 0; k < nc; ++k) L.pa2[k] = take(dvol);
+      for (int k = 0; k < nc; ++k) L.pb2[k] = take(dvol);
+    }
+    if (op == RI_OP_PROX && (p->g.flags & RI_TV_DUAL_BF16)) L.stage = take(vol);
   }
   if (op == RI_OP_SOLVE) {
     L.vol1 = take(vol);
@@ -312,7 +327,7 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
     L.pdfit = take((size_t)L.n_dfit * sizeof(double));
     L.psum = take((size_t)L.n_obj * sizeof(double));
     L.ptv = take((size_t)L.n_obj * sizeof(double));
-    L.n_prox = tv_blocks_bound((int)nx, (int)ny, (int)nz);
+    L.n_prox = tv_blocks_bound((int)nx, (int)ny, (int)nz, p->cus);
     L.qsum = take((size_t)L.n_prox * sizeof(double));
     L.qtv = take((size_t)L.n_prox * sizeof(double));
     L.hist = take((size_t)kHistCap * sizeof(double));
@@ -363,6 +378,20 @@ static ri_status check_common(ri_plan* p, const void* in, const void* out, void*
   HIP_TRY(hipGetDevice(&dev));
   if (dev != p->device) return fail(RI_ERR_INVALID_ARG, "plan belongs to device %d, current device is %d", p->device, dev);
   return RI_OK;
+}
+
+// Dual buffers and inner-solver options of a prox from the plan and a layout.
+static void prox_duals(const ri_plan* p, const Layout& L, void* ws, ProxArgs* a) {
+  for (int k = 0; k < 3; ++k) {
+    a->pa[k] = at<float>(ws, L.pa[k]);
+    a->pb[k] = at<float>(ws, L.pb[k]);
+    a->pa2[k] = at<float>(ws, L.pa2[k]);
+    a->pb2[k] = at<float>(ws, L.pb2[k]);
+  }
+  a->tv2 = (p->g.flags & RI_TV2D) ? 1 : 0;
+  a->dual_bf16 = (p->g.flags & RI_TV_DUAL_BF16) ? 1 : 0;
+  a->fgp = (p->g.flags & RI_TV_FGP) ? 1 : 0;
+  a->cus = p->cus;
 }
 
 // ---------------------------------------------------------------------------
@@ -542,8 +571,7 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   ProxArgs a{};
   a.v = v;
   a.x = x_out;
-  for (int k = 0; k < 3; ++k) a.pa[k] = at<float>(ws, L.pa[k]);
-  for (int k = 0; k < 3; ++k) a.pb[k] = at<float>(ws, L.pb[k]);
+  prox_duals(p, L, ws, &a);
   a.nx = p->g.nx;
   a.ny = p->g.ny;
   a.nz = p->g.nz;
@@ -558,13 +586,14 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   // the z-margin of the neighbouring chunk while other blocks store x, and not
   // every block is resident at once, so x may not go into v's buffer.  The
   // final pass writes its result into the dual set it does not use (its
-  // output set: it stores no dual), which is then copied over v.
+  // output set: it stores no dual) -- or, with bfloat16 duals, too small for
+  // x, into a staging volume -- which is then copied over v.
   const double tau = step * pp->tv;
   const int K = (tau > 0.0 && pp->inner_iters > 0) ? pp->inner_iters : 0;
   float* staged = nullptr;
   if (v == x_out && K > 0) {
-    const int npass = prox_passes(K, tau, p->tune.tv_levels);
-    staged = ((npass - 1) & 1) ? a.pa[0] : a.pb[0];
+    const int npass = prox_passes(K, tau, p->tune.tv_levels, a.fgp != 0);
+    staged = a.dual_bf16 ? at<float>(ws, L.stage) : (((npass - 1) & 1) ? a.pa[0] : a.pb[0]);
     a.x = staged;
   }
   HIP_TRY(launch_prox(a, (hipStream_t)stream, nullptr));
@@ -590,6 +619,7 @@ struct SolveCtx {
   int inner;
   bool dense;
   int nonneg;
+  bool warm;     // the TV dual carries over from one outer iteration to the next
 };
 
 struct PhaseTimer {
@@ -658,6 +688,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   oa.psum = at<double>(c.ws, L.psum);
   oa.ptv = at<double>(c.ws, L.ptv);
   oa.first_only = 1;
+  oa.tv2 = (p->g.flags & RI_TV2D) ? 1 : 0;
   oa.st = c.st;
   // A x_it (skipping empty rows and planes unless dense)
   RowsR2CArgs& ra = I.fwd_rows;
@@ -704,7 +735,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   sa.n_obj = L.n_obj;
   sa.qsum = at<double>(c.ws, L.qsum);
   sa.qtv = at<double>(c.ws, L.qtv);
-  sa.n_prox = tv_pass_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks);
+  sa.n_prox = tv_final_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks, p->cus);
   sa.hist = at<double>(c.ws, L.hist);
   RowsR2CArgs& rr = I.resid;
   rr.ax0 = at<float>(c.ws, L.ax0);
@@ -740,8 +771,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   // fused-lasso prox -> x_{it+1}, occupancy flags
   ProxArgs& pa = I.prox;
   for (int k = 0; k < 3; ++k) pa.vol[k] = c.vol[k];
-  for (int k = 0; k < 3; ++k) pa.pa[k] = at<float>(c.ws, L.pa[k]);
-  for (int k = 0; k < 3; ++k) pa.pb[k] = at<float>(c.ws, L.pb[k]);
+  prox_duals(p, L, c.ws, &pa);
   pa.rowflag = rowflag;
   pa.planeflag = planeflag;
   pa.psum = at<double>(c.ws, L.qsum);
@@ -754,6 +784,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   pa.tv = c.tv;
   pa.st = c.st;
   pa.levels = p->tune.tv_levels;
+  pa.warm = c.warm ? 1 : 0;
   pa.blocks = p->tune.tv_blocks;
   return I;
 }
@@ -809,8 +840,10 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
   if (!(sp->x0_scale >= 0) || !std::isfinite(sp->x0_scale))
     return fail(RI_ERR_INVALID_ARG, "x0_scale must be finite and >= 0");
   if (sp->f_ref > 0 && !(sp->gap_tol >= 0)) return fail(RI_ERR_INVALID_ARG, "gap_tol must be >= 0");
-  if (sp->flags & ~(RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH | RI_SOLVE_RESTART | RI_SOLVE_TIMING))
+  if (sp->flags & ~(RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH | RI_SOLVE_RESTART | RI_SOLVE_TIMING | RI_SOLVE_DUAL_WARM))
     return fail(RI_ERR_INVALID_ARG, "unknown solve flags 0x%x", sp->flags);
+  if ((sp->flags & RI_SOLVE_DUAL_WARM) && (p->g.flags & RI_TV_FGP))
+    return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_TV_FGP plans");
   return RI_OK;
 }
 
@@ -843,6 +876,13 @@ static hipError_t enqueue_setup(const SolveCtx& c, const ri_solve_params* sp, hi
     if ((e = launch_flags_from_x(c.vol[0], p->g.nx, p->g.ny, p->g.nz, rowflag, planeflag, s)) != hipSuccess) return e;
   }
   if ((e = launch_copy_f32(c.vol[2], c.vol[0], nvox, s)) != hipSuccess) return e;
+  if (c.warm) {
+    // the first prox starts its dual from zero; it reads the first dual set
+    const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
+    const size_t nfill = (p->g.flags & RI_TV_DUAL_BF16) ? nvox / 2 : nvox;   // bf16 zeros are zero words
+    for (int k = 0; k < nc; ++k)
+      if ((e = launch_fill_f32(at<float>(c.ws, c.L.pa[k]), nfill, 0.f, s)) != hipSuccess) return e;
+  }
   if ((e = launch_fill_f32(at<float>(c.ws, c.L.ax0), npix, 0.f, s)) != hipSuccess) return e;
   return launch_fill_f32(at<float>(c.ws, c.L.ax1), npix, 0.f, s);
 }
@@ -856,7 +896,8 @@ static ri_status read_state(const SolveCtx& c, hipStream_t s, SolveState* out) {
 static ri_status get_graph(ri_plan* p, const SolveCtx& c, hipGraphExec_t* exec) {
   GraphCache& g = p->gc;
   if (g.exec && g.ws == c.ws && g.b == c.b && g.x == c.vol[0] && g.step == c.step && g.l1 == c.l1 &&
-      g.tv == c.tv && g.inner == c.inner && g.dense == (int)c.dense && g.nonneg == c.nonneg) {
+      g.tv == c.tv && g.inner == c.inner && g.dense == (int)c.dense && g.nonneg == c.nonneg &&
+      g.warm == (int)c.warm) {
     *exec = g.exec;
     return RI_OK;
   }
@@ -874,7 +915,7 @@ static ri_status get_graph(ri_plan* p, const SolveCtx& c, hipGraphExec_t* exec) 
   g.graph = graph;
   g.exec = ex;
   g.ws = c.ws; g.b = c.b; g.x = c.vol[0]; g.step = c.step; g.l1 = c.l1; g.tv = c.tv;
-  g.inner = c.inner; g.dense = (int)c.dense; g.nonneg = c.nonneg;
+  g.inner = c.inner; g.dense = (int)c.dense; g.nonneg = c.nonneg; g.warm = (int)c.warm;
   *exec = ex;
   return RI_OK;
 }
@@ -930,6 +971,7 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const void*
   c.inner = sp->inner_iters;
   c.dense = (sp->flags & RI_SOLVE_DENSE) != 0;
   c.nonneg = sp->nonneg ? 1 : 0;
+  c.warm = (sp->flags & RI_SOLVE_DUAL_WARM) != 0;
   const bool timing = (sp->flags & RI_SOLVE_TIMING) != 0 && report != nullptr;
   const bool use_graph = !timing && !(sp->flags & RI_SOLVE_NO_GRAPH);
   PhaseTimer tm;
@@ -982,6 +1024,10 @@ struct BatchLaunch {
   int kind;
   int size;       // template size (m or ny), 0 when the kernel is not specialised
   int pass;       // TV pass index
+  bool final_pass = false;  // TV: the frames' final pass
+  bool tv2 = false;         // TV: per-plane 2D TV frames
+  bool fgp = false;         // TV: accelerated-dual frames
+  bool bf16 = false;        // TV: bfloat16-dual frames
   std::vector<int> frames;
   size_t args_off = 0, offs_off = 0;
   int nblocks = 0;
@@ -1003,7 +1049,7 @@ static size_t kind_args_size(int kind) {
 }
 
 static int prox_pass_count(const ri_plan* p, const ri_solve_params& sp) {
-  return prox_passes(sp.inner_iters, (1.0 / p->lipschitz) * sp.tv, p->tune.tv_levels);
+  return prox_passes(sp.inner_iters, (1.0 / p->lipschitz) * sp.tv, p->tune.tv_levels, (p->g.flags & RI_TV_FGP) != 0);
 }
 
 // The launches of one batched iteration (frames grouped by transform size).
@@ -1036,18 +1082,36 @@ static std::vector<BatchLaunch> batch_launches(int n, ri_plan* const* plans, con
   group(BK_RESID, true, false);
   group(BK_ADJ_COLS, false, true);
   group(BK_ADJ_ROWS, true, false);
-  // TV pass p of every frame that has one, one launch per fusion depth
+  // TV pass p of every frame that has one, one launch per fusion depth and
+  // per kind of pass (a dual pass, or a frame's final pass)
   int maxpass = 0;
   for (int i = 0; i < n; ++i) maxpass = std::max(maxpass, prox_pass_count(plans[i], params[i]));
   for (int p = 0; p < maxpass; ++p) {
-    for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
-      BatchLaunch b;
-      b.kind = BK_TV;
-      b.size = H;
-      b.pass = p;
-      for (int i = 0; i < n; ++i)
-        if (plans[i]->tune.tv_levels == H && p < prox_pass_count(plans[i], params[i])) b.frames.push_back(i);
-      if (!b.frames.empty()) out.push_back(b);
+    for (int fin = 0; fin < 2; ++fin) {
+      for (int t2 = 0; t2 < 2; ++t2) {
+        for (int fg = 0; fg < 4; ++fg) {   // bit 0: FGP, bit 1: bfloat16 dual
+          for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
+            BatchLaunch b;
+            b.kind = BK_TV;
+            b.size = H;
+            b.pass = p;
+            b.final_pass = fin != 0;
+            b.tv2 = t2 != 0;
+            b.fgp = (fg & 1) != 0;
+            b.bf16 = (fg & 2) != 0;
+            for (int i = 0; i < n; ++i) {
+              const int np = prox_pass_count(plans[i], params[i]);
+              const bool f2 = (plans[i]->g.flags & RI_TV2D) != 0;
+              const bool ff = (plans[i]->g.flags & RI_TV_FGP) != 0;
+              const bool fb = (plans[i]->g.flags & RI_TV_DUAL_BF16) != 0;
+              if (prox_levels(plans[i]->tune.tv_levels, ff) == H && p < np && (p == np - 1) == (fin != 0) &&
+                  f2 == (t2 != 0) && ff == b.fgp && fb == b.bf16)
+                b.frames.push_back(i);
+            }
+            if (!b.frames.empty()) out.push_back(b);
+          }
+        }
+      }
     }
   }
   return out;
@@ -1117,6 +1181,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     c.inner = params[i].inner_iters;
     c.dense = (params[i].flags & RI_SOLVE_DENSE) != 0;
     c.nonneg = params[i].nonneg ? 1 : 0;
+    c.warm = (params[i].flags & RI_SOLVE_DUAL_WARM) != 0;
     off += fb;
   }
   for (int i = 0; i < n; ++i)
@@ -1129,7 +1194,8 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
   // per-frame argument structs (grids filled in as the single-frame launchers do)
   std::vector<IterArgs> it(n);
   std::vector<std::vector<char>> tv(n);
-  std::vector<int> tv_blocks(n), npass(n);
+  std::vector<std::vector<int>> tv_blocks(n);
+  std::vector<int> npass(n);
   for (int i = 0; i < n; ++i) {
     it[i] = iteration_args(ctx[i]);
     const ri_plan* p = plans[i];
@@ -1146,9 +1212,10 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     g = grid_rows(m, ny * nz);                 it[i].adj_rows.gx = g.x; it[i].adj_rows.gy = g.y;
     npass[i] = prox_pass_count(p, params[i]);
     tv[i].resize(tv_pass_args_size() * npass[i]);
-    prox_pass_args(it[i].prox, tv[i].data(), &tv_blocks[i]);
+    tv_blocks[i].resize(npass[i]);
+    prox_pass_args(it[i].prox, tv[i].data(), tv_blocks[i].data());
   }
-  auto frame_blocks = [&](int kind, int i) -> int {
+  auto frame_blocks = [&](int kind, int pass, int i) -> int {
     const IterArgs& a = it[i];
     switch (kind) {
       case BK_OBJ: return a.obj.gx * a.obj.gy;
@@ -1160,7 +1227,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
       case BK_RESID: return a.resid.gx * a.resid.gy;
       case BK_ADJ_COLS: return a.adj_cols.gx * a.adj_cols.gy;
       case BK_ADJ_ROWS: return a.adj_rows.gx * a.adj_rows.gy;
-      case BK_TV: return tv_blocks[i];
+      case BK_TV: return tv_blocks[i][pass];
     }
     return 0;
   };
@@ -1196,7 +1263,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     uint32_t acc = 0;
     for (size_t k = 0; k < bl.frames.size(); ++k) {
       o[k] = acc;
-      acc += (uint32_t)frame_blocks(bl.kind, bl.frames[k]);
+      acc += (uint32_t)frame_blocks(bl.kind, bl.pass, bl.frames[k]);
     }
     o[bl.frames.size()] = acc;
     bl.nblocks = (int)acc;
@@ -1226,7 +1293,9 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
         case BK_SCAL: e = launch_scalars_batched((const ScalarArgs*)a, mp, bl.nblocks, q); break;
         case BK_ADJ_COLS: e = launch_adj_cols_batched(bl.size, (const AdjColsArgs*)a, mp, bl.nblocks, q); break;
         case BK_ADJ_ROWS: e = launch_adj_rows_batched(bl.size, (const AdjRowsArgs*)a, mp, bl.nblocks, q); break;
-        case BK_TV: e = launch_tv_pass_batched(bl.size, a, mp, bl.nblocks, q); break;
+        case BK_TV:
+          e = launch_tv_pass_batched(bl.size, bl.final_pass, bl.tv2, bl.fgp, bl.bf16, a, mp, bl.nblocks, q);
+          break;
       }
       if (e != hipSuccess) return e;
     }
@@ -1510,8 +1579,7 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
       ProxArgs a{};
       a.v = xv;
       a.x = xo;
-      for (int k = 0; k < 3; ++k) a.pa[k] = at<float>(ws, LT.pa[k]);
-      for (int k = 0; k < 3; ++k) a.pb[k] = at<float>(ws, LT.pb[k]);
+      prox_duals(p, LT, ws, &a);
       a.rowflag = at<uint8_t>(ws, LT.rowflag);
       a.planeflag = at<uint8_t>(ws, LT.planeflag);
       a.nx = nx; a.ny = ny; a.nz = nz;

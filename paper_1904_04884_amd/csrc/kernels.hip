@@ -643,7 +643,7 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
     for (int k = 0; k < 4; ++k) {
       const float gx = (i + k + 1 < nx) ? a4[k + 1] - a4[k] : 0.f;
       const float gy = hy ? b4[k] - a4[k] : 0.f;
-      const float gz = hz ? c4[k] - a4[k] : 0.f;
+      const float gz = (hz && !a.tv2) ? c4[k] - a4[k] : 0.f;
       ss += fabsf(a4[k]);   // ||x||_1 (x >= 0 in the constrained problem, signed otherwise)
       // per-voxel norm in FP32 (relative error ~1e-7), running sums in FP64
       tt += sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
@@ -661,7 +661,7 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
     const int z = row < nrows ? (int)(row / ny) : 0, y = row < nrows ? (int)(row % ny) : 0;
     hy[rr] = y + 1 < ny;
     hz[rr] = z + 1 < nz;
-    bool f0 = on[rr], fy = on[rr] && hy[rr], fz = on[rr] && hz[rr];
+    bool f0 = on[rr], fy = on[rr] && hy[rr], fz = on[rr] && hz[rr] && !a.tv2;
     if (a.rowflag != nullptr && on[rr]) {
       f0 = a.rowflag[row] != 0;
       fy = fy && a.rowflag[row + 1] != 0;

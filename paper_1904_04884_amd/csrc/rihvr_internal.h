@@ -195,6 +195,7 @@ struct ObjArgs {
   double* psum; double* ptv;  // [nblocks]
   const SolveState* st;
   int first_only;             // solver: only x_0 (later iterates are summed by the prox)
+  int tv2;                    // per-plane 2D TV: no z differences
   int gx, gy;
 };
 dim3 grid_obj(int nx, int ny, int nz);
@@ -249,6 +250,8 @@ struct ProxArgs {
   float* vol[3];       // solver: the rotating volume buffers (v and x chosen on device)
   float* pa[3];        // dual components px, py, pz (ping)
   float* pb[3];        // dual components (pong)
+  float* pa2[3];       // FGP: the second dual of each set (p beside r)
+  float* pb2[3];
   uint8_t* rowflag; uint8_t* planeflag;  // nullable: set where x != 0
   double* psum; double* ptv;             // nullable: per-block sum(x), TV(x) of the result
   int nx, ny, nz;
@@ -258,24 +261,35 @@ struct ProxArgs {
   const SolveState* st;  // solver: weights from st, step from `step`
   int levels;            // dual steps fused per pass (kTvLevelsMin..kTvLevelsMax; else the default)
   int blocks;            // target blocks per pass (<= 0: the default)
+  int tv2;               // per-plane 2D TV (pa[2], pb[2] unused)
+  int cus;               // compute units of the device (shapes the final pass's grid; <= 0: uniform)
+  int dual_bf16;         // dual buffers hold bfloat16
+  int fgp;               // accelerated dual iteration (one step per pass; pa2 / pb2 hold p)
+  int warm;              // solver: the dual starts from the previous prox's (kept in pa / pb,
+                         // the sets alternating by outer iteration when the pass count is odd)
 };
 constexpr int kTvLevelsMin = 2, kTvLevelsMax = 4, kTvDefaultLevels = 3;
 constexpr int kTvDefaultBlocks = 1536;
 hipError_t launch_prox(const ProxArgs& a, hipStream_t s, int* launches);
-int prox_passes(int inner_iters, double tau, int levels);
+int prox_passes(int inner_iters, double tau, int levels, bool fgp);
+int prox_levels(int levels, bool fgp);
 // Planes per block of a pass for the given tuning (distinct values = distinct grids).
 int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks);
-// Blocks of one pass for the given tuning, and a bound over every tuning.
+// Blocks of a dual pass and of the final pass (its tiles have a halo one
+// wider) for the given tuning, and a bound over every tuning and pass.
 int tv_pass_blocks(int nx, int ny, int nz, int levels, int blocks);
-int tv_blocks_bound(int nx, int ny, int nz);
+int tv_final_blocks(int nx, int ny, int nz, int levels, int blocks, int cus);
+int tv_blocks_bound(int nx, int ny, int nz, int cus);
 
 // Batched prox: the argument structs of every pass of every frame are built on
 // the host (prox_pass_args) and uploaded; launch p runs pass p of all frames.
 struct TvPassArgs;
 size_t tv_pass_args_size();
 // Fills `out` (npass structs, host memory of npass * tv_pass_args_size() bytes)
-// for one frame and returns the number of passes and the frame's blocks per pass.
+// for one frame and returns the number of passes; blocks_per_pass (nullable,
+// npass entries) receives the frame's blocks of each pass.
 int prox_pass_args(const ProxArgs& a, void* out, int* blocks_per_pass);
-hipError_t launch_tv_pass_batched(int levels, const void* args, BatchMap map, int nblocks, hipStream_t s);
+hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, const void* args,
+                                  BatchMap map, int nblocks, hipStream_t s);
 
 }  // namespace rihvr

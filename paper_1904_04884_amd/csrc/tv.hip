@@ -22,6 +22,20 @@
 // computed but not stored, and tiles overlap by 2H.  The z-range is cut into
 // chunks with an L+1 plane margin so that the grid fills the device.
 //
+// Per-plane 2D TV (TV2): the TV of the paper's Eq. (4) taken in every plane on
+// its own.  The dual has no z component (neither read nor stored), the step is
+// 1/(8 tau) and planes do not couple, so chunks need no z margin.
+//
+// Dual storage in bfloat16 (dual_bf16): the dual between passes is rounded to
+// bfloat16 (to nearest, ties to even) when stored and widened when read; the
+// arithmetic stays FP32.  The dual lies in the unit ball, so its bytes halve
+// at 2^-9 relative precision.
+//
+// FGP (accelerated dual iteration): every dual pass takes one step at the
+// extrapolated point r, reads (r, p_prev) and stores (p, r_next), r_next =
+// p + w (p - p_prev) with w = (t_k - 1)/t_{k+1} of the FISTA sequence (set per
+// pass by the host); the final pass steps at r like a plain pass.
+//
 // Boundaries: the z-component of the dual is exactly zero on the last plane
 // (its z-difference is zero there, from p = 0 on) and the state below the first
 // plane starts at zero, so the divergence carries no z masks; x / y masks are
@@ -30,6 +44,10 @@
 // One pass fuses up to H steps; a prox is a sequence of passes ping-ponging the
 // dual between two buffers.  The last pass adds a half step (primal recovery),
 // the soft threshold, the occupancy flags of the result and the store of x.
+// It runs its own kernel whose tile has an (H+1)-voxel halo: x at a voxel needs
+// the dual one voxel below it on every axis, and the objective's differences
+// need x one voxel above, so with one more voxel of halo the last pass fuses
+// a full H dual steps as well (K steps take ceil(K/H) passes).
 #include <algorithm>
 #include <vector>
 
@@ -52,9 +70,21 @@ struct TvPassArgs {
   double* psum; double* ptv;      // final pass: per-block sum(x) and TV(x) of the stored x (nullable)
   const SolveState* st;
   int nx, ny, nz;
-  int levels;                     // fused dual steps in this pass (<= H, <= H-1 when final)
+  int levels;                     // fused dual steps in this pass (<= H)
   int first, final_, nonneg;
-  int zchunk;                     // output planes per block
+  int tv2;                        // per-plane 2D TV (no z component, no z margin)
+  int keep_dual;                  // final pass: also store the dual to pout (warm start of the next prox)
+  int flip_npass;                 // > 0: the solve's passes ping-pong the dual across outer iterations;
+                                  // pin and pout trade places when (st->it - 1) * flip_npass is odd
+  int dual_bf16;                  // the dual buffers hold bfloat16
+  const float* pin2[3];           // FGP: p_prev read with r (= pin)
+  float* pout2[3];                // FGP: p written beside r_next (= pout)
+  float fgp_w;                    // FGP: extrapolation weight of this pass
+  int fgp;                        // FGP dual pass (one step; never the final pass)
+  int zchunk;                     // output planes per block (the first nfull tiles)
+  int nfull;                      // tiles (in raster order) cut into chunks of zchunk planes; the
+  int zchunk2;                    // remaining gx*gy - nfull tiles are cut into chunks of zchunk2
+  int nblocks;                    // blocks of the pass (the objective partials are per block)
   float tau, c, thr;
   int gx, gy;                     // tiles along x and y (the grid of one frame)
 };
@@ -91,12 +121,35 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, f
   __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
 }
 
+// Dual planes, FP32 or bfloat16 (`bf`, uniform).  Offsets are those of the
+// FP32 layout; a bfloat16 element sits at half of it (kTvOff / 2 is still past
+// every plane).
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t dual_rsrc(const float* base, size_t plane, size_t sz, bool bf) {
+  if (!bf) return plane_rsrc(base, plane, sz);
+  const uint16_t* b = reinterpret_cast<const uint16_t*>(base) + plane * sz;
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(b), (short)0, (int)(sz * 2), kTvRsrcWord3);
+}
+__device__ __forceinline__ float dual_ld(__amdgpu_buffer_rsrc_t r, unsigned off, bool bf) {
+  if (!bf) return buf_ld(r, off);
+  const unsigned short h = __builtin_amdgcn_raw_buffer_load_b16(r, (int)(off >> 1), 0, 0);
+  return __uint_as_float((unsigned)h << 16);
+}
+__device__ __forceinline__ void dual_st(__amdgpu_buffer_rsrc_t r, unsigned off, float v, bool bf) {
+  if (!bf) {
+    buf_st(r, off, v);
+    return;
+  }
+  const unsigned u = __float_as_uint(v);
+  const unsigned h = (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;   // round to nearest, ties to even (|v| <= 1)
+  __builtin_amdgcn_raw_buffer_store_b16((unsigned short)h, r, (int)(off >> 1), 0, 0);
+}
+
 // Pass body.  H: the halo (tile geometry); LV: register slots for fused steps
-// (H, or H - 1 on the final pass, which fuses at most H - 1).  EDGE: the tile
+// (the halo on dual passes; on the final pass, whose halo is one wider, H - 1).  EDGE: the tile
 // touches the volume boundary, so every access and every difference is masked;
-// interior tiles (most of them) skip the masks.  FIRST: the incoming dual is
+// interior tiles (most of them) skip the masks.  TV2: per-plane 2D TV.  FIRST: the incoming dual is
 // zero (nothing is read).  FINAL: the last pass (primal recovery and output)
-// instead of storing the dual.
+// instead of storing the dual.  FGP: a one-step accelerated dual pass (above).
 //
 // With psum / ptv set, the final pass also sums x and its isotropic TV (forward
 // differences, zero at the last index of each axis) over the points it stores.
@@ -105,18 +158,30 @@ __device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, f
 // the x+1 neighbour comes by a wave shift, the y+1 neighbour from the next row
 // of the lane or, for the last row, from the next wave through LDS.  Every
 // neighbour lies in the computed tile: the final pass fuses at most H - 1
-// steps, so x is exact one point beyond the stored region.
+// steps for its halo of H, so x is exact one point beyond the stored region.
 
-template <int H, int LV, bool EDGE, bool FIRST, bool FINAL>
-__device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int bz,
+template <int H, int LV, bool EDGE, bool FIRST, bool FINAL, bool TV2, bool FGP, bool BF>
+__device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int zb, int ze, int blk,
                                              float (*s_py)[2][kTvWaves][64], float (*s_ut)[2][kTvWaves][64],
-                                             float* s_v, float (*s_x)[kTvWaves][64], double (*s_red)[kTvWaves]) {
+                                             float* s_v, float (*s_x)[kTvWaves][64], double (*s_red)[kTvWaves],
+                                             float* s_fin, double* s_sum) {
   constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
   const float* __restrict__ v = uniform_ptr(A.v ? A.v : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->prev));
   float* __restrict__ xo = uniform_ptr(A.x ? A.x : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->next));
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // dual buffers of this pass: with a warm-started dual the sets alternate
+  // from one outer iteration to the next when a prox has an odd number of passes
+  const bool flip = A.flip_npass > 0 && A.st != nullptr && (((A.st->it - 1) * A.flip_npass) & 1);
+  const float* pin[3];
+  float* pout[3];
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    pin[k] = uniform_ptr(flip ? const_cast<const float*>(A.pout[k]) : A.pin[k]);
+    pout[k] = uniform_ptr(flip ? const_cast<float*>(A.pin[k]) : A.pout[k]);
+  }
+  constexpr bool bf = BF;   // dual buffers in bfloat16
   const int x = bx * IX - H + lane;
   const int ybase = by * IY - H + wv * Q;
   const bool inx = !EDGE || (x >= 0 && x < nx);
@@ -124,8 +189,8 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   const bool ix_store = inx && lane >= H && lane < kTvRX - H;
   const size_t sz = (size_t)nx * ny;
   const int L = A.levels;
-  const int zb = bz * A.zchunk, ze = min(nz, zb + A.zchunk);
-  const int M = L + 1;
+
+  const int M = TV2 ? 0 : L + 1;
   const int zs = max(0, zb - M), zl = min(nz, ze + M);
   const float tau = A.tau, cc = A.c;
 
@@ -143,8 +208,8 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     off[q] = (inx && iny) ? (unsigned)(y * nx + x) * 4u : kTvOff;
     offs[q] = ys[q] ? off[q] : kTvOff;
   }
-  // per fused step: previous plane's dual (3) and primal (1); final stage: previous p_z
-  float Pp[LV][Q][3], Up[LV][Q], PzF[Q];
+  // per fused step: previous plane's dual (3) and primal (1)
+  float Pp[LV][Q][3], Up[LV][Q];
 #pragma unroll
   for (int l = 0; l < LV; ++l)
 #pragma unroll
@@ -152,34 +217,42 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       Pp[l][q][0] = Pp[l][q][1] = Pp[l][q][2] = 0.f;
       Up[l][q] = 0.f;
     }
-#pragma unroll
-  for (int q = 0; q < Q; ++q) PzF[q] = 0.f;
-  // objective pieces (final pass): x of the previous output plane, FP64 sums
+  // Final-pass state kept in thread-private LDS rather than registers (the
+  // final pass holds H fused steps in a tile of halo H + 1 and would spill):
+  // the previous output plane's p_z (PzF) and x (Xp), and the FP64 sums of
+  // ||x||_1 and TV(x) (objective pieces).
+  auto PzF = [&](int q) -> float& { return s_fin[q * NT + threadIdx.x]; };
+  auto Xp = [&](int q) -> float& { return s_fin[(Q + q) * NT + threadIdx.x]; };
   const bool obj = FINAL && A.psum != nullptr;
-  float Xp[Q];
+  if constexpr (FINAL) {
 #pragma unroll
-  for (int q = 0; q < Q; ++q) Xp[q] = 0.f;
-  double s_acc = 0.0, t_acc = 0.0;
+    for (int q = 0; q < Q; ++q) {
+      PzF(q) = 0.f;
+      Xp(q) = 0.f;
+    }
+    s_sum[threadIdx.x] = 0.0;
+    s_sum[NT + threadIdx.x] = 0.0;
+  }
   // terms of the plane held in Xp; xn: the next plane (hz: it exists), slot:
   // the LDS slot holding the first row of every wave of the Xp plane
-  auto accumulate = [&](const float (&xn)[Q], bool hz, int slot) {
+  auto accumulate = [&](const float* xn, bool hz, int slot) {
     float ss = 0.f, tt = 0.f;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-      const float x0 = Xp[q];
+      const float x0 = Xp(q);
       const float xr = dpp_from_right(x0);
-      const float xu = (q < Q - 1) ? Xp[q + 1] : s_x[slot][wv < NW - 1 ? wv + 1 : wv][lane];
+      const float xu = (q < Q - 1) ? Xp(q + 1) : s_x[slot][wv < NW - 1 ? wv + 1 : wv][lane];
       const float gx = xhi ? xr - x0 : 0.f;
       const float gy = yhi[q] ? xu - x0 : 0.f;
-      const float gz = hz ? xn[q] - x0 : 0.f;
+      const float gz = (hz && !TV2) ? xn[q] - x0 : 0.f;
       // per-voxel norm in FP32 (the hardware square root, within 1 ulp, not
       // the correctly rounded sequence), running sums in FP64
       const float t = __builtin_amdgcn_sqrtf(fmaf(gx, gx, fmaf(gy, gy, gz * gz)));
       ss += ys[q] ? fabsf(x0) : 0.f;   // ||x||_1
       tt += ys[q] ? t : 0.f;
     }
-    s_acc += (double)ss;
-    t_acc += (double)tt;
+    s_sum[threadIdx.x] += (double)ss;
+    s_sum[NT + threadIdx.x] += (double)tt;
   };
 
   // Input planes are prefetched two ahead into two register sets used in
@@ -190,24 +263,46 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   struct InPlane {
     float v[Q];
     float p[Q][3];
+    float pp[Q][3];   // FGP: p_prev of the plane
   };
   auto load_plane = [&](InPlane& P, int a) {
     const __amdgpu_buffer_rsrc_t rv = plane_rsrc(v, a, sz);
 #pragma unroll
     for (int q = 0; q < Q; ++q) P.v[q] = buf_ld(rv, off[q]);
     if constexpr (!FIRST) {
-      const __amdgpu_buffer_rsrc_t r0 = plane_rsrc(A.pin[0], a, sz);
-      const __amdgpu_buffer_rsrc_t r1 = plane_rsrc(A.pin[1], a, sz);
-      const __amdgpu_buffer_rsrc_t r2 = plane_rsrc(A.pin[2], a, sz);
+      const __amdgpu_buffer_rsrc_t r0 = dual_rsrc(pin[0], a, sz, bf);
+      const __amdgpu_buffer_rsrc_t r1 = dual_rsrc(pin[1], a, sz, bf);
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
-        P.p[q][0] = buf_ld(r0, off[q]);
-        P.p[q][1] = buf_ld(r1, off[q]);
-        P.p[q][2] = buf_ld(r2, off[q]);
+        P.p[q][0] = dual_ld(r0, off[q], bf);
+        P.p[q][1] = dual_ld(r1, off[q], bf);
+      }
+      if constexpr (!TV2) {
+        const __amdgpu_buffer_rsrc_t r2 = dual_rsrc(pin[2], a, sz, bf);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) P.p[q][2] = dual_ld(r2, off[q], bf);
+      } else {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) P.p[q][2] = 0.f;
+      }
+      if constexpr (FGP) {
+        const __amdgpu_buffer_rsrc_t s0 = dual_rsrc(A.pin2[0], a, sz, bf);
+        const __amdgpu_buffer_rsrc_t s1 = dual_rsrc(A.pin2[1], a, sz, bf);
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+          P.pp[q][0] = dual_ld(s0, off[q], bf);
+          P.pp[q][1] = dual_ld(s1, off[q], bf);
+          P.pp[q][2] = 0.f;
+        }
+        if constexpr (!TV2) {
+          const __amdgpu_buffer_rsrc_t s2 = dual_rsrc(A.pin2[2], a, sz, bf);
+#pragma unroll
+          for (int q = 0; q < Q; ++q) P.pp[q][2] = dual_ld(s2, off[q], bf);
+        }
       }
     }
   };
-  auto vring = [&](int a, int q) -> float& { return s_v[((a % (H + 1)) * Q + q) * NT + threadIdx.x]; };
+  auto vring = [&](int a, int q) -> float& { return s_v[((a % (LV + 1)) * Q + q) * NT + threadIdx.x]; };
 
   // Arrival of the previous dual c3 at plane a for fused step l: u(a), then
   // the dual step at plane a - 1 (which needs u(a) for its z-difference).
@@ -223,7 +318,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       const float pym = (q > 0) ? c3[q - 1][1] : s_py[l][par][wv > 0 ? wv - 1 : 0][lane];
       float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
       d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
-      d += c3[q][2] - Pp[l][q][2];
+      if constexpr (!TV2) d += c3[q][2] - Pp[l][q][2];
       un[q] = fmaf(tau, d, un[q]);
     }
     if (a > zs) {
@@ -237,7 +332,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         const float gz = un[q] - u0;       // plane a exists
         const float qx = fmaf(cc, gx, Pp[l][q][0]);
         const float qy = fmaf(cc, gy, Pp[l][q][1]);
-        const float qz = fmaf(cc, gz, Pp[l][q][2]);
+        const float qz = TV2 ? 0.f : fmaf(cc, gz, Pp[l][q][2]);
         const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
         const float sc = fminf(1.f, __frsqrt_rn(n2));   // 1 / max(1, |q|)
         Pp[l][q][0] = c3[q][0];
@@ -273,7 +368,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       const float gy = yhi[q] ? uyp - u0 : 0.f;
       const float qx = fmaf(cc, gx, Pp[l][q][0]);
       const float qy = fmaf(cc, gy, Pp[l][q][1]);
-      const float qz = Pp[l][q][2];
+      const float qz = TV2 ? 0.f : Pp[l][q][2];
       const float n2 = fmaf(qx, qx, fmaf(qy, qy, qz * qz));
       const float sc = fminf(1.f, __frsqrt_rn(n2));
       c3[q][0] = qx * sc;
@@ -283,25 +378,49 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   };
   // Output stage: the dual of the last fused step at plane m (stored), or on
   // the final pass the primal recovery, soft threshold, store and flags.
+  auto store3 = [&](float* const* dst, int m, const float (&c3)[Q][3]) {
+    const __amdgpu_buffer_rsrc_t o0 = dual_rsrc(dst[0], m, sz, bf);
+    const __amdgpu_buffer_rsrc_t o1 = dual_rsrc(dst[1], m, sz, bf);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      dual_st(o0, offs[q], c3[q][0], bf);
+      dual_st(o1, offs[q], c3[q][1], bf);
+    }
+    if constexpr (!TV2) {
+      const __amdgpu_buffer_rsrc_t o2 = dual_rsrc(dst[2], m, sz, bf);
+#pragma unroll
+      for (int q = 0; q < Q; ++q) dual_st(o2, offs[q], c3[q][2], bf);
+    }
+  };
+  // FGP: p_prev of the plane that arrived last (the next plane to be output)
+  float PPv[Q][3];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) PPv[q][0] = PPv[q][1] = PPv[q][2] = 0.f;
+  auto store_dual = [&](int m, const float (&c3)[Q][3]) {
+    if constexpr (FGP) {
+      // c3 is p at plane m; the next pass steps at r_next = p + w (p - p_prev)
+      const float w = A.fgp_w;
+      float rn[Q][3];
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) rn[q][k] = fmaf(w, c3[q][k] - PPv[q][k], c3[q][k]);
+      store3(pout, m, rn);
+      store3(A.pout2, m, c3);
+    } else {
+      store3(pout, m, c3);
+    }
+  };
   auto output = [&](int m, int par, float (&c3)[Q][3]) {
     const bool zstore = m >= zb && m < ze;
     if constexpr (!FINAL) {
-      if (zstore) {
-        const __amdgpu_buffer_rsrc_t o0 = plane_rsrc(A.pout[0], m, sz);
-        const __amdgpu_buffer_rsrc_t o1 = plane_rsrc(A.pout[1], m, sz);
-        const __amdgpu_buffer_rsrc_t o2 = plane_rsrc(A.pout[2], m, sz);
-#pragma unroll
-        for (int q = 0; q < Q; ++q) {
-          buf_st(o0, offs[q], c3[q][0]);
-          buf_st(o1, offs[q], c3[q][1]);
-          buf_st(o2, offs[q], c3[q][2]);
-        }
-      }
+      if (zstore) store_dual(m, c3);
     } else {
+      if (A.keep_dual && zstore) store_dual(m, c3);
       float vm[Q];
 #pragma unroll
       for (int q = 0; q < Q; ++q) vm[q] = vring(m, q);  // thread-private: read before the barrier
-      s_py[H][par][wv][lane] = c3[Q - 1][1];
+      s_py[LV][par][wv][lane] = c3[Q - 1][1];
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rx = plane_rsrc(xo, m, sz);
       float xs[Q];
@@ -310,13 +429,13 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         float u = vm[q];
         if (tau != 0.f) {
           const float pxm = dpp_from_left(c3[q][0]);
-          const float pym = (q > 0) ? c3[q - 1][1] : s_py[H][par][wv > 0 ? wv - 1 : 0][lane];
+          const float pym = (q > 0) ? c3[q - 1][1] : s_py[LV][par][wv > 0 ? wv - 1 : 0][lane];
           float d = (xhi ? c3[q][0] : 0.f) - (xlo ? pxm : 0.f);
           d += (yhi[q] ? c3[q][1] : 0.f) - (ylo[q] ? pym : 0.f);
-          d += c3[q][2] - PzF[q];
+          if constexpr (!TV2) d += c3[q][2] - PzF(q);
           u = fmaf(tau, d, u);
         }
-        PzF[q] = c3[q][2];
+        if constexpr (!TV2) PzF(q) = c3[q][2];
         float xv;
         if (A.nonneg) {
           xv = fmaxf(u - A.thr, 0.f);
@@ -339,7 +458,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         if (m - 1 >= zb && m - 1 < ze) accumulate(xs, true, par ^ 1);
         s_x[par][wv][lane] = xs[0];  // read after the next output's barrier
 #pragma unroll
-        for (int q = 0; q < Q; ++q) Xp[q] = xs[q];
+        for (int q = 0; q < Q; ++q) Xp(q) = xs[q];
       }
     }
   };
@@ -355,7 +474,14 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       vring(a1, q) = vcopy(P.v[q]);
       c3[q][0] = FIRST ? 0.f : vcopy(P.p[q][0]);
       c3[q][1] = FIRST ? 0.f : vcopy(P.p[q][1]);
-      c3[q][2] = FIRST ? 0.f : vcopy(P.p[q][2]);
+      c3[q][2] = (FIRST || TV2) ? 0.f : vcopy(P.p[q][2]);
+    }
+    float ppa[Q][3];   // FGP: p_prev of plane a1 (one step: output of a1 comes at the next arrival)
+    if constexpr (FGP) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) ppa[q][k] = FIRST ? 0.f : vcopy(P.pp[q][k]);
     }
     if (a1 + 2 < zl) load_plane(P, a1 + 2);
 #pragma unroll
@@ -367,6 +493,12 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
     }
     const int m = a1 - L;
     if (m >= zs) output(m, par, c3);
+    if constexpr (FGP) {
+#pragma unroll
+      for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) PPv[q][k] = ppa[q][k];
+    }
   };
 
   InPlane PA, PB;
@@ -399,11 +531,13 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   }
   if constexpr (FINAL) {
     if (obj) {
-      if (ze == nz) {
-        // the last plane of the volume: no plane above it (its z-difference is 0)
+      if (ze == nz || TV2) {
+        // the last plane of the volume: no plane above it (its z-difference is
+        // 0); in 2D the last plane of every chunk, which has no z margin
         __syncthreads();
-        accumulate(Xp, false, (nsteps - 1) & 1);
+        accumulate(nullptr, false, (nsteps - 1) & 1);
       }
+      double s_acc = s_sum[threadIdx.x], t_acc = s_sum[NT + threadIdx.x];
 #pragma unroll
       for (int off = 32; off > 0; off >>= 1) {
         s_acc += __shfl_xor(s_acc, off, 64);
@@ -420,7 +554,6 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
           s += s_red[0][w];
           t += s_red[1][w];
         }
-        const size_t blk = (size_t)bx + (size_t)A.gx * ((size_t)by + (size_t)A.gy * bz);
         A.psum[blk] = s;
         A.ptv[blk] = t;
       }
@@ -428,36 +561,31 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
   }
 }
 
-template <int H>
-__device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int by, int bz) {
-  __shared__ float s_py[H + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step, parity
-  __shared__ float s_ut[H][2][kTvWaves][64];      // top-row u per wave, per step, parity
-  __shared__ float s_v[(H + 1) * kTvQ * kTvWaves * 64];  // v ring, thread-private
-  __shared__ float s_x[2][kTvWaves][64];          // final pass: first-row x per wave, parity
-  __shared__ double s_red[2][kTvWaves];           // final pass: per-wave sums
+// HT: tile halo, LV: fused-step register slots.  Dual passes use HT = LV = H;
+// the final pass HT = H + 1, LV = H.
+template <int HT, int LV, bool FINAL, bool TV2, bool FGP, bool BF>
+__device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int by, int zb, int ze, int blk) {
+  __shared__ float s_py[LV + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step (+ final), parity
+  __shared__ float s_ut[LV][2][kTvWaves][64];      // top-row u per wave, per step, parity
+  __shared__ float s_v[(LV + 1) * kTvQ * kTvWaves * 64];  // v ring, thread-private
+  __shared__ float s_x[FINAL ? 2 : 1][kTvWaves][64];     // final pass: first-row x per wave, parity
+  __shared__ double s_red[2][kTvWaves];            // final pass: per-wave sums
+  __shared__ float s_fin[FINAL ? 2 * kTvQ * kTvWaves * 64 : 1];    // final pass: PzF, Xp (thread-private)
+  __shared__ double s_sum[FINAL ? 2 * kTvWaves * 64 : 1];          // final pass: FP64 sums (thread-private)
   if (A.st != nullptr && A.st->done) return;
-  constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;
-  const int x0 = bx * IX - H, y0 = by * IY - H;
+  constexpr int IX = kTvRX - 2 * HT, IY = kTvRY - 2 * HT;
+  const int x0 = bx * IX - HT, y0 = by * IY - HT;
   // interior tile: every point of the region and its +-1 neighbours lie inside
   const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
-#define RIHVR_TV_BODY(E, F, FIN) \
-  tv_pass_body<H, (FIN) ? H - 1 : H, E, F, FIN>(A, bx, by, bz, s_py, s_ut, s_v, s_x, s_red)
-  if (A.final_) {
-    if (A.first) {
-      if (interior) RIHVR_TV_BODY(false, true, true);
-      else RIHVR_TV_BODY(true, true, true);
-    } else {
-      if (interior) RIHVR_TV_BODY(false, false, true);
-      else RIHVR_TV_BODY(true, false, true);
-    }
+  auto* sx = reinterpret_cast<float (*)[kTvWaves][64]>(&s_x[0][0][0]);
+#define RIHVR_TV_BODY(E, F) \
+  tv_pass_body<HT, LV, E, F, FINAL, TV2, FGP, BF>(A, bx, by, zb, ze, blk, s_py, s_ut, s_v, sx, s_red, s_fin, s_sum)
+  if (A.first) {
+    if (interior) RIHVR_TV_BODY(false, true);
+    else RIHVR_TV_BODY(true, true);
   } else {
-    if (A.first) {
-      if (interior) RIHVR_TV_BODY(false, true, false);
-      else RIHVR_TV_BODY(true, true, false);
-    } else {
-      if (interior) RIHVR_TV_BODY(false, false, false);
-      else RIHVR_TV_BODY(true, false, false);
-    }
+    if (interior) RIHVR_TV_BODY(false, false);
+    else RIHVR_TV_BODY(true, false);
   }
 #undef RIHVR_TV_BODY
 }
@@ -467,14 +595,46 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
 // one block per CU), which every fusion depth fits.
 constexpr int kTvWavesPerSimd = (kTvWaves + 3) / 4;
 
-template <int H>
-__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass(TvPassArgs A) {
-  const uint32_t n = gridDim.x * gridDim.y * gridDim.z;
-  const uint32_t t = xcd_tile(blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z), n);
-  tv_pass_entry<H>(A, t % A.gx, (t / A.gx) % A.gy, t / (A.gx * A.gy));
+// Work of block t of a pass (t < A.nblocks): the first nfull tiles (raster
+// order) times their z chunks of zchunk planes, tile-fastest; then the other
+// tiles times their chunks of zchunk2 planes.
+struct TvWork {
+  int bx, by, zb, ze;
+};
+__device__ __forceinline__ TvWork tv_work(const TvPassArgs& A, uint32_t t) {
+  const uint32_t n1 = (uint32_t)A.nfull * (uint32_t)((A.nz + A.zchunk - 1) / A.zchunk);
+  uint32_t tile, zb, zc;
+  if (t < n1) {
+    tile = t % A.nfull;
+    zc = A.zchunk;
+    zb = (t / A.nfull) * zc;
+  } else {
+    const uint32_t r = (uint32_t)(A.gx * A.gy - A.nfull), u = t - n1;
+    tile = A.nfull + u % r;
+    zc = A.zchunk2;
+    zb = (u / r) * zc;
+  }
+  TvWork w;
+  w.bx = (int)(tile % A.gx);
+  w.by = (int)(tile / A.gx);
+  w.zb = (int)zb;
+  w.ze = min(A.nz, (int)(zb + zc));
+  return w;
 }
 
-template <int H>
+// The first part of the grid (whole rounds of tiles) takes the XCD-contiguous
+// order; the thin chunks of the split tiles, dispatched last, keep the
+// hardware order so that they spread over every XCD.
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF>
+__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass(TvPassArgs A) {
+  const uint32_t hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  const uint32_t n1 = (uint32_t)A.nfull * (uint32_t)((A.nz + A.zchunk - 1) / A.zchunk);
+  const uint32_t t = hw < n1 ? xcd_tile(hw, n1) : hw;
+  const TvWork w = tv_work(A, t);
+  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF>(A, w.bx, w.by, w.zb, w.ze, (int)t);
+}
+
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF>
 __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(const TvPassArgs* __restrict__ args,
                                                                                   BatchMap map) {
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
@@ -485,63 +645,99 @@ __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(co
     else hi = mid;
   }
   lo = __builtin_amdgcn_readfirstlane(lo);  // uniform: the frame's arguments come in as scalar loads
-  const TvPassArgs A = args[lo];
+  // read in place (scalar loads when used) rather than copied: a copy of the
+  // whole struct held in scalar registers for the kernel's lifetime spills
+  const TvPassArgs& A = args[lo];
   const int lb = (int)(b - (uint32_t)__builtin_amdgcn_readfirstlane(map.offs[lo]));
-  tv_pass_entry<H>(A, lb % A.gx, (lb / A.gx) % A.gy, lb / (A.gx * A.gy));
+  const TvWork w = tv_work(A, (uint32_t)lb);
+  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF>(A, w.bx, w.by, w.zb, w.ze, lb);
 }
 
 // Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut into
 // chunks of at least 16 planes until the grid holds about `want` blocks.
-static void pass_grid(int nx, int ny, int nz, int H, int want, dim3* grid, int* zchunk) {
-  const int tx = (nx + (kTvRX - 2 * H) - 1) / (kTvRX - 2 * H);
-  const int ty = (ny + (kTvRY - 2 * H) - 1) / (kTvRY - 2 * H);
-  const int nzc = std::max(1, std::min(nz / 16, (want + tx * ty - 1) / (tx * ty)));
-  const int zc = (nz + nzc - 1) / nzc;
-  *zchunk = zc;
-  *grid = dim3(tx, ty, (nz + zc - 1) / zc);
+// `halo` is the tile halo of the pass (H on dual passes, H + 1 on the final).
+struct TvGrid {
+  int gx, gy, zchunk, nfull, zchunk2, nblocks;
+};
+
+static TvGrid pass_grid(int nx, int ny, int nz, int halo, int want) {
+  TvGrid g{};
+  g.gx = (nx + (kTvRX - 2 * halo) - 1) / (kTvRX - 2 * halo);
+  g.gy = (ny + (kTvRY - 2 * halo) - 1) / (kTvRY - 2 * halo);
+  const int tiles = g.gx * g.gy;
+  const int nzc = std::max(1, std::min(nz / 16, (want + tiles - 1) / tiles));
+  g.zchunk = (nz + nzc - 1) / nzc;
+  g.nfull = tiles;
+  g.zchunk2 = g.zchunk;
+  g.nblocks = tiles * ((nz + g.zchunk - 1) / g.zchunk);
+  return g;
+}
+
+// The final pass runs one 12-wave block per compute unit, so its time is
+// whole rounds of `cus` blocks.  Its tiles are one voxel smaller than those of
+// the dual passes; when they fill whole rounds but for a few (at 1024^2 one
+// tile beyond 512), the leftover tiles are cut into thin z chunks that run
+// side by side in one short extra round instead of a full one.
+static TvGrid final_grid(int nx, int ny, int nz, int H, int want, int cus) {
+  TvGrid g = pass_grid(nx, ny, nz, H + 1, want);
+  const int tiles = g.gx * g.gy;
+  if (cus <= 0 || g.zchunk < nz || tiles <= cus) return g;
+  const int r = tiles % cus;
+  const int k = r > 0 ? std::min(nz, cus / r) : 1;
+  if (k < 2) return g;
+  g.nfull = tiles - r;
+  g.zchunk2 = (nz + k - 1) / k;
+  g.nblocks = g.nfull + r * ((nz + g.zchunk2 - 1) / g.zchunk2);
+  return g;
 }
 
 static int clamp_levels(int H) { return H < kTvLevelsMin ? kTvDefaultLevels : std::min(H, kTvLevelsMax); }
 
-int prox_passes(int inner_iters, double tau, int levels) {
+int prox_passes(int inner_iters, double tau, int levels, bool fgp) {
   if (!(tau > 0.0) || inner_iters <= 0) return 1;
+  if (fgp) return inner_iters;        // one accelerated step per pass
   const int H = clamp_levels(levels);
-  return (inner_iters + 1 + H - 1) / H;   // K dual steps + one primal half step
+  return (inner_iters + H - 1) / H;   // H dual steps per pass, the final pass included
 }
+
+// Fusion depth a prox runs with (FGP passes use the depth-2 tiles).
+int prox_levels(int levels, bool fgp) { return fgp ? 2 : clamp_levels(levels); }
 
 size_t tv_pass_args_size() { return sizeof(TvPassArgs); }
 
 int tv_pass_blocks(int nx, int ny, int nz, int levels, int blocks) {
-  dim3 g;
-  int zc = 0;
-  pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks, &g, &zc);
-  return (int)(g.x * g.y * g.z);
+  return pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks).nblocks;
 }
 
-int tv_blocks_bound(int nx, int ny, int nz) {
-  // the most tiles (deepest halo) times the most z chunks pass_grid makes
-  const int tx = (nx + (kTvRX - 2 * kTvLevelsMax) - 1) / (kTvRX - 2 * kTvLevelsMax);
-  const int ty = (ny + (kTvRY - 2 * kTvLevelsMax) - 1) / (kTvRY - 2 * kTvLevelsMax);
-  return tx * ty * std::max(1, nz / 16);
+int tv_final_blocks(int nx, int ny, int nz, int levels, int blocks, int cus) {
+  return final_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks, cus).nblocks;
+}
+
+int tv_blocks_bound(int nx, int ny, int nz, int cus) {
+  // the most tiles (the final pass's halo at the deepest fusion) times the
+  // most z chunks pass_grid makes, or the split of final_grid (at most one
+  // thin chunk per compute unit beyond the tiles)
+  const int h = kTvLevelsMax + 1;
+  const int tx = (nx + (kTvRX - 2 * h) - 1) / (kTvRX - 2 * h);
+  const int ty = (ny + (kTvRY - 2 * h) - 1) / (kTvRY - 2 * h);
+  return tx * ty * std::max(1, nz / 16) + std::max(cus, 0);
 }
 
 int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks) {
-  dim3 g;
-  int zc = 0;
-  pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks, &g, &zc);
-  return zc;
+  return pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks).zchunk;
 }
 
-// Argument structs of every pass of one prox application.  Dual steps per
-// pass: non-final passes take H, the final pass the rest (at most H - 1,
-// leaving room for the primal half step in its halo).
+// Argument structs of every pass of one prox application.  Every pass takes
+// up to H dual steps; the final pass (its own tile grid, halo H + 1) also
+// recovers the primal, thresholds and stores x.
 int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   const double tau = pa.step * pa.tv;
   const double thr = pa.step * pa.l1;
   const bool use_tv = tau > 0.0 && pa.inner_iters > 0;
   const int K = use_tv ? pa.inner_iters : 0;
-  const int H = clamp_levels(pa.levels);
-  const int npass = prox_passes(K, tau, H);
+  const bool fgp = pa.fgp != 0;
+  const int H = prox_levels(pa.levels, fgp);
+  const int npass = prox_passes(K, tau, H, fgp);
   TvPassArgs a{};
   a.v = pa.v;
   a.x = pa.x;
@@ -554,26 +750,44 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   a.nx = pa.nx; a.ny = pa.ny; a.nz = pa.nz;
   a.nonneg = pa.nonneg;
   a.tau = (float)tau;
-  a.c = use_tv ? (float)(1.0 / (12.0 * tau)) : 0.f;
+  a.tv2 = pa.tv2 ? 1 : 0;
+  a.dual_bf16 = pa.dual_bf16 ? 1 : 0;
+  a.c = use_tv ? (float)(1.0 / ((pa.tv2 ? 8.0 : 12.0) * tau)) : 0.f;
   a.thr = (float)thr;
-  dim3 grid;
-  pass_grid(pa.nx, pa.ny, pa.nz, H, pa.blocks > 0 ? pa.blocks : kTvDefaultBlocks, &grid, &a.zchunk);
-  a.gx = grid.x;
-  a.gy = grid.y;
-  if (blocks_per_pass) *blocks_per_pass = grid.x * grid.y * grid.z;
+  const int want = pa.blocks > 0 ? pa.blocks : kTvDefaultBlocks;
   TvPassArgs* o = static_cast<TvPassArgs*>(out);
   int done = 0;
+  double tk = 1.0;   // FGP: t_k of the step a pass takes
   for (int p = 0; p < npass; ++p) {
     const bool fin = p == npass - 1;
-    const int lv = fin ? K - done : std::min(H, K - done);
+    const TvGrid g = fin ? final_grid(pa.nx, pa.ny, pa.nz, H, want, pa.cus) : pass_grid(pa.nx, pa.ny, pa.nz, H, want);
+    a.gx = g.gx;
+    a.gy = g.gy;
+    a.zchunk = g.zchunk;
+    a.nfull = g.nfull;
+    a.zchunk2 = g.zchunk2;
+    a.nblocks = g.nblocks;
+    if (blocks_per_pass) blocks_per_pass[p] = g.nblocks;
+    const int lv = fgp ? std::min(1, K - done) : std::min(H, K - done);
     a.levels = lv;
-    a.first = (done == 0) ? 1 : 0;
+    a.first = (done == 0 && !pa.warm) ? 1 : 0;   // a warm dual is read by the first pass
     a.final_ = fin ? 1 : 0;
+    a.keep_dual = (fin && pa.warm) ? 1 : 0;
+    a.flip_npass = (pa.warm && (npass & 1)) ? npass : 0;
+    a.fgp = (fgp && !fin) ? 1 : 0;
+    const double tn = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * tk * tk));
+    a.fgp_w = (float)((tk - 1.0) / tn);
+    tk = tn;
     float* const* src = (p & 1) ? pa.pb : pa.pa;
     float* const* dst = (p & 1) ? pa.pa : pa.pb;
+    float* const* src2 = (p & 1) ? pa.pb2 : pa.pa2;
+    float* const* dst2 = (p & 1) ? pa.pa2 : pa.pb2;
     for (int k = 0; k < 3; ++k) {
-      a.pin[k] = src[k];
-      a.pout[k] = dst[k];
+      const bool none = pa.tv2 && k == 2;
+      a.pin[k] = none ? nullptr : src[k];
+      a.pout[k] = none ? nullptr : dst[k];
+      a.pin2[k] = (none || !fgp) ? nullptr : src2[k];
+      a.pout2[k] = (none || !fgp) ? nullptr : dst2[k];
     }
     o[p] = a;
     done += lv;
@@ -581,32 +795,76 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   return npass;
 }
 
+// Kernel selection: fusion depth, final / dual pass, 2D or 3D TV, FGP (dual
+// passes of depth-2 tiles only), bfloat16 dual.  BATCH picks the batched form.
+template <bool BATCH, bool FINAL, bool TV2, bool FGP, bool BF>
+static void launch_k(int H, dim3 g, const TvPassArgs* a, BatchMap map, hipStream_t s) {
+  const dim3 b(kTvWaves * 64);
+  if constexpr (FGP) {
+    if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, true, BF>), g, b, 0, s, a, map);
+    else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, true, BF>), g, b, 0, s, *a);
+  } else {
+    switch (H) {
+      case 2:
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        break;
+      case 3:
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<3, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<3, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        break;
+      default:
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<4, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<4, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        break;
+    }
+  }
+}
+
+template <bool BATCH, bool FINAL, bool TV2>
+static void launch_sel(bool fgp, bool bf, int H, dim3 g, const TvPassArgs* a, BatchMap map, hipStream_t s) {
+  if constexpr (!FINAL) {
+    if (fgp) {
+      if (bf) launch_k<BATCH, false, TV2, true, true>(H, g, a, map, s);
+      else launch_k<BATCH, false, TV2, true, false>(H, g, a, map, s);
+      return;
+    }
+  }
+  if (bf) launch_k<BATCH, FINAL, TV2, false, true>(H, g, a, map, s);
+  else launch_k<BATCH, FINAL, TV2, false, false>(H, g, a, map, s);
+}
+
+template <bool BATCH>
+static void launch_any(bool final_pass, bool tv2, bool fgp, bool bf, int H, dim3 g, const TvPassArgs* a,
+                       BatchMap map, hipStream_t s) {
+  if (final_pass) {
+    if (tv2) launch_sel<BATCH, true, true>(false, bf, H, g, a, map, s);
+    else launch_sel<BATCH, true, false>(false, bf, H, g, a, map, s);
+  } else {
+    if (tv2) launch_sel<BATCH, false, true>(fgp, bf, H, g, a, map, s);
+    else launch_sel<BATCH, false, false>(fgp, bf, H, g, a, map, s);
+  }
+}
+
 hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
   const double tau = pa.step * pa.tv;
   const int K = (tau > 0.0 && pa.inner_iters > 0) ? pa.inner_iters : 0;
-  const int H = clamp_levels(pa.levels);
-  std::vector<TvPassArgs> args(prox_passes(K, tau, H));
-  int nb = 0;
-  const int npass = prox_pass_args(pa, args.data(), &nb);
-  const dim3 grid(args[0].gx, args[0].gy, (nb / (args[0].gx * args[0].gy)));
-  for (int p = 0; p < npass; ++p) {
-    switch (H) {
-      case 2: hipLaunchKernelGGL(k_tv_pass<2>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
-      case 3: hipLaunchKernelGGL(k_tv_pass<3>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
-      default: hipLaunchKernelGGL(k_tv_pass<4>, grid, dim3(kTvWaves * 64), 0, s, args[p]); break;
-    }
-  }
+  const int H = prox_levels(pa.levels, pa.fgp != 0);
+  const int np = prox_passes(K, tau, H, pa.fgp != 0);
+  std::vector<TvPassArgs> args(np);
+  std::vector<int> nb(np);
+  const int npass = prox_pass_args(pa, args.data(), nb.data());
+  for (int p = 0; p < npass; ++p)
+    launch_any<false>(args[p].final_ != 0, args[p].tv2 != 0, args[p].fgp != 0, args[p].dual_bf16 != 0, H,
+                      dim3(nb[p]), &args[p], BatchMap{nullptr, 0}, s);
   if (launches) *launches = npass;
   return hipGetLastError();
 }
 
-hipError_t launch_tv_pass_batched(int levels, const void* args, BatchMap map, int nblocks, hipStream_t s) {
-  const TvPassArgs* a = static_cast<const TvPassArgs*>(args);
-  switch (clamp_levels(levels)) {
-    case 2: hipLaunchKernelGGL(k_tv_pass_b<2>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
-    case 3: hipLaunchKernelGGL(k_tv_pass_b<3>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
-    default: hipLaunchKernelGGL(k_tv_pass_b<4>, dim3(nblocks), dim3(kTvWaves * 64), 0, s, a, map); break;
-  }
+hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, const void* args,
+                                  BatchMap map, int nblocks, hipStream_t s) {
+  launch_any<true>(final_pass, tv2, fgp && !final_pass, bf16, clamp_levels(levels), dim3(nblocks),
+                   static_cast<const TvPassArgs*>(args), map, s);
   return hipGetLastError();
 }
 

@@ -31,12 +31,16 @@ RI_ERR_NOT_CONVERGED = 7
 RI_F32, RI_F64 = 0, 1
 
 RI_NO_CARRIER = 0x1
+RI_TV2D = 0x2
+RI_TV_FGP = 0x4
+RI_TV_DUAL_BF16 = 0x8
 RI_INIT_ZERO = 0
 RI_INIT_GIVEN = 1
 RI_SOLVE_DENSE = 0x1
 RI_SOLVE_NO_GRAPH = 0x2
 RI_SOLVE_RESTART = 0x4
 RI_SOLVE_TIMING = 0x8
+RI_SOLVE_DUAL_WARM = 0x10
 
 RI_OP_FORWARD, RI_OP_ADJOINT, RI_OP_PROX, RI_OP_SOLVE, RI_OP_AUTOTUNE = 0, 1, 2, 3, 4
 RI_NUM_PHASES = 6
@@ -49,8 +53,17 @@ EXPORTED = (
     "ri_workspace_size_batched",
     "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
     "ri_unet_train_step",
+    "ri_detect_workspace_size", "ri_detect", "ri_link_workspace_size", "ri_link", "ri_track_update",
+    "ri_track_filter",
     "ri_status_string", "ri_last_error",
 )
+
+
+class ri_detect_params(C.Structure):
+    _fields_ = [("rel_threshold", C.c_double), ("min_voxels", C.c_int32)]
+
+
+RI_OBJECT_FIELDS = ("z", "y", "x", "weight", "voxels", "first")   # ri_object: 6 doubles
 
 
 class ri_geometry(C.Structure):
@@ -153,6 +166,13 @@ def lib():
     L.ri_unet_train_step.argtypes = [cfgp, vp, vp, vp, vp, C.c_int32, fp, vp, fp, vp, fp, C.c_int32, C.c_int32,
                                      C.c_int32, vp, vp, sz, vp]
     L.ri_forward_noalloc_max_scratch.restype = C.c_size_t
+    i32 = C.c_int32
+    L.ri_detect_workspace_size.argtypes = [i32, i32, i32, i32, C.POINTER(C.c_size_t)]
+    L.ri_detect.argtypes = [C.POINTER(ri_detect_params), vp, i32, i32, i32, vp, i32, vp, i32, vp, sz, vp]
+    L.ri_link_workspace_size.argtypes = [i32, i32, C.POINTER(C.c_size_t)]
+    L.ri_link.argtypes = [vp, vp, i32, vp, vp, i32, C.POINTER(C.c_double), C.c_double, vp, vp, vp, sz, vp]
+    L.ri_track_update.argtypes = [vp, vp, vp, vp, i32, vp, vp, vp, i32, vp]
+    L.ri_track_filter.argtypes = [vp, vp, i32, i32, vp, vp, vp]
     L.ri_status_string.argtypes = [C.c_int]
     L.ri_status_string.restype = C.c_char_p
     L.ri_last_error.argtypes = []
@@ -300,8 +320,14 @@ def _stream_handle(torch):
 
 
 def geometry_struct(geom) -> ri_geometry:
-    """From any object with nx, ny, nz, pixel_um, wavelength_um, z0_um, dz_um[, carrier]."""
+    """From any object with nx, ny, nz, pixel_um, wavelength_um, z0_um, dz_um[, carrier, tv_dims]."""
     flags = 0 if getattr(geom, "carrier", True) else RI_NO_CARRIER
+    if getattr(geom, "tv_dims", 3) == 2:
+        flags |= RI_TV2D
+    if getattr(geom, "tv_fgp", False):
+        flags |= RI_TV_FGP
+    if getattr(geom, "dual_bf16", False):
+        flags |= RI_TV_DUAL_BF16
     return ri_geometry(int(geom.nx), int(geom.ny), int(geom.nz), float(geom.pixel_um),
                        float(geom.wavelength_um), float(geom.z0_um), float(geom.dz_um), flags)
 
@@ -470,3 +496,78 @@ class UNet:
                                   ws.numel(),
                                   _stream_handle(torch)), "ri_unet_train_step")
         return loss
+
+
+# ---------------------------------------------------------------------------
+# Particle tracking back end (torch tensors in, torch tensors out)
+# ---------------------------------------------------------------------------
+def detect(x, rel_threshold=1.0 / 256.0, min_voxels=5, max_objects=65536, max_components=1 << 20):
+    """Objects of a float32 volume [nz][ny][nx] on the device: returns
+    (objects [max_objects][6] float64 device tensor, counts [2] int32 device
+    tensor: kept objects, components).  Rows follow ri_object (z, y, x,
+    weight, voxels, first)."""
+    import torch
+    nz, ny, nx = x.shape
+    nbytes = C.c_size_t()
+    _check(lib().ri_detect_workspace_size(nx, ny, nz, max_components, C.byref(nbytes)), "ri_detect_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=x.device)
+    objs = torch.zeros((max_objects, 6), dtype=torch.float64, device=x.device)
+    counts = torch.zeros(2, dtype=torch.int32, device=x.device)
+    prm = ri_detect_params(float(rel_threshold), int(min_voxels))
+    _check(lib().ri_detect(C.byref(prm), x.data_ptr(), nx, ny, nz, objs.data_ptr(), max_objects, counts.data_ptr(),
+                           max_components, ws.data_ptr(), ws.numel(), _stream_handle(torch)), "ri_detect")
+    return objs, counts
+
+
+def link(prev, n_prev, cur, n_cur, max_disp, spacing=(1.0, 1.0, 1.0)):
+    """Crocker-Grier links of object tables prev -> cur (device tensors with
+    device counts n_prev, n_cur: int32 tensors of one element): returns
+    (link [len(prev)] int32, status [1] int32), both on the device."""
+    import torch
+    nbytes = C.c_size_t()
+    _check(lib().ri_link_workspace_size(prev.shape[0], cur.shape[0], C.byref(nbytes)), "ri_link_workspace_size")
+    ws = torch.empty(nbytes.value, dtype=torch.uint8, device=prev.device)
+    lk = torch.full((prev.shape[0],), -1, dtype=torch.int32, device=prev.device)
+    status = torch.zeros(1, dtype=torch.int32, device=prev.device)
+    sp = (C.c_double * 3)(*[float(v) for v in spacing])
+    _check(lib().ri_link(prev.data_ptr(), n_prev.data_ptr(), prev.shape[0], cur.data_ptr(), n_cur.data_ptr(),
+                         cur.shape[0], sp, float(max_disp), lk.data_ptr(), status.data_ptr(), ws.data_ptr(),
+                         ws.numel(), _stream_handle(torch)), "ri_link")
+    return lk, status
+
+
+class Tracks:
+    """Track ids frame by frame on the device (ri_track_update), then the
+    minimum-duration filter (ri_track_filter)."""
+
+    def __init__(self, max_tracks=1 << 20):
+        import torch
+        self.torch = torch
+        self.max_tracks = max_tracks
+        self.track_len = torch.zeros(max_tracks, dtype=torch.int32, device="cuda")
+        self.next_id = torch.zeros(1, dtype=torch.int32, device="cuda")
+        self.ids = None
+        self.n = torch.zeros(1, dtype=torch.int32, device="cuda")
+
+    def update(self, lk, n_cur, max_cur):
+        """lk: links from the previous frame (None for the first frame)."""
+        torch = self.torch
+        ids = torch.full((max_cur,), -1, dtype=torch.int32, device="cuda")
+        zero = torch.zeros(1, dtype=torch.int32, device="cuda")
+        n_prev = self.n if lk is not None else zero
+        _check(lib().ri_track_update(lk.data_ptr() if lk is not None else None, n_prev.data_ptr(),
+                                     self.ids.data_ptr() if lk is not None else None, n_cur.data_ptr(), max_cur,
+                                     ids.data_ptr(), self.next_id.data_ptr(), self.track_len.data_ptr(),
+                                     self.max_tracks, _stream_handle(torch)), "ri_track_update")
+        self.ids = ids
+        self.n = n_cur.clone()
+        return ids
+
+    def kept(self, min_len):
+        torch = self.torch
+        kept = torch.zeros(self.max_tracks, dtype=torch.uint8, device="cuda")
+        n_kept = torch.zeros(1, dtype=torch.int32, device="cuda")
+        _check(lib().ri_track_filter(self.track_len.data_ptr(), self.next_id.data_ptr(), self.max_tracks,
+                                     int(min_len), kept.data_ptr(), n_kept.data_ptr(), _stream_handle(torch)),
+               "ri_track_filter")
+        return kept, n_kept

@@ -34,6 +34,9 @@ class Geometry:
     pixel_um: lateral pixel pitch; wavelength_um: illumination wavelength.
     Plane j sits at z_j = z0_um + j * dz_um from the sensor.
     carrier: keep the exp(i 2 pi z / lambda) carrier in the transfer function.
+    tv_dims: 3 for the 3D TV, 2 for the per-plane 2D TV of the paper's Eq. (4).
+    tv_fgp, dual_bf16: inner-solver options of the library (accelerated dual
+    iteration; dual stored in bfloat16).
     """
     nx: int
     ny: int
@@ -43,6 +46,9 @@ class Geometry:
     z0_um: float
     dz_um: float
     carrier: bool = True
+    tv_dims: int = 3
+    tv_fgp: bool = False
+    dual_bf16: bool = False
 
     @property
     def shape(self):

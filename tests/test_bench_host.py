@@ -21,3 +21,22 @@ def test_measured_traffic_lookup():
     t = bench.measured_traffic({"tv_levels": 4, "tv_blocks": 256, "col_blocks": 512})
     assert t is None or t > 6.6e9          # at least the algorithmic bytes of a pass
     assert bench.measured_traffic({"tv_levels": 2, "tv_blocks": 6144, "col_blocks": 512}) is None
+
+
+def test_cpu_baseline_runs_the_oracle_on_worker_processes():
+    from paper_1904_04884_amd import scenes
+    cfg = scenes.config_c2()
+    g = scenes.geometry_c2()
+    nvox = g.nx * g.ny * g.nz
+    r = bench.cpu_baseline(scenes, 100, nvox, cfg, workers=2)
+    assert r["cores"] == 2 and r["kind"] == "oracle" and len(r["slab_seconds"]) == 2
+    # two slabs of 8 planes, one iteration each: the rate is their voxels over the wall time
+    assert r["voxel_iters_per_s"] > 0
+    assert abs(r["value"] - r["voxel_iters_per_s"] / (nvox * 100)) <= 1e-12 * r["value"]
+
+
+def test_prox_bytes_per_voxel_schedule():
+    # first pass v in, p out; middle passes v, p in, p out; final v, p in, x out
+    assert bench.prox_bytes_per_voxel(1) == 8.0
+    assert bench.prox_bytes_per_voxel(2) == 16.0 + 20.0
+    assert bench.prox_bytes_per_voxel(5) == 120.0

@@ -181,6 +181,20 @@ def test_prox_in_place(torch_cuda, plans):
     assert torch.equal(a, b)
 
 
+def exact_tv1d(v, tau):
+    """Exact 1D TV prox through its dual, the box-constrained least squares
+    min_{|p_i| <= 1} 1/2 ||v - tau D^T p||^2 solved by bounded-variable least
+    squares (an active-set method that terminates at the exact minimiser);
+    enumerating the 3^(n-1) active sets is too slow at n = 16."""
+    from scipy.optimize import lsq_linear
+    n = len(v)
+    D = np.zeros((n - 1, n))
+    for i in range(n - 1):
+        D[i, i], D[i, i + 1] = -1.0, 1.0
+    p = lsq_linear(tau * D.T, v, bounds=(-1.0, 1.0), method="bvls", tol=1e-15).x
+    return v - tau * D.T @ p
+
+
 def test_prox_line_matches_brute_force_1d(torch_cuda, plans):
     """A 1 x 1 x n line along x: isotropic TV is 1D TV and the fused-lasso prox is
     exact; GP with many steps must approach the brute-force dual solution."""
@@ -202,8 +216,11 @@ def test_prox_line_matches_brute_force_1d(torch_cuda, plans):
     line[0, 0, :] = rng.standard_normal(n)
     line[0, 1:, :] = line[0, 0, :]  # constant along y: no y-differences
     out1 = to_host(plans(g1).prox(to_dev(torch, line), 1.0, thr, tau, 4000))
-    exact = np.maximum(brute_tv1d(line[0, 0].astype(np.float64), tau) - thr, 0.0)
+    exact = np.maximum(exact_tv1d(line[0, 0].astype(np.float64), tau) - thr, 0.0)
     assert np.max(np.abs(out1[0, 0] - exact)) <= 1e-4
+    # the bounded least-squares dual agrees with the enumerated one on a short line
+    w = rng.standard_normal(7)
+    assert np.max(np.abs(exact_tv1d(w, tau) - brute_tv1d(w, tau))) <= 1e-12
 
 
 # ---------------------------------------------------------------------------

@@ -286,6 +286,153 @@ def test_p13_tv_prox_invariants():
     assert np.allclose(prox.prox_tv_gp(c, 0.3, 10), c, atol=0, rtol=0)
 
 
+# --- Variants of the prox: per-plane 2D TV, warm-started dual, FGP, dual rounding ---
+# (the paper's Eq. 4 is a per-plane 2D TV; the GP dual step is 1/(4 dims tau);
+# a dual warm start and FGP are the inner-solver options of the same GP method)
+@pytest.mark.parametrize("dims,factor", [(3, 5.0 / 6.0), (2, 3.0 / 4.0)])
+def test_gp_dual_closed_form_two_points(dims, factor):
+    """Two voxels along x, v = (a, b): D^T D = 2 on the single difference, so a
+    GP step with c = 1/(4 dims tau) maps p to (1 - 2 tau c) p + c (b - a), and
+    from p = 0: p_k = (b - a)/(2 tau) (1 - (1 - 2 tau c)^k) while |p| < 1 --
+    1 - 2 tau c is 5/6 in 3D and 3/4 in 2D (the step of each)."""
+    a, b, tau = 0.2, 1.0, 1.0
+    v = np.array([a, b]).reshape(1, 1, 2)
+    for k in range(0, 9):
+        u, (px, py, pz) = prox.prox_tv_gp(v, tau, k, return_dual=True, dims=dims)
+        pk = (b - a) / (2 * tau) * (1 - factor ** k)
+        assert px[0, 0, 0] == pytest.approx(pk, abs=1e-15)
+        assert np.all(py == 0) and np.all(pz == 0) and px[0, 0, 1] == 0.0
+        assert u.ravel() == pytest.approx([a + tau * pk, b - tau * pk], abs=1e-15)
+
+
+def test_tv2d_brute_force_and_no_z_coupling():
+    rng = np.random.default_rng(21)
+    u = rng.standard_normal((3, 3, 4))
+    tot = 0.0
+    for z, y, x in itertools.product(range(3), range(3), range(4)):
+        gx = u[z, y, x + 1] - u[z, y, x] if x < 3 else 0.0
+        gy = u[z, y + 1, x] - u[z, y, x] if y < 2 else 0.0
+        tot += math.sqrt(gx * gx + gy * gy)
+    assert prox.tv(u, 2) == pytest.approx(tot, rel=1e-14)
+    # a line along z has no 2D variation: its prox is the identity
+    v = rng.standard_normal((6, 1, 1))
+    assert np.array_equal(prox.prox_tv_gp(v, 0.4, 50, dims=2), v)
+    # a different constant in every plane is a fixed point in 2D, not in 3D
+    c = np.broadcast_to(np.arange(4.0)[:, None, None], (4, 5, 6)).copy()
+    assert np.array_equal(prox.prox_tv_gp(c, 0.3, 10, dims=2), c)
+    assert not np.allclose(prox.prox_tv_gp(c, 0.3, 10, dims=3), c)
+
+
+@pytest.mark.parametrize("seed,n", [(3, 5), (4, 6)])
+def test_tv2d_prox_matches_brute_1d_along_x_and_y(seed, n):
+    rng = np.random.default_rng(seed)
+    v = rng.standard_normal(n)
+    tau, thr = 0.35, 0.1
+    x_exact = np.maximum(brute_tv1d(v, tau) - thr, 0.0)
+    for shape in ((1, 1, n), (1, n, 1)):
+        x = prox.prox_fused_lasso(v.reshape(shape), 1.0, thr, tau, 20000, dims=2).ravel()
+        assert np.max(np.abs(x - x_exact)) <= 1e-8
+
+
+def test_tv2d_planes_are_independent_and_keep_their_means():
+    rng = np.random.default_rng(22)
+    v = rng.standard_normal((4, 6, 7))
+    u = prox.prox_tv_gp(v, 0.25, 15, dims=2)
+    for j in range(4):
+        uj = prox.prox_tv_gp(v[j:j + 1], 0.25, 15, dims=2)
+        assert np.array_equal(u[j:j + 1], uj)
+        assert abs(u[j].sum() - v[j].sum()) <= 1e-12 * np.abs(v[j]).sum()
+
+
+def test_dual_warm_start_continues_the_iteration():
+    """k1 steps from p = 0, then k2 steps from that dual, equal k1 + k2 steps
+    from 0 (the GP state is the dual alone); the converged dual is a fixed
+    point (two-point case: p* = (b - a)/(2 tau))."""
+    rng = np.random.default_rng(23)
+    v = rng.standard_normal((3, 5, 6))
+    for dims in (2, 3):
+        u_a, p_a = prox.prox_tv_gp(v, 0.3, 4, return_dual=True, dims=dims)
+        u_b, p_b = prox.prox_tv_gp(v, 0.3, 3, return_dual=True, dims=dims, p0=p_a)
+        u_c, p_c = prox.prox_tv_gp(v, 0.3, 7, return_dual=True, dims=dims)
+        assert np.array_equal(u_b, u_c) and all(np.array_equal(x, y) for x, y in zip(p_b, p_c))
+    w = np.array([0.0, 1.0]).reshape(1, 1, 2)
+    pstar = (np.array([[[0.5, 0.0]]]), np.zeros((1, 1, 2)), np.zeros((1, 1, 2)))
+    u, p = prox.prox_tv_gp(w, 1.0, 3, return_dual=True, p0=pstar)
+    assert p[0][0, 0, 0] == 0.5 and u.ravel().tolist() == [0.5, 0.5]
+
+
+def test_fgp_two_points_matches_scalar_recurrence():
+    """On two voxels the FGP iteration is a scalar one: p_k = clip(g r_k + c (b - a)),
+    g = 1 - 2 tau c, t_{k+1} = (1 + sqrt(1 + 4 t_k^2))/2,
+    r_{k+1} = p_k + ((t_k - 1)/t_{k+1}) (p_k - p_{k-1})."""
+    a, b, tau = 0.0, 3.0, 1.0
+    for dims in (2, 3):
+        c = 1.0 / (4 * dims * tau)
+        g = 1.0 - 2.0 * tau * c
+        p_prev, r, t = 0.0, 0.0, 1.0
+        v = np.array([a, b]).reshape(1, 1, 2)
+        for k in range(1, 12):
+            p = min(1.0, max(-1.0, g * r + c * (b - a)))
+            t_new = (1 + math.sqrt(1 + 4 * t * t)) / 2
+            r = p + (t - 1) / t_new * (p - p_prev)
+            p_prev, t = p, t_new
+            _, (px, _, _) = prox.prox_tv_gp(v, tau, k, return_dual=True, dims=dims, fast=True)
+            assert px[0, 0, 0] == pytest.approx(p, abs=1e-15), (dims, k)
+    # FGP reaches the clipped optimum (p = 1 here: |b - a| > 2 tau) in fewer steps than GP
+    v = np.array([a, b]).reshape(1, 1, 2)
+    k_fgp = next(k for k in range(1, 200)
+                 if prox.prox_tv_gp(v, tau, k, return_dual=True, fast=True)[1][0][0, 0, 0] == 1.0)
+    k_gp = next(k for k in range(1, 200) if prox.prox_tv_gp(v, tau, k, return_dual=True)[1][0][0, 0, 0] == 1.0)
+    assert k_fgp < k_gp
+
+
+def test_dual_rounding_is_applied_at_the_stated_steps():
+    rng = np.random.default_rng(24)
+    v = rng.standard_normal((3, 4, 5))
+    q = lambda a: np.round(a * 64.0) / 64.0          # a coarse rounding, easy to see
+    # rounded after steps 3 and 6 of 7: seven steps equal 6 rounded steps then one more
+    _, p6 = prox.prox_tv_gp(v, 0.3, 6, return_dual=True, store=q, store_every=3)
+    _, p7 = prox.prox_tv_gp(v, 0.3, 7, return_dual=True, store=q, store_every=3)
+    _, p6r = prox.prox_tv_gp(v, 0.3, 1, return_dual=True, p0=tuple(q(a) for a in p6))
+    assert all(np.array_equal(x, y) for x, y in zip(p7, p6r))
+    # the last step is not rounded (it stays on chip): 6 steps leave step 6 unrounded
+    assert not np.array_equal(p6[0], q(p6[0]))
+    # steps 1..3 rounded at 3, then 3 more from the rounded dual: 6 steps rounded at 3
+    _, p3 = prox.prox_tv_gp(v, 0.3, 4, return_dual=True, store=q, store_every=3)
+    _, p3a = prox.prox_tv_gp(v, 0.3, 3, return_dual=True)
+    _, p3b = prox.prox_tv_gp(v, 0.3, 1, return_dual=True, p0=tuple(q(a) for a in p3a))
+    assert all(np.array_equal(x, y) for x, y in zip(p3, p3b))
+    # rounding every step and every third step are different iterations
+    _, pe = prox.prox_tv_gp(v, 0.3, 7, return_dual=True, store=q, store_every=1)
+    assert not np.array_equal(pe[0], p7[0])
+    # FGP: the extrapolated point is what the next pass reads, and it is rounded too
+    _, f4 = prox.prox_tv_gp(v, 0.3, 4, return_dual=True, fast=True, store=q, store_every=2)
+    _, f4u = prox.prox_tv_gp(v, 0.3, 4, return_dual=True, fast=True)
+    assert not np.array_equal(f4[0], f4u[0])
+
+
+def test_fista_variants_first_iterate_and_converged_inner_solve():
+    g = small_geom(nx=16, ny=16, nz=2)
+    rng = np.random.default_rng(25)
+    b = rng.standard_normal((16, 16))
+    # the first outer iteration of a dual-warm solve starts from p = 0: same as cold
+    x1 = fista.fista(g, b, 0.05, 0.3, 1, 5)
+    assert np.array_equal(fista.fista(g, b, 0.05, 0.3, 1, 5, dual_warm=True), x1)
+    # as the inner problem converges, the start of the dual and the dual method
+    # stop mattering: the iterates approach one another
+    diffs = []
+    for k in (30, 300, 3000):
+        xc = fista.fista(g, b, 0.05, 0.3, 3, k)
+        xw = fista.fista(g, b, 0.05, 0.3, 3, k, dual_warm=True)
+        xf = fista.fista(g, b, 0.05, 0.3, 3, k, fgp=True)
+        diffs.append((np.max(np.abs(xw - xc)), np.max(np.abs(xf - xc))))
+    assert diffs[2][0] < diffs[1][0] < diffs[0][0] and diffs[2][0] <= 2e-4 * np.max(np.abs(xc))
+    assert diffs[2][1] < diffs[1][1] < diffs[0][1] and diffs[2][1] <= 2e-4 * np.max(np.abs(xc))
+    # the 2D objective counts no z differences
+    d, s1, t2 = fista.objective_terms(g, xc, b, 0.05, 0.3, tv_dims=2)
+    assert t2 == pytest.approx(prox.tv(xc, 2), rel=1e-15) and t2 <= prox.tv3(xc)
+
+
 # --- P14: scale covariance ------------------------------------------------------
 def test_p14_scale_covariance():
     g = small_geom(nx=16, ny=16, nz=4)
@@ -422,6 +569,75 @@ def test_match_nearest_neighbour_within_radius():
     # (0,0,0) takes the closer of its two candidates; (20,0,0) has none within 2
     assert sorted(pairs) == [(0, 2), (1, 0)]
     assert np.allclose(sorted(np.abs(errs).sum(axis=1)), [0.5, 0.5])
+
+
+def test_objects_table_by_hand():
+    """Objects ordered by smallest linear index, with count, intensity sum and
+    weighted centroid; components below the minimum volume are counted among
+    the raw components but dropped."""
+    x = np.zeros((5, 6, 8))
+    x[1, 1, 0:4] = 1.0                    # 4 voxels: dropped
+    x[3, 4, 2:7] = [1, 2, 3, 2, 2]        # 5 voxels, first linear index 3*48 + 4*8 + 2
+    x[0, 5, 6] = 0.5                      # a single voxel: a component of its own, dropped
+    rows, n = detect.objects(x)
+    assert n == 3 and rows.shape == (1, 6)
+    z, y, xc, w, cnt, first = rows[0]
+    assert (cnt, first, w) == (5, 3 * 48 + 4 * 8 + 2, 10.0)
+    assert (z, y) == (3.0, 4.0) and xc == pytest.approx((2 * 1 + 3 * 2 + 4 * 3 + 5 * 2 + 6 * 2) / 10.0, abs=1e-15)
+    # the order follows the smallest linear index, not the size
+    x[0, 3, 0:6] = 1.0                    # 6 voxels at linear index 24..29
+    rows, n = detect.objects(x)
+    assert [r[5] for r in rows] == [24, 3 * 48 + 4 * 8 + 2] and n == 4
+
+
+def test_link_prefers_total_squared_displacement_over_greedy():
+    """Greedy nearest-first linking takes s2-t1 (0.1) and leaves s1 unlinked
+    (cost 0.01 + R^2 = 6.26); the Crocker-Grier minimum links both
+    (1.9^2 + 1.5^2 = 5.86)."""
+    prev = np.array([[0, 0, 0.0], [0, 0, 2.0]])
+    cur = np.array([[0, 0, 1.9], [0, 0, 3.5]])
+    assert detect.link(prev, cur, 2.5).tolist() == [0, 1]
+    # no candidate within the maximum displacement: unlinked
+    assert detect.link(np.array([[0, 0, 0.0]]), np.array([[0, 0, 9.0]]), 2.5).tolist() == [-1]
+    # physical spacing: 1 plane = 10 units, so a one-plane move exceeds 2.5
+    assert detect.link(np.array([[0, 0, 0.0]]), np.array([[1, 0, 0.0]]), 2.5, spacing=(10, 1, 1)).tolist() == [-1]
+    with pytest.raises(ValueError):
+        detect.link(np.zeros((9, 3)), np.zeros((9, 3)), 1.0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_link_cost_equals_assignment_optimum(seed):
+    """The subnetwork search reaches the optimum of the assignment problem
+    with a private 'unlinked' column of cost R^2 per source (solved by
+    scipy's linear_sum_assignment), and when that optimum is unique, the same
+    links."""
+    from scipy.optimize import linear_sum_assignment
+    rng = np.random.default_rng(seed)
+    prev = rng.uniform(0, 20, (30, 3))
+    cur = prev + rng.normal(0, 0.8, (30, 3))
+    cur = np.concatenate([cur[rng.permutation(30)[:26]], rng.uniform(0, 20, (3, 3))])
+    R = 2.0
+    lk = detect.link(prev, cur, R)
+    d2 = ((prev[:, None, :] - cur[None, :, :]) ** 2).sum(-1)
+    big = 1e9
+    cost = np.full((30, 29 + 30), big)
+    cost[:, :29] = np.where(d2 <= R * R, d2, big)
+    cost[np.arange(30), 29 + np.arange(30)] = R * R
+    r, c = linear_sum_assignment(cost)
+    opt = cost[r, c].sum()
+    got = sum(d2[i, j] if j >= 0 else R * R for i, j in enumerate(lk))
+    assert got == pytest.approx(opt, rel=1e-12)
+    assert len(set(j for j in lk if j >= 0)) == sum(1 for j in lk if j >= 0)    # each target once
+    assert all(j < 0 or d2[i, j] <= R * R for i, j in enumerate(lk))
+
+
+def test_track_ids_lengths_and_minimum_duration():
+    f0 = np.array([[0, 0, 0.0], [0, 0, 10.0]])
+    f1 = np.array([[0, 0, 10.5], [0, 0, 0.5], [0, 0, 30.0]])     # both move; a new one appears
+    f2 = np.array([[0, 0, 1.0]])                                   # only the first survives
+    ids, lengths, kept = detect.track([f0, f1, f2], 2.0, min_len=3)
+    assert [a.tolist() for a in ids] == [[0, 1], [1, 0, 2], [0]]
+    assert lengths.tolist() == [3, 2, 1] and kept.tolist() == [True, False, False]
 
 
 # --- P15: particle recovery at C1 (behaviour, not parity) ---------------------
