@@ -407,12 +407,14 @@ def run_compare(args, torch, rihvr, scenes):
 
 
 def run_warmstart(args, torch, rihvr, scenes):
-    """Iterations to gap 1e-4, cold vs learned warm start, on held-out scenes."""
+    """Iterations to gap 1e-4, cold vs learned warm start, on held-out scenes;
+    with --ws-curve, one network per training-set size (the first n of the
+    same pairs), all judged on the same held-out scenes."""
     from paper_1904_04884_amd import warmstart
     cfg = scenes.config_c2()
     g = scenes.geometry_c2().with_(nx=args.ws_size, ny=args.ws_size, nz=args.ws_planes)
     plan = rihvr.Plan(g)
-    ws = warmstart.WarmStart(plan, levels=4, base=16, seed=0)
+    counts = sorted(int(c) for c in args.ws_curve.split(",")) if args.ws_curve else [args.ws_pairs]
 
     def holo(seed):
         n = int(np.random.default_rng(seed).integers(500, 3001) * (g.nx * g.ny * g.nz) / (512 * 512 * 128))
@@ -423,39 +425,62 @@ def run_warmstart(args, torch, rihvr, scenes):
         return (plan.forward(xt) + torch.from_numpy(sc.noise.astype(np.float32)).cuda()).contiguous()
 
     t0 = time.perf_counter()
-    pairs = [ws.make_pair(holo(1000 + i), cfg.l1, cfg.tv, args.ws_pair_iters, cfg.inner_iters)[0]
-             for i in range(args.ws_pairs)]
-    t_pairs = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    curve = ws.train(pairs, steps=args.ws_steps, crop=(32, 64, 64), lr=1e-3, log_every=max(1, args.ws_steps // 5))
+    maker = warmstart.WarmStart(plan, levels=4, base=16, seed=0)
+    pairs = []
+    for i in range(counts[-1]):
+        pairs.append(maker.make_pair(holo(1000 + i), cfg.l1, cfg.tv, args.ws_pair_iters, cfg.inner_iters)[0])
+        if (i + 1) % 64 == 0:
+            log(f"warm start: {i + 1} training pairs ({time.perf_counter() - t0:.0f} s)")
     torch.cuda.synchronize()
-    t_train = time.perf_counter() - t0
-    del pairs
-    cold, warm, used, t_cold, t_warm = [], [], [], 0.0, 0.0
+    t_pairs = time.perf_counter() - t0
+    # held-out scenes: reference objective and cold iterations once
+    held = []
+    t_cold = 0.0
     for i in range(args.ws_eval):
         b = holo(9000 + i)
         f_ref = plan.solve(b, cfg.l1, cfg.tv, 20 * 100, cfg.inner_iters,
                            flags=rihvr.RI_SOLVE_RESTART)[1]["objective_min"]
         torch.cuda.synchronize()
-        t0 = time.perf_counter()
+        t1 = time.perf_counter()
         _, rc, _ = plan.solve(b, cfg.l1, cfg.tv, 2000, cfg.inner_iters, f_ref=f_ref, gap_tol=1e-4, check_every=1)
         torch.cuda.synchronize()
-        t_cold += time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _, rw, u = ws.solve(b, cfg.l1, cfg.tv, 2000, cfg.inner_iters, f_ref=f_ref, gap_tol=1e-4, check_every=1)
+        t_cold += time.perf_counter() - t1
+        held.append((b, f_ref, rc["iters"]))
+    cold = [h[2] for h in held]
+    log(f"held-out cold iterations: {cold}")
+    curve = []
+    for n in counts:
+        ws = warmstart.WarmStart(plan, levels=4, base=16, seed=0)
+        t1 = time.perf_counter()
+        losses = ws.train(pairs[:n], steps=args.ws_steps, crop=(32, 64, 64), lr=1e-3,
+                          log_every=max(1, args.ws_steps // 5))
         torch.cuda.synchronize()
-        t_warm += time.perf_counter() - t0
-        cold.append(rc["iters"])
-        warm.append(rw["iters"])
-        used.append(bool(u))
-        log(f"held-out {i}: cold {rc['iters']} warm {rw['iters']} (proposal used {u})")
+        t_train = time.perf_counter() - t1
+        warm, used, t_warm = [], [], 0.0
+        for b, f_ref, _ in held:
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            _, rw, u = ws.solve(b, cfg.l1, cfg.tv, 2000, cfg.inner_iters, f_ref=f_ref, gap_tol=1e-4, check_every=1)
+            torch.cuda.synchronize()
+            t_warm += time.perf_counter() - t1
+            warm.append(rw["iters"])
+            used.append(bool(u))
+        entry = {"pairs": n, "warm_iters": warm, "proposal_used": used, "train_s": t_train, "loss_curve": losses,
+                 "iters_ratio": float(np.mean(cold) / max(np.mean(warm), 1e-9)),
+                 "cold_holograms_per_s": len(cold) / t_cold, "warm_holograms_per_s": len(warm) / t_warm}
+        log(f"warm start with {n} pairs: iterations {warm} (cold {cold}), "
+            f"{entry['iters_ratio']:.2f}x fewer, {entry['warm_holograms_per_s']:.3f} vs "
+            f"{entry['cold_holograms_per_s']:.3f} holograms/s")
+        curve.append(entry)
     plan.close()
+    last = curve[-1]
     return {
         "metric": "iterations to objective gap 1e-4, cold vs learned warm start",
-        "geometry": [g.nx, g.ny, g.nz], "pairs": args.ws_pairs, "pair_iters": args.ws_pair_iters,
-        "train_steps": args.ws_steps, "loss_curve": curve, "t_pairs_s": t_pairs, "t_train_s": t_train,
-        "cold_iters": cold, "warm_iters": warm, "proposal_used": used,
-        "cold_holograms_per_s": len(cold) / t_cold, "warm_holograms_per_s": len(warm) / t_warm,
+        "geometry": [g.nx, g.ny, g.nz], "pairs": counts[-1], "pair_iters": args.ws_pair_iters,
+        "train_steps": args.ws_steps, "t_pairs_s": t_pairs, "cold_iters": cold,
+        "warm_iters": last["warm_iters"], "proposal_used": last["proposal_used"],
+        "cold_holograms_per_s": last["cold_holograms_per_s"], "warm_holograms_per_s": last["warm_holograms_per_s"],
+        "curve": curve,
     }
 
 
@@ -485,6 +510,8 @@ def main():
     ap.add_argument("--ws-pair-iters", type=int, default=300)
     ap.add_argument("--ws-steps", type=int, default=1500)
     ap.add_argument("--ws-eval", type=int, default=4)
+    ap.add_argument("--ws-curve", type=str, default=None,
+                    help="training-set sizes for a curve of warm-start gain against pair count, e.g. 64,192,512")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch shapes")
     ap.add_argument("--restart", action="store_true",
                     help="timed solves use function-value restart of the momentum (FISTA variant; not the default)")

@@ -112,7 +112,7 @@ Net build_net(int L, int base) {
 // Activation / gradient buffers for one volume size.
 struct Buffers {
   size_t total = 0;
-  size_t packed = 0, in0 = 0, y = 0, gy8 = 0, loss = 0;
+  size_t packed = 0, in0 = 0, y = 0, gy8 = 0, loss = 0, part = 0;
   std::vector<size_t> a, cat, p, idx, da, db, ga, gcat, gda, gdb, gp;
   size_t bbot = 0, gbbot = 0;
 };
@@ -169,6 +169,25 @@ Buffers layout(const Net& n, int D, int H, int W, bool train) {
       }
     }
     B.gbbot = take(nv(L - 1) * n.ch[L - 1] * 2);
+    // partial sums of the gradient reductions: the largest of any layer's
+    // weight (chunks x taps x C x N), bias (chunks x N) and loss (blocks) partials
+    size_t most = 16384;
+    auto chunks = [](long rows, long per) { return (size_t)((rows + per - 1) / per); };
+    for (int l = 0; l < L; ++l) {
+      const long rows = (long)nv(l);
+      const size_t c = n.ch[l], cin = l == 0 ? 1 : n.ch[l - 1];
+      const size_t nw = chunks(rows, wgrad_rows_per_block(rows)), nbias = chunks(rows, bias_rows_per_block(rows));
+      most = std::max(most, nw * 27 * std::max(cin, c) * c);               // encoder a, b
+      most = std::max(most, nbias * 2 * c);
+      if (l < L - 1) {
+        most = std::max(most, nw * 27 * 2 * c * c);                           // decoder a (2c in), b
+        const long crows = (long)nv(l + 1);
+        const size_t nu = chunks(crows, wgrad_rows_per_block(crows));
+        most = std::max(most, nu * 8 * (size_t)n.ch[l + 1] * c);              // up-convolution
+      }
+    }
+    most = std::max(most, chunks((long)nv(0), wgrad_rows_per_block((long)nv(0))) * (size_t)n.ch[0]);   // head
+    B.part = take(most * 4);
   }
   B.total = off;
   return B;
@@ -311,14 +330,14 @@ ri_status backward(const Net& n, const float* params, const float* target, float
   const long nv0 = (long)D * H * W;
   uint16_t* gy8 = at<uint16_t>(ws, B.gy8);
   UTRY(launch_zero_u16(gy8, (size_t)nv0 * 8, s));
-  UTRY(hipMemsetAsync(at<float>(ws, B.loss), 0, sizeof(float), s));
-  UTRY(launch_mse(at<float>(ws, B.y), target, nv0, pos_weight, gy8, 8, at<float>(ws, B.loss), s));
+  float* part = at<float>(ws, B.part);
+  UTRY(launch_mse(at<float>(ws, B.y), target, nv0, pos_weight, gy8, 8, at<float>(ws, B.loss), part, s));
   // head
   const Layer& hd = n.layers[n.head()];
   const uint16_t* top = L > 1 ? at<uint16_t>(ws, B.db[0]) : at<uint16_t>(ws, B.bbot);
   uint16_t* gtop = L > 1 ? at<uint16_t>(ws, B.gdb[0]) : at<uint16_t>(ws, B.gbbot);
-  UTRY(launch_wgrad(wg(GG_POINT, D, H, W, gy8, 8, 0, 1, top, n.ch[0], 0, n.ch[0], grads + hd.w), 1, s));
-  UTRY(launch_bias_grad(gy8, 8, 0, 1, nv0, grads + hd.b, s));
+  UTRY(launch_wgrad(wg(GG_POINT, D, H, W, gy8, 8, 0, 1, top, n.ch[0], 0, n.ch[0], grads + hd.w), 1, part, s));
+  UTRY(launch_bias_grad(gy8, 8, 0, 1, nv0, grads + hd.b, part, s));
   UTRY(launch_gather_gemm(gemm(GG_POINT, D, H, W, gy8, 8, 0, 1, hd.b_c, pk + hd.pb, n.ch[0], hd.b_npad, nullptr, 0,
                                gtop, n.ch[0], 0), s));
   // decoder, finest level first
@@ -335,20 +354,20 @@ ri_status backward(const Net& n, const float* params, const float* target, float
     const uint16_t* dao = at<uint16_t>(ws, B.da[l]);
     const uint16_t* cat = at<uint16_t>(ws, B.cat[l]);
     UTRY(launch_relu_mask(gdb, c, 0, dbo, c, 0, c, nvl, s));
-    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gdb, c, 0, c, dao, c, 0, c, grads + db.w), 27, s));
-    UTRY(launch_bias_grad(gdb, c, 0, c, nvl, grads + db.b, s));
+    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gdb, c, 0, c, dao, c, 0, c, grads + db.w), 27, part, s));
+    UTRY(launch_bias_grad(gdb, c, 0, c, nvl, grads + db.b, part, s));
     UTRY(launch_gather_gemm(gemm(GG_CONV3_BWD, Dl, Hl, Wl, gdb, c, 0, 27, db.b_c, pk + db.pb, c, db.b_npad, nullptr,
                                  0, gda, c, 0), s));
     UTRY(launch_relu_mask(gda, c, 0, dao, c, 0, c, nvl, s));
-    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gda, c, 0, c, cat, 2 * c, 0, 2 * c, grads + da.w), 27, s));
-    UTRY(launch_bias_grad(gda, c, 0, c, nvl, grads + da.b, s));
+    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gda, c, 0, c, cat, 2 * c, 0, 2 * c, grads + da.w), 27, part, s));
+    UTRY(launch_bias_grad(gda, c, 0, c, nvl, grads + da.b, part, s));
     UTRY(launch_gather_gemm(gemm(GG_CONV3_BWD, Dl, Hl, Wl, gda, c, 0, 27, da.b_c, pk + da.pb, 2 * c, da.b_npad,
                                  nullptr, 0, gcat, 2 * c, 0), s));
     // up-convolution: gradient rows at the fine level, parameters over coarse rows
     const uint16_t* hin = (l + 1 == L - 1) ? at<uint16_t>(ws, B.bbot) : at<uint16_t>(ws, B.db[l + 1]);
     uint16_t* ghin = (l + 1 == L - 1) ? at<uint16_t>(ws, B.gbbot) : at<uint16_t>(ws, B.gdb[l + 1]);
-    UTRY(launch_wgrad(wg(GG_UP_FWD, Dl / 2, Hl / 2, Wl / 2, gcat, 2 * c, 0, c, hin, cu, 0, cu, grads + up.w), 8, s));
-    UTRY(launch_bias_grad(gcat, 2 * c, 0, c, nvl, grads + up.b, s));
+    UTRY(launch_wgrad(wg(GG_UP_FWD, Dl / 2, Hl / 2, Wl / 2, gcat, 2 * c, 0, c, hin, cu, 0, cu, grads + up.w), 8, part, s));
+    UTRY(launch_bias_grad(gcat, 2 * c, 0, c, nvl, grads + up.b, part, s));
     UTRY(launch_gather_gemm(gemm(GG_UP_BWD, Dl / 2, Hl / 2, Wl / 2, gcat, 2 * c, 0, 8, up.b_c, pk + up.pb, cu,
                                  up.b_npad, nullptr, 0, ghin, cu, 0), s));
   }
@@ -367,15 +386,15 @@ ri_status backward(const Net& n, const float* params, const float* target, float
     UTRY(launch_relu_mask(gout, ocs, oc0, out, ocs, oc0, c, nvl, s));
     const uint16_t* a = at<uint16_t>(ws, B.a[l]);
     uint16_t* ga = at<uint16_t>(ws, B.ga[l]);
-    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gout, ocs, oc0, c, a, c, 0, c, grads + eb.w), 27, s));
-    UTRY(launch_bias_grad(gout, ocs, oc0, c, nvl, grads + eb.b, s));
+    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, gout, ocs, oc0, c, a, c, 0, c, grads + eb.w), 27, part, s));
+    UTRY(launch_bias_grad(gout, ocs, oc0, c, nvl, grads + eb.b, part, s));
     UTRY(launch_gather_gemm(gemm(GG_CONV3_BWD, Dl, Hl, Wl, gout, ocs, oc0, 27, eb.b_c, pk + eb.pb, c, eb.b_npad,
                                  nullptr, 0, ga, c, 0), s));
     UTRY(launch_relu_mask(ga, c, 0, a, c, 0, c, nvl, s));
     const uint16_t* src = l == 0 ? at<uint16_t>(ws, B.in0) : at<uint16_t>(ws, B.p[l - 1]);
     const int scs = l == 0 ? 8 : n.ch[l - 1], cin = l == 0 ? 1 : n.ch[l - 1];
-    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, ga, c, 0, c, src, scs, 0, cin, grads + ea.w), 27, s));
-    UTRY(launch_bias_grad(ga, c, 0, c, nvl, grads + ea.b, s));
+    UTRY(launch_wgrad(wg(GG_CONV3_FWD, Dl, Hl, Wl, ga, c, 0, c, src, scs, 0, cin, grads + ea.w), 27, part, s));
+    UTRY(launch_bias_grad(ga, c, 0, c, nvl, grads + ea.b, part, s));
     if (l > 0)
       UTRY(launch_gather_gemm(gemm(GG_CONV3_BWD, Dl, Hl, Wl, ga, c, 0, 27, ea.b_c, pk + ea.pb, cin, ea.b_npad,
                                    nullptr, 0, at<uint16_t>(ws, B.gp[l - 1]), cin, 0), s));

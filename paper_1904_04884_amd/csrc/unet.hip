@@ -443,21 +443,32 @@ __global__ void __launch_bounds__(256) k_wgrad(WgradArgs a) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int n = ni * 16 + (lane >> 4) * 4 + q;
-      if (n < a.N && c < a.C) atomicAdd(&a.dw[((size_t)t * a.C + c) * a.N + n], acc[i][q]);
+      // this block's partial (row chunk blockIdx.x); summed in chunk order by k_sum_partials
+      if (n < a.N && c < a.C)
+        a.part[(size_t)blockIdx.x * a.taps * a.C * a.N + ((size_t)t * a.C + c) * a.N + n] = acc[i][q];
     }
   }
 }
 
-// bias gradient: db[n] += sum_r g[r][n]
+// bias gradient: partial sums of g[r][n] over a chunk of rows per block
 __global__ void __launch_bounds__(256) k_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows,
-                                                   long rows_per_block, int up_fine, float* db) {
+                                                   long rows_per_block, float* part) {
   const long r0 = (long)blockIdx.x * rows_per_block, r1 = min(nrows, r0 + rows_per_block);
   for (int n = threadIdx.x; n < N; n += 256) {
     float s = 0.f;
     for (long r = r0; r < r1; ++r) s += bf2f(g[(size_t)r * cs + c0 + n]);
-    atomicAdd(&db[n], s);
+    part[(size_t)blockIdx.x * N + n] = s;
   }
-  (void)up_fine;
+}
+
+// out[e] += sum over b of part[b * count + e], b in order: partial sums of
+// row chunks reduced the same way on every run (no floating-point atomics).
+__global__ void k_sum_partials(const float* __restrict__ part, int nb, size_t count, float* out) {
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count; e += (size_t)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int b = 0; b < nb; ++b) s += part[(size_t)b * count + e];
+    out[e] += s;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -533,7 +544,7 @@ __global__ void k_mse(const float* y, const float* t, long n, float inv_n, float
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
   __syncthreads();
-  if (threadIdx.x == 0) atomicAdd(loss, (red[0] + red[1] + red[2] + red[3]) * inv_n);
+  if (threadIdx.x == 0) loss[blockIdx.x] = (red[0] + red[1] + red[2] + red[3]) * inv_n;   // per-block partial
 }
 
 // Adam on FP32 master weights
@@ -584,6 +595,10 @@ __global__ void k_pack_up_fwd(const float* u, int cin, int cout, uint16_t* out) 
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
+__global__ void k_fill_f32_one(float* p) {
+  if (threadIdx.x == 0) *p = 0.f;
+}
+
 static int ew_grid(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b > 16384 ? 16384 : (b == 0 ? 1 : b));
@@ -653,19 +668,29 @@ hipError_t launch_gather_gemm(const GatherGemmArgs& a, hipStream_t s) {
   }
 }
 
-hipError_t launch_wgrad(const WgradArgs& a, int taps, hipStream_t s) {
+long wgrad_rows_per_block(long nrows) { return std::max<long>(2048, (nrows + kReduceBlocks - 1) / kReduceBlocks); }
+long bias_rows_per_block(long nrows) { return std::max<long>(4096, (nrows + kReduceBlocks - 1) / kReduceBlocks); }
+
+hipError_t launch_wgrad(WgradArgs a, int taps, float* part, hipStream_t s) {
   if (a.Npad > kWgMaxN || a.Cpad > kWgMaxC || a.Npad % 16 || a.Cpad % 16) return hipErrorInvalidValue;
   const long nrows = (long)a.D * a.H * a.W;
+  a.rows_per_block = wgrad_rows_per_block(nrows);
+  a.taps = taps;
+  a.part = part;
   const int nb = (int)((nrows + a.rows_per_block - 1) / a.rows_per_block);
   const int groups = ((a.Npad / 16) * (a.Cpad / 16) + 15) / 16;
   hipLaunchKernelGGL(k_wgrad, dim3(nb, taps, groups), dim3(256), 0, s, a);
+  const size_t count = (size_t)taps * a.C * a.N;
+  hipLaunchKernelGGL(k_sum_partials, dim3(ew_grid(count)), dim3(256), 0, s, part, nb, count, a.dw);
   return hipGetLastError();
 }
 
-hipError_t launch_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows, float* db, hipStream_t s) {
-  const long per = 4096;
+hipError_t launch_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows, float* db, float* part,
+                            hipStream_t s) {
+  const long per = bias_rows_per_block(nrows);
   const int nb = (int)((nrows + per - 1) / per);
-  hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, s, g, cs, c0, N, nrows, per, 0, db);
+  hipLaunchKernelGGL(k_bias_grad, dim3(nb), dim3(256), 0, s, g, cs, c0, N, nrows, per, part);
+  hipLaunchKernelGGL(k_sum_partials, dim3(ew_grid((size_t)N)), dim3(256), 0, s, part, nb, (size_t)N, db);
   return hipGetLastError();
 }
 
@@ -701,8 +726,12 @@ hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long 
 }
 
 hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint16_t* g, int gcs, float* loss,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_mse, dim3(ew_grid(n)), dim3(256), 0, s, y, t, n, 1.f / (float)n, pos_w, g, gcs, loss);
+                      float* part, hipStream_t s) {
+  // per-block partials in part (ew_grid(n) <= kLossBlocks of them), then one ordered sum
+  const int nb = ew_grid(n);
+  hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, y, t, n, 1.f / (float)n, pos_w, g, gcs, part);
+  hipLaunchKernelGGL(k_fill_f32_one, dim3(1), dim3(64), 0, s, loss);
+  hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, part, nb, (size_t)1, loss);
   return hipGetLastError();
 }
 

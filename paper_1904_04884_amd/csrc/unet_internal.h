@@ -40,10 +40,20 @@ struct WgradArgs {
   const uint16_t* s;       // layer input, channel view
   int s_cs, s_c0, C, Cpad;
   float* dw;               // FP32 [t][C][N], accumulated
-  long rows_per_block;
+  long rows_per_block;     // set by launch_wgrad
+  int taps;                // set by launch_wgrad
+  float* part;             // per-row-chunk partials [chunk][t][C][N] (set by launch_wgrad)
 };
-hipError_t launch_wgrad(const WgradArgs& a, int taps, hipStream_t s);
-hipError_t launch_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows, float* db, hipStream_t s);
+// Weight and bias gradients are reduced without floating-point atomics: each
+// block writes the partial sum of its chunk of rows (at most kReduceBlocks
+// chunks) to `part`, and one ordered pass adds the chunks, so a training step
+// gives the same bits on every run.
+constexpr long kReduceBlocks = 256;
+long wgrad_rows_per_block(long nrows);
+long bias_rows_per_block(long nrows);
+hipError_t launch_wgrad(WgradArgs a, int taps, float* part, hipStream_t s);
+hipError_t launch_bias_grad(const uint16_t* g, int cs, int c0, int N, long nrows, float* db, float* part,
+                            hipStream_t s);
 
 hipError_t launch_pool_fwd(const uint16_t* x, int xcs, int xc0, uint16_t* y, int ycs, uint8_t* idx, int C, int D,
                            int H, int W, hipStream_t s);
@@ -54,7 +64,7 @@ hipError_t launch_relu_mask(uint16_t* g, int gcs, int gc0, const uint16_t* y, in
 hipError_t launch_zero_u16(uint16_t* p, size_t n, hipStream_t s);
 hipError_t launch_input(const float* in, float scale, uint16_t* x, int cs, long nvox, hipStream_t s);
 hipError_t launch_mse(const float* y, const float* t, long n, float pos_w, uint16_t* g, int gcs, float* loss,
-                      hipStream_t s);
+                      float* part, hipStream_t s);   // part: one float per block (<= 16384)
 hipError_t launch_adam(float* w, const float* g, float* m, float* v, size_t n, float lr, double b1, double b2,
                        double eps, int step, hipStream_t s);
 hipError_t launch_pack(const float* w, int T, int cin, int cout, int transpose, int Npad, int Cpad, uint16_t* out,

@@ -84,9 +84,12 @@ class WarmStart:
         torch = self.torch
         g = torch.Generator().manual_seed(seed)
         m = 1 << (self.levels - 1)
-        inputs = [self.network_input(p.b, p.plan) for p in pairs]
         if self.scale is None:
-            ms = sum(float((t.double() ** 2).mean()) for t in inputs) / len(inputs)
+            # normalisation from (at most) 32 pairs; network inputs are formed
+            # per step from the pair's hologram (A^T b by the library), so the
+            # training set holds holograms and targets only
+            sample = pairs[:32]
+            ms = sum(float((self.network_input(p.b, p.plan).double() ** 2).mean()) for p in sample) / len(sample)
             self.scale = 1.0 / math.sqrt(max(ms, 1e-300))
             self.t_scale = 1.0 / max(max(float(p.target.max()) for p in pairs), 1e-30)
         if pos_weight is None:
@@ -97,12 +100,13 @@ class WarmStart:
         losses = []
         for it in range(steps):
             k = int(torch.randint(len(pairs), (1,), generator=g))
-            nz, ny, nx = inputs[k].shape
+            inp = self.network_input(pairs[k].b, pairs[k].plan)
+            nz, ny, nx = inp.shape
             cz, cy, cx = (min(c, n) // m * m for c, n in zip(crop, (nz, ny, nx)))
             z0 = int(torch.randint(nz - cz + 1, (1,), generator=g))
             y0 = int(torch.randint(ny - cy + 1, (1,), generator=g))
             x0 = int(torch.randint(nx - cx + 1, (1,), generator=g))
-            xi = inputs[k][z0:z0 + cz, y0:y0 + cy, x0:x0 + cx].contiguous()
+            xi = inp[z0:z0 + cz, y0:y0 + cy, x0:x0 + cx].contiguous()
             ti = (pairs[k].target[z0:z0 + cz, y0:y0 + cy, x0:x0 + cx] * self.t_scale).contiguous()
             loss = self.net.train_step(xi, ti, lr=lr, scale=self.scale, pos_weight=pos_weight)
             if log_every and (it % log_every == 0 or it == steps - 1):
