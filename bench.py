@@ -517,6 +517,8 @@ def main():
                     help="timed solves use function-value restart of the momentum (FISTA variant; not the default)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="fixed launch shapes tv_levels,tv_blocks,col_blocks (no autotuning; for profiling)")
+    ap.add_argument("--no-row-store", dest="row_store", action="store_false",
+                    help="skip the row-store leg (the same solve with row-compressed iterates)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy (for scaling FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
@@ -638,6 +640,35 @@ def main():
                  "flags": "RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH, cold start"}
         log(f"plain FISTA: {1.0 / dtp:.4f} holograms/s ({rep_p['iters']} iterations); "
             f"headline / plain = {value * dtp:.3f}")
+    row_store = None
+    if args.row_store:
+        # the same solve with x_k, x_{k-1}, x_{k+1} in row stores: a first
+        # solve with room for every row gives the peak occupancy; the timed
+        # solve uses pools of exactly that many rows
+        dense_ws = rihvr.ri_workspace_size_op(plan.handle, rihvr.RI_OP_SOLVE)
+        rows = g.ny * g.nz
+
+        def store_solve():
+            return plan.solve(b, cfg.l1, cfg.tv, args.max_iters, cfg.inner_iters, f_ref=f_ref, gap_tol=args.gap,
+                              check_every=args.check_every, raise_on_error=False)
+        plan.row_fraction = 1.0
+        _, rep_1, _ = store_solve()
+        peak = rep_1["store_rows_peak"]
+        plan.row_fraction = peak / rows
+        store_ws = rihvr.ri_workspace_size_op(plan.handle, rihvr.RI_OP_SOLVE)
+        store_solve()                         # captures the graph for this layout
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        _, rep_s, st_s = store_solve()
+        torch.cuda.synchronize()
+        dts = time.perf_counter() - t1
+        plan.row_fraction = 0.0
+        row_store = {"peak_rows": peak, "rows": rows, "row_fraction": peak / rows,
+                     "status": rihvr.ri_status_string(st_s), "holograms_per_s": 1.0 / dts, "iters": rep_s["iters"],
+                     "solve_workspace_bytes": store_ws, "dense_solve_workspace_bytes": dense_ws,
+                     "value_over_row_store": value * dts}
+        log(f"row stores: peak {peak} of {rows} rows; {1.0 / dts:.4f} holograms/s, {rep_s['iters']} iterations, "
+            f"status {row_store['status']}; solve workspace {store_ws / 2**30:.2f} GiB vs {dense_ws / 2**30:.2f} GiB")
     fft = fft_rates(torch, plan, g)
     log("FFT: " + ", ".join(f"{k} {v['tflops']:.2f} TFLOP/s ({v['ms']:.3f} ms)"
                             for k, v in fft.items() if isinstance(v, dict)))
@@ -682,6 +713,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "plain_fista": plain,
+        "row_store": row_store,
         "fft": fft,
         "copy_bandwidth": copy_bw,
     }

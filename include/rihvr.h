@@ -132,6 +132,8 @@ typedef struct {
   double empty_row_frac;    /* of the returned iterate */
   double phase_ms[RI_NUM_PHASES]; /* with RI_SOLVE_TIMING: device time per phase */
   int32_t phase_launches[RI_NUM_PHASES];
+  int32_t store_rows_peak;  /* row stores: most occupied rows of any iterate (also
+                               when a pool ran out); 0 with dense iterates */
 } ri_solve_report;
 
 typedef struct ri_plan ri_plan;
@@ -183,6 +185,30 @@ ri_status ri_workspace_size_op(const ri_plan* plan, ri_op op, size_t* bytes);
  */
 ri_status ri_plan_get_tuning(const ri_plan* plan, ri_tuning* out);
 ri_status ri_plan_set_tuning(ri_plan* plan, const ri_tuning* tuning);
+
+/*
+ * Storage of the solver's iterates (section "Methodology", the paragraph on
+ * storing the sparse particle volume; the paper keeps x_k as coordinate lists
+ * per plane).  row_fraction = 0 (the default): x_k, x_{k-1} and x_{k+1} are
+ * dense volumes (two in the workspace, one in x_inout).  row_fraction in
+ * (0, 1]: the iterates live in two row stores (x_k in one; x_{k-1} in the
+ * other until the gradient step has read it, then x_{k+1}), each a pool of
+ * max(1, ceil(row_fraction * ny * nz - 1e-6)) rows of nx FP32 values plus a table of
+ * ny * nz int32 slots (-1: the row is all zero), and x_inout holds the dense
+ * gradient-step output during the solve.  The workspace of RI_OP_SOLVE (and of
+ * ri_workspace_size_batched) then holds 2 * row_fraction volumes of iterates
+ * instead of 2.  A row takes a pool row exactly when it holds a non-zero value,
+ * so a fraction at least that of the occupied rows of every iterate (and of a
+ * given x_0) always fits; the report's store_rows_peak gives that count.  Results are bit-identical to the dense storage.  An
+ * iterate with more occupied rows than a pool holds stops the solve with status
+ * RI_ERR_WORKSPACE_TOO_SMALL (returned by ri_solve when a report is requested;
+ * x_inout then holds no valid result).  Not available with RI_TV_DUAL_BF16
+ * plans (RI_ERR_INVALID_ARG from ri_solve).  ri_forward, ri_adjoint, ri_prox
+ * and ri_plan_autotune are unaffected.  Drops the plan's cached solve graph.
+ * RI_ERR_INVALID_ARG for a fraction outside [0, 1] or NaN.
+ */
+ri_status ri_plan_set_storage(ri_plan* plan, double row_fraction);
+ri_status ri_plan_get_storage(const ri_plan* plan, double* row_fraction);
 
 typedef struct {
   ri_tuning best;           /* the tuning now set on the plan */

@@ -49,7 +49,7 @@ def objective(geom, x, b, l1, tv, tv_dims=3) -> float:
 
 def fista(geom, b, l1, tv, n_outer, n_inner, x0=None, step=None, nonneg=True,
           restart=False, history=False, tv_dims=3, dual_warm=False, fgp=False, dual_store=None,
-          dual_store_every=1):
+          dual_store_every=1, on_iterate=None):
     b = np.asarray(b, dtype=np.float64)
     t = 1.0 / optics.lipschitz(geom) if step is None else float(step)
     x = np.zeros((geom.nz, geom.ny, geom.nx)) if x0 is None else np.array(x0, dtype=np.float64)
@@ -76,4 +76,6 @@ def fista(geom, b, l1, tv, n_outer, n_inner, x0=None, step=None, nonneg=True,
             f_prev = f
         y = x_new + beta * (x_new - x)
         x, s = x_new, s_new
+        if on_iterate is not None:
+            on_iterate(x)   # observer of each new iterate (tests); changes nothing
     return (x, f_hist) if history else x

@@ -71,6 +71,7 @@ struct GraphCache {
   const void* x = nullptr;
   double step = 0, l1 = 0, tv = 0;
   int inner = -1, dense = -1, nonneg = -1, warm = -1;
+  double store_frac = -1.0;
 };
 
 struct ri_plan {
@@ -87,6 +88,7 @@ struct ri_plan {
   hipStream_t capture = nullptr;
   GraphCache gc;
   ri_tuning tune{kTvDefaultLevels, kTvDefaultBlocks, kColDefaultBlocks};
+  double store_frac = 0.0;   // > 0: row-compressed iterates with room for this fraction of rows
   PlanTables tables() const { return PlanTables{theta, zc, tw_row, tw_col}; }
 };
 
@@ -243,6 +245,8 @@ struct Layout {
   size_t vol1 = 0, vol2 = 0, pa[3] = {0, 0, 0}, pb[3] = {0, 0, 0};  // volumes (float; duals float or bf16)
   size_t pa2[3] = {0, 0, 0}, pb2[3] = {0, 0, 0};                   // FGP: second dual of each set
   size_t stage = 0;                                                 // in-place prox with bf16 duals
+  size_t pool[2] = {0, 0}, slot[2] = {0, 0}, count = 0, overflow = 0;   // row-compressed iterates
+  uint32_t cap = 0;                                                 // pool rows per store (0: dense)
   size_t spec = 0, gp = 0, gi = 0, th = 0;                 // spectra (float2)
   size_t ax0 = 0, ax1 = 0;                                 // holograms (float)
   size_t rowflag = 0, planeflag = 0, rowflag_prev = 0;     // bytes
@@ -271,8 +275,16 @@ static void chunking(const ri_plan* p, int col_blocks, int* nchunk, int* ppc) {
   *nchunk = (p->g.nz + per - 1) / per;
 }
 
-static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
-  if (op == RI_OP_AUTOTUNE) return make_layout(p, RI_OP_SOLVE, kColTuneMax);  // room for every candidate
+// Pool rows of a row store: the requested fraction of the volume's rows (a
+// row is allocated once, by the first segment that holds a non-zero value);
+// a fraction k / rows gives exactly k rows despite its rounding.
+static uint32_t store_cap(const ri_plan* p) {
+  const double rows = (double)p->g.ny * p->g.nz;
+  return (uint32_t)std::max(1.0, std::min(rows, std::ceil(p->store_frac * rows - 1e-6)));
+}
+
+static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0, bool dense_iterates = false) {
+  if (op == RI_OP_AUTOTUNE) return make_layout(p, RI_OP_SOLVE, kColTuneMax, true);  // room for every candidate
   Layout L;
   const size_t nx = p->g.nx, ny = p->g.ny, nz = p->g.nz, m = p->m;
   const size_t vol = nx * ny * nz * sizeof(float);
@@ -315,8 +327,18 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0) {
     if (op == RI_OP_PROX && (p->g.flags & RI_TV_DUAL_BF16)) L.stage = take(vol);
   }
   if (op == RI_OP_SOLVE) {
-    L.vol1 = take(vol);
-    L.vol2 = take(vol);
+    if (p->store_frac > 0.0 && !dense_iterates) {
+      // x_k, x_{k-1}, x_{k+1} in row stores; the caller's x_inout holds the
+      // dense gradient-step output v during the solve
+      L.cap = store_cap(p);
+      for (int k = 0; k < 2; ++k) L.pool[k] = take((size_t)L.cap * nx * sizeof(float));
+      for (int k = 0; k < 2; ++k) L.slot[k] = take(ny * nz * sizeof(int32_t));
+      L.count = take(2 * sizeof(uint32_t));
+      L.overflow = take(sizeof(uint32_t));
+    } else {
+      L.vol1 = take(vol);
+      L.vol2 = take(vol);
+    }
     L.ax0 = take(nx * ny * sizeof(float));
     L.ax1 = take(nx * ny * sizeof(float));
     L.rowflag = take(ny * nz);
@@ -620,7 +642,24 @@ struct SolveCtx {
   bool dense;
   int nonneg;
   bool warm;     // the TV dual carries over from one outer iteration to the next
+  RowStores rs;  // row-compressed iterates (rs.on) or none
 };
+
+static RowStores row_stores(const ri_plan* p, const Layout& L, void* ws, float* x_inout) {
+  RowStores rs{};
+  if (L.cap == 0) return rs;
+  for (int k = 0; k < 2; ++k) {
+    rs.pool[k] = at<float>(ws, L.pool[k]);
+    rs.slot[k] = at<int32_t>(ws, L.slot[k]);
+  }
+  rs.count = at<uint32_t>(ws, L.count);
+  rs.overflow = at<uint32_t>(ws, L.overflow);
+  rs.cap = L.cap;
+  rs.nx = p->g.nx;
+  rs.v = x_inout;
+  rs.on = 1;
+  return rs;
+}
 
 struct PhaseTimer {
   bool on = false;
@@ -689,6 +728,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   oa.ptv = at<double>(c.ws, L.ptv);
   oa.first_only = 1;
   oa.tv2 = (p->g.flags & RI_TV2D) ? 1 : 0;
+  oa.rs = c.rs;
   oa.st = c.st;
   // A x_it (skipping empty rows and planes unless dense)
   RowsR2CArgs& ra = I.fwd_rows;
@@ -698,6 +738,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   ra.rowflag = c.dense ? nullptr : rowflag;
   ra.st = c.st;
   ra.mode = 2;
+  ra.rs = c.rs;
   ra.pt = pt;
   FwdColsArgs& fa = I.fwd_cols;
   fa.t = at<float2>(c.ws, L.spec);
@@ -737,6 +778,8 @@ static IterArgs iteration_args(const SolveCtx& c) {
   sa.qtv = at<double>(c.ws, L.qtv);
   sa.n_prox = tv_final_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks, p->cus);
   sa.hist = at<double>(c.ws, L.hist);
+  sa.overflow = c.rs.on ? c.rs.overflow : nullptr;
+  sa.count = c.rs.on ? c.rs.count : nullptr;
   RowsR2CArgs& rr = I.resid;
   rr.ax0 = at<float>(c.ws, L.ax0);
   rr.ax1 = at<float>(c.ws, L.ax1);
@@ -767,6 +810,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   ar.step = c.step;
   ar.mode = 1;
   ar.scale = scale;
+  ar.rs = c.rs;
   ar.pt = pt;
   // fused-lasso prox -> x_{it+1}, occupancy flags
   ProxArgs& pa = I.prox;
@@ -786,6 +830,8 @@ static IterArgs iteration_args(const SolveCtx& c) {
   pa.levels = p->tune.tv_levels;
   pa.warm = c.warm ? 1 : 0;
   pa.blocks = p->tune.tv_blocks;
+  pa.rs = c.rs;
+  if (c.rs.on) pa.v = c.rs.v;   // v is the dense gradient-step output; x_{k+1} goes to a row store
   return I;
 }
 
@@ -819,6 +865,7 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   if (tm) tm->end(2);
   if (tm) tm->begin(PH_PROX);
   int nl = 0;
+  if (c.rs.on) LTRY(launch_store_clear_next(c.rs, ny, p->g.nz, c.st, s));
   LTRY(launch_prox(I.prox, s, &nl));
   if (tm) tm->end(nl);
 #undef LTRY
@@ -844,6 +891,8 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
     return fail(RI_ERR_INVALID_ARG, "unknown solve flags 0x%x", sp->flags);
   if ((sp->flags & RI_SOLVE_DUAL_WARM) && (p->g.flags & RI_TV_FGP))
     return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_TV_FGP plans");
+  if (p->store_frac > 0.0 && (p->g.flags & RI_TV_DUAL_BF16))
+    return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_TV_DUAL_BF16 plans");
   return RI_OK;
 }
 
@@ -869,13 +918,19 @@ static hipError_t enqueue_setup(const SolveCtx& c, const ri_solve_params* sp, hi
   if ((e = launch_fill_u8(at<uint8_t>(c.ws, c.L.rowflag_prev), (size_t)p->g.ny * p->g.nz, 1, s)) != hipSuccess)
     return e;
   if (sp->init == RI_INIT_ZERO) {
-    if ((e = launch_fill_f32(c.vol[0], nvox, 0.f, s)) != hipSuccess) return e;
+    if (!c.rs.on && (e = launch_fill_f32(c.vol[0], nvox, 0.f, s)) != hipSuccess) return e;
   } else {
     if (sp->x0_scale != 0.0 && sp->x0_scale != 1.0)
       if ((e = launch_scale_f32(c.vol[0], nvox, (float)sp->x0_scale, s)) != hipSuccess) return e;
     if ((e = launch_flags_from_x(c.vol[0], p->g.nx, p->g.ny, p->g.nz, rowflag, planeflag, s)) != hipSuccess) return e;
   }
-  if ((e = launch_copy_f32(c.vol[2], c.vol[0], nvox, s)) != hipSuccess) return e;
+  if (c.rs.on) {
+    // x_0 and x_{-1} into row stores 0 and 1 (all rows absent for a cold start)
+    const float* x0 = sp->init == RI_INIT_ZERO ? nullptr : c.vol[0];
+    if ((e = launch_store_start(c.rs, x0, p->g.ny, p->g.nz, s)) != hipSuccess) return e;
+  } else {
+    if ((e = launch_copy_f32(c.vol[2], c.vol[0], nvox, s)) != hipSuccess) return e;
+  }
   if (c.warm) {
     // the first prox starts its dual from zero; it reads the first dual set
     const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
@@ -885,6 +940,14 @@ static hipError_t enqueue_setup(const SolveCtx& c, const ri_solve_params* sp, hi
   }
   if ((e = launch_fill_f32(at<float>(c.ws, c.L.ax0), npix, 0.f, s)) != hipSuccess) return e;
   return launch_fill_f32(at<float>(c.ws, c.L.ax1), npix, 0.f, s);
+}
+
+// The final iterate into the caller's volume (from its row store, or from the
+// rotating slot it ended in).
+static hipError_t copy_out(const SolveCtx& c, float* x_out, hipStream_t s) {
+  const ri_plan* p = c.p;
+  if (c.rs.on) return launch_store_expand(c.rs, x_out, p->g.ny, p->g.nz, c.st, s);
+  return launch_copy_final(c.vol[0], c.vol[1], c.vol[2], x_out, (size_t)p->g.nx * p->g.ny * p->g.nz, c.st, s);
 }
 
 static ri_status read_state(const SolveCtx& c, hipStream_t s, SolveState* out) {
@@ -897,7 +960,7 @@ static ri_status get_graph(ri_plan* p, const SolveCtx& c, hipGraphExec_t* exec) 
   GraphCache& g = p->gc;
   if (g.exec && g.ws == c.ws && g.b == c.b && g.x == c.vol[0] && g.step == c.step && g.l1 == c.l1 &&
       g.tv == c.tv && g.inner == c.inner && g.dense == (int)c.dense && g.nonneg == c.nonneg &&
-      g.warm == (int)c.warm) {
+      g.warm == (int)c.warm && g.store_frac == c.p->store_frac) {
     *exec = g.exec;
     return RI_OK;
   }
@@ -916,6 +979,7 @@ static ri_status get_graph(ri_plan* p, const SolveCtx& c, hipGraphExec_t* exec) 
   g.exec = ex;
   g.ws = c.ws; g.b = c.b; g.x = c.vol[0]; g.step = c.step; g.l1 = c.l1; g.tv = c.tv;
   g.inner = c.inner; g.dense = (int)c.dense; g.nonneg = c.nonneg; g.warm = (int)c.warm;
+  g.store_frac = c.p->store_frac;
   *exec = ex;
   return RI_OK;
 }
@@ -945,6 +1009,7 @@ static ri_status fill_report(const SolveCtx& c, hipStream_t s, ri_solve_report* 
   rep->lipschitz = p->lipschitz;
   rep->empty_row_frac = (double)er / (double)rf.size();
   rep->empty_plane_frac = (double)ep / (double)pf.size();
+  rep->store_rows_peak = h.rows_peak;
   if (tm) tm->collect(rep->phase_ms, rep->phase_launches);
   return (ri_status)h.status;
 }
@@ -962,8 +1027,9 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const void*
   c.ws = ws;
   c.b = b;
   c.vol[0] = x_inout;
-  c.vol[1] = at<float>(ws, c.L.vol1);
-  c.vol[2] = at<float>(ws, c.L.vol2);
+  c.vol[1] = c.L.cap ? nullptr : at<float>(ws, c.L.vol1);
+  c.vol[2] = c.L.cap ? nullptr : at<float>(ws, c.L.vol2);   // row stores replace slot 2
+  c.rs = row_stores(p, c.L, ws, x_inout);
   c.st = at<SolveState>(ws, c.L.state);
   c.step = 1.0 / p->lipschitz;
   c.l1 = sp->l1;
@@ -1003,7 +1069,7 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const void*
     }
   }
   if (timing) tm.begin(PH_OTHER);
-  HIP_TRY(launch_copy_final(c.vol[0], c.vol[1], c.vol[2], x_inout, (size_t)p->g.nx * p->g.ny * p->g.nz, c.st, s));
+  HIP_TRY(copy_out(c, x_inout, s));
   if (timing) tm.end(1);
   if (!report) return RI_OK;
   return fill_report(c, s, report, timing ? &tm : nullptr);
@@ -1028,6 +1094,7 @@ struct BatchLaunch {
   bool tv2 = false;         // TV: per-plane 2D TV frames
   bool fgp = false;         // TV: accelerated-dual frames
   bool bf16 = false;        // TV: bfloat16-dual frames
+  bool sparse = false;      // TV: frames with row-compressed iterates
   std::vector<int> frames;
   size_t args_off = 0, offs_off = 0;
   int nblocks = 0;
@@ -1089,7 +1156,7 @@ static std::vector<BatchLaunch> batch_launches(int n, ri_plan* const* plans, con
   for (int p = 0; p < maxpass; ++p) {
     for (int fin = 0; fin < 2; ++fin) {
       for (int t2 = 0; t2 < 2; ++t2) {
-        for (int fg = 0; fg < 4; ++fg) {   // bit 0: FGP, bit 1: bfloat16 dual
+        for (int fg = 0; fg < 8; ++fg) {   // bit 0: FGP, bit 1: bfloat16 dual, bit 2: row stores
           for (int H = kTvLevelsMin; H <= kTvLevelsMax; ++H) {
             BatchLaunch b;
             b.kind = BK_TV;
@@ -1099,13 +1166,15 @@ static std::vector<BatchLaunch> batch_launches(int n, ri_plan* const* plans, con
             b.tv2 = t2 != 0;
             b.fgp = (fg & 1) != 0;
             b.bf16 = (fg & 2) != 0;
+            b.sparse = (fg & 4) != 0;
             for (int i = 0; i < n; ++i) {
               const int np = prox_pass_count(plans[i], params[i]);
               const bool f2 = (plans[i]->g.flags & RI_TV2D) != 0;
               const bool ff = (plans[i]->g.flags & RI_TV_FGP) != 0;
               const bool fb = (plans[i]->g.flags & RI_TV_DUAL_BF16) != 0;
+              const bool fs = (p == np - 1) && plans[i]->store_frac > 0.0;   // only the final pass writes a store
               if (prox_levels(plans[i]->tune.tv_levels, ff) == H && p < np && (p == np - 1) == (fin != 0) &&
-                  f2 == (t2 != 0) && ff == b.fgp && fb == b.bf16)
+                  f2 == (t2 != 0) && ff == b.fgp && fb == b.bf16 && fs == b.sparse)
                 b.frames.push_back(i);
             }
             if (!b.frames.empty()) out.push_back(b);
@@ -1172,8 +1241,9 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     c.ws = base + off;
     c.b = b[i];
     c.vol[0] = x_inout[i];
-    c.vol[1] = at<float>(c.ws, c.L.vol1);
-    c.vol[2] = at<float>(c.ws, c.L.vol2);
+    c.vol[1] = c.L.cap ? nullptr : at<float>(c.ws, c.L.vol1);
+    c.vol[2] = c.L.cap ? nullptr : at<float>(c.ws, c.L.vol2);
+    c.rs = row_stores(plans[i], c.L, c.ws, x_inout[i]);
     c.st = at<SolveState>(c.ws, c.L.state);
     c.step = 1.0 / p->lipschitz;
     c.l1 = params[i].l1;
@@ -1278,6 +1348,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
 
   auto enqueue_batch_iteration = [&](hipStream_t q) -> hipError_t {
     hipError_t e = hipSuccess;
+    bool cleared = false;
     for (const BatchLaunch& bl : launches) {
       if (bl.nblocks == 0) continue;
       const BatchMap mp{reinterpret_cast<const uint32_t*>(tables + bl.offs_off), (int)bl.frames.size()};
@@ -1294,7 +1365,15 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
         case BK_ADJ_COLS: e = launch_adj_cols_batched(bl.size, (const AdjColsArgs*)a, mp, bl.nblocks, q); break;
         case BK_ADJ_ROWS: e = launch_adj_rows_batched(bl.size, (const AdjRowsArgs*)a, mp, bl.nblocks, q); break;
         case BK_TV:
-          e = launch_tv_pass_batched(bl.size, bl.final_pass, bl.tv2, bl.fgp, bl.bf16, a, mp, bl.nblocks, q);
+          if (!cleared) {
+            // the stores that this iteration's final passes fill start empty
+            for (int i = 0; i < n && e == hipSuccess; ++i)
+              if (ctx[i].rs.on) e = launch_store_clear_next(ctx[i].rs, plans[i]->g.ny, plans[i]->g.nz, ctx[i].st, q);
+            cleared = true;
+            if (e != hipSuccess) return e;
+          }
+          e = launch_tv_pass_batched(bl.size, bl.final_pass, bl.tv2, bl.fgp, bl.bf16, bl.sparse, a, mp, bl.nblocks,
+                                     q);
           break;
       }
       if (e != hipSuccess) return e;
@@ -1343,8 +1422,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
   if (graph) hipGraphDestroy(graph);
   if (rs != RI_OK) return rs;
   for (int i = 0; i < n; ++i)
-    HIP_TRY(launch_copy_final(ctx[i].vol[0], ctx[i].vol[1], ctx[i].vol[2], x_inout[i],
-                              (size_t)plans[i]->g.nx * plans[i]->g.ny * plans[i]->g.nz, ctx[i].st, s));
+    HIP_TRY(copy_out(ctx[i], x_inout[i], s));
   if (!reports) return RI_OK;
   ri_status agg = RI_OK;
   for (int i = 0; i < n; ++i) {
@@ -1381,6 +1459,21 @@ extern "C" ri_status ri_plan_set_tuning(ri_plan* p, const ri_tuning* t) {
   if (vs != RI_OK) return vs;
   p->tune = *t;
   drop_graph(p);
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_set_storage(ri_plan* p, double row_fraction) {
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (!(row_fraction >= 0.0 && row_fraction <= 1.0))
+    return fail(RI_ERR_INVALID_ARG, "row_fraction=%g must be in [0, 1]", row_fraction);
+  p->store_frac = row_fraction;
+  drop_graph(p);
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_get_storage(const ri_plan* p, double* row_fraction) {
+  if (!p || !row_fraction) return fail(RI_ERR_INVALID_ARG, "NULL argument");
+  *row_fraction = p->store_frac;
   return RI_OK;
 }
 

@@ -108,13 +108,19 @@ __device__ __forceinline__ void rows_r2c_body(const RowsR2CArgs& a, int bx, int 
   }
   float2* buf = lds[r];
   if (a.mode != 1) {
-    const float* xin = a.x;
-    if (a.mode == 2) xin = pick3(a.xs[0], a.xs[1], a.xs[2], a.st->it % 3);   // solver iterate, before the scalar kernel
-    const float2* src = reinterpret_cast<const float2*>(xin) + (size_t)row * M;
+    const float2* src = nullptr;
+    if (a.mode == 2 && a.rs.on) {
+      // solver iterate from its row store (an absent row is all zero)
+      if (row < a.nrows) src = reinterpret_cast<const float2*>(store_row(a.rs, a.st->it & 1, (size_t)row));
+    } else {
+      const float* xin = a.x;
+      if (a.mode == 2) xin = pick3(a.xs[0], a.xs[1], a.xs[2], a.st->it % 3);   // solver iterate, before the scalar kernel
+      src = reinterpret_cast<const float2*>(xin) + (size_t)row * M;
+    }
 #pragma unroll
     for (int s = 0; s < P; ++s) {
       const int e = t + s * T;
-      buf[e] = active ? src[e] : make_float2(0.f, 0.f);
+      buf[e] = (active && src != nullptr) ? src[e] : make_float2(0.f, 0.f);
     }
   } else {
     const SolveState* st = a.st;
@@ -580,20 +586,31 @@ __device__ __forceinline__ void adj_rows_body(const AdjRowsArgs& a, int bx, int 
     return;
   }
   const SolveState* st = a.st;
-  const float2* xc = reinterpret_cast<const float2*>(pick3(a.x0, a.x1, a.x2, st->cur)) + (size_t)row * M;
-  float2* xp = reinterpret_cast<float2*>(pick3(a.x0, a.x1, a.x2, st->prev)) + (size_t)row * M;
+  const float2* xc;
+  const float2* xpr;
+  float2* vo;
+  if (a.rs.on) {
+    // iterates from their row stores; v into the dense prox input
+    xc = fc ? reinterpret_cast<const float2*>(store_row(a.rs, st->scur, (size_t)row)) : nullptr;
+    xpr = fp ? reinterpret_cast<const float2*>(store_row(a.rs, st->scur ^ 1, (size_t)row)) : nullptr;
+    vo = reinterpret_cast<float2*>(a.rs.v) + (size_t)row * M;
+  } else {
+    xc = fc ? reinterpret_cast<const float2*>(pick3(a.x0, a.x1, a.x2, st->cur)) + (size_t)row * M : nullptr;
+    vo = reinterpret_cast<float2*>(pick3(a.x0, a.x1, a.x2, st->prev)) + (size_t)row * M;
+    xpr = fp ? vo : nullptr;
+  }
   const float beta = (float)st->beta;
   const float gs = (float)(a.step * (double)a.scale);
 #pragma unroll
   for (int s = 0; s < P; ++s) {
     const int e = t + s * T;
     const float2 g = buf[e];
-    const float2 c = fc ? xc[e] : make_float2(0.f, 0.f);
-    const float2 p = fp ? xp[e] : make_float2(0.f, 0.f);
+    const float2 c = xc != nullptr ? xc[e] : make_float2(0.f, 0.f);
+    const float2 p = xpr != nullptr ? xpr[e] : make_float2(0.f, 0.f);
     float2 v;
     v.x = c.x + beta * (c.x - p.x) - gs * g.x;
     v.y = c.y + beta * (c.y - p.y) - gs * g.y;
-    xp[e] = v;
+    vo[e] = v;
   }
   if (t == 0) {
     if (a.rowflag_prev != nullptr) a.rowflag_prev[row] = fc ? 1 : 0;  // x_k is x_{k-1} next time
@@ -662,20 +679,31 @@ __device__ __forceinline__ void obj_body(const ObjArgs& a, int bx, int) {
     hy[rr] = y + 1 < ny;
     hz[rr] = z + 1 < nz;
     bool f0 = on[rr], fy = on[rr] && hy[rr], fz = on[rr] && hz[rr] && !a.tv2;
-    if (a.rowflag != nullptr && on[rr]) {
+    const float* r0 = x + (size_t)(row < nrows ? row : 0) * nx;
+    const float* ry = r0 + nx;
+    const float* rz = r0 + (size_t)ny * nx;
+    if (a.rs.on && on[rr]) {
+      // rows from the iterate's store: an absent row is all zero
+      const int k = a.st != nullptr ? (a.st->it & 1) : 0;
+      r0 = store_row(a.rs, k, (size_t)row);
+      ry = fy ? store_row(a.rs, k, (size_t)row + 1) : nullptr;
+      rz = fz ? store_row(a.rs, k, (size_t)row + ny) : nullptr;
+      f0 = r0 != nullptr;
+      fy = ry != nullptr;
+      fz = rz != nullptr;
+    } else if (a.rowflag != nullptr && on[rr]) {
       f0 = a.rowflag[row] != 0;
       fy = fy && a.rowflag[row + 1] != 0;
       fz = fz && a.rowflag[row + ny] != 0;
     }
-    const float* r0 = x + (size_t)(row < nrows ? row : 0) * nx;
     v[rr] = vy[rr] = vz[rr] = zero;
     vx[rr] = 0.f;
     if (!on[rr]) continue;
     for (int i = i0; i <= ilast; i += CH) {
       v[rr] = f0 ? ld4(r0 + i) : zero;
       vx[rr] = (f0 && i + 4 < nx) ? r0[i + 4] : 0.f;
-      vy[rr] = fy ? ld4(r0 + nx + i) : zero;
-      vz[rr] = fz ? ld4(r0 + (size_t)ny * nx + i) : zero;
+      vy[rr] = fy ? ld4(ry + i) : zero;
+      vz[rr] = fz ? ld4(rz + i) : zero;
       if (i != ilast) reduce4(i, v[rr], vx[rr], vy[rr], vz[rr], hy[rr], hz[rr]);
     }
   }
@@ -739,10 +767,17 @@ __device__ __forceinline__ void scalars_body(const ScalarArgs& a, int, int) {
     }
   }
   if (it >= st->max_iters) done = 1;
+  if (a.count != nullptr) st->rows_peak = max(st->rows_peak, (int)a.count[it & 1]);   // rows of x_it
+  if (a.overflow != nullptr && *a.overflow != 0) {   // a row store ran out of rows (or a wait bound was hit): x_it is incomplete
+    st->status = RI_ERR_WORKSPACE_TOO_SMALL;
+    st->converged = 0;
+    done = 1;
+  }
   // slots of this iteration: x_it in it%3, x_{it-1} in (it+2)%3, x_{it+1} -> (it+1)%3
   st->cur = it % 3;
   st->prev = (it + 2) % 3;
   st->next = (it + 1) % 3;
+  st->scur = it & 1;
   st->ax_cur = it & 1;
   st->ax_prev = (it + 1) & 1;
   if (done) {
@@ -771,6 +806,8 @@ __global__ void k_state_init(SolveState* st, StateInit in) {
   s.converged = 0;
   s.status = RI_OK;
   s.cur = 0; s.prev = 2; s.next = 1;
+  s.scur = 0;
+  s.rows_peak = 0;
   s.ax_cur = 0; s.ax_prev = 1;
   s.max_iters = in.max_iters;
   s.restart = in.restart;
@@ -817,6 +854,76 @@ __global__ void k_flags_from_x(const float* x, int nx, long nrows, int ny, uint8
   }
 }
 
+// Row stores: dense copy of the current store, start, clear of the next store.
+__global__ void k_store_expand(RowStores rs, float* dst, size_t n, const SolveState* st) {
+  const int k = st->scur;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float* r = store_row(rs, k, i / rs.nx);
+    dst[i] = r != nullptr ? r[i % rs.nx] : 0.f;
+  }
+}
+
+__global__ void k_store_reset(RowStores rs) {
+  if (threadIdx.x < 2) rs.count[threadIdx.x] = 0;
+  if (threadIdx.x == 2) *rs.overflow = 0;
+}
+
+// One block per row: a row with a non-zero value takes a pool row in stores 0
+// and 1 (x_0 and x_{-1}); the others are marked absent in both.  x == nullptr
+// starts from the zero volume (every row absent).
+__global__ void k_store_start(RowStores rs, const float* x, long nrows) {
+  const long row = blockIdx.x;
+  if (row >= nrows) return;
+  const float* src = x != nullptr ? x + (size_t)row * rs.nx : nullptr;
+  int any = 0;
+  if (src != nullptr)
+    for (int i = threadIdx.x; i < rs.nx; i += blockDim.x) any |= (src[i] != 0.f);
+  any = __syncthreads_or(any);
+  __shared__ int32_t s0, s2;
+  if (threadIdx.x == 0) {
+    s0 = s2 = -1;
+    if (any) {
+      const uint32_t a = atomicAdd(&rs.count[0], 1u), b = atomicAdd(&rs.count[1], 1u);
+      if (a < rs.cap && b < rs.cap) {
+        s0 = (int32_t)a;
+        s2 = (int32_t)b;
+      } else {
+        atomicOr(rs.overflow, 1u);
+      }
+    }
+    rs.slot[0][row] = s0;
+    rs.slot[1][row] = s2;
+  }
+  __syncthreads();
+  if (s0 < 0) return;
+  float* d0 = rs.pool[0] + (size_t)s0 * rs.nx;
+  float* d2 = rs.pool[1] + (size_t)s2 * rs.nx;
+  for (int i = threadIdx.x; i < rs.nx; i += blockDim.x) {
+    const float v = src[i];
+    d0[i] = v;
+    d2[i] = v;
+  }
+}
+
+// Recycle the store of x_{k-1} for x_{k+1}: zero the pool rows it used (every
+// pool row not in use stays zero) and mark every row absent; the count is
+// reset by a second kernel, after every block has read it.
+__global__ void k_store_clear_next(RowStores rs, long nrows, const SolveState* st) {
+  if (st->done) return;
+  const int k = st->scur ^ 1;
+  int32_t* sl = k == 0 ? rs.slot[0] : rs.slot[1];
+  float* pl = k == 0 ? rs.pool[0] : rs.pool[1];
+  const size_t used = (size_t)min(rs.count[k], rs.cap) * rs.nx;
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < used; i += stride) pl[i] = 0.f;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < nrows; i += (long)stride) sl[i] = -1;
+}
+
+__global__ void k_store_count_reset(RowStores rs, const SolveState* st) {
+  if (st->done) return;
+  if (threadIdx.x == 0) rs.count[st->scur ^ 1] = 0;
+}
+
 static int grid_for(size_t n) {
   size_t b = (n + 255) / 256;
   return (int)(b > 65536 ? 65536 : (b == 0 ? 1 : b));
@@ -850,6 +957,27 @@ hipError_t launch_flags_from_x(const float* x, int nx, int ny, int nz, uint8_t* 
                                hipStream_t s) {
   const long nrows = (long)ny * nz;
   hipLaunchKernelGGL(k_flags_from_x, dim3((unsigned)nrows), dim3(256), 0, s, x, nx, nrows, ny, rowflag, planeflag);
+  return hipGetLastError();
+}
+hipError_t launch_store_expand(const RowStores& rs, float* dst, int ny, int nz, const SolveState* st, hipStream_t s) {
+  const size_t n = (size_t)rs.nx * ny * nz;
+  hipLaunchKernelGGL(k_store_expand, dim3(grid_for(n)), dim3(256), 0, s, rs, dst, n, st);
+  return hipGetLastError();
+}
+hipError_t launch_store_start(const RowStores& rs, const float* x, int ny, int nz, hipStream_t s) {
+  const long nrows = (long)ny * nz;
+  // every pool row starts zero; the rows of x_0 are then written whole
+  for (int k = 0; k < 2; ++k)
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for((size_t)rs.cap * rs.nx)), dim3(256), 0, s, rs.pool[k],
+                       (size_t)rs.cap * rs.nx, 0.f);
+  hipLaunchKernelGGL(k_store_reset, dim3(1), dim3(64), 0, s, rs);
+  hipLaunchKernelGGL(k_store_start, dim3((unsigned)nrows), dim3(256), 0, s, rs, x, nrows);
+  return hipGetLastError();
+}
+hipError_t launch_store_clear_next(const RowStores& rs, int ny, int nz, const SolveState* st, hipStream_t s) {
+  const long nrows = (long)ny * nz;
+  hipLaunchKernelGGL(k_store_clear_next, dim3(grid_for((size_t)nrows * rs.nx)), dim3(256), 0, s, rs, nrows, st);
+  hipLaunchKernelGGL(k_store_count_reset, dim3(1), dim3(64), 0, s, rs, st);
   return hipGetLastError();
 }
 hipError_t launch_state_init(SolveState* st, const StateInit& init, hipStream_t s) {

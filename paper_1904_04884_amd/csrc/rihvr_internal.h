@@ -52,7 +52,8 @@ struct SolveState {
   int32_t ax_cur, ax_prev;   // hologram-buffer slots
   int32_t max_iters;
   int32_t restart;
-  int32_t pad_;
+  int32_t scur;        // row store holding x_it (the other one: x_{it-1}, then x_{it+1})
+  int32_t rows_peak;   // row stores: most pool rows any iterate took so far
   double s;            // FISTA s_k
   double beta;         // momentum of the current extrapolation
   double f_prev;       // objective of the previous iterate
@@ -64,6 +65,35 @@ struct SolveState {
 };
 
 constexpr int kHistCap = 8192;   // objective history entries kept on the device
+
+// Row-compressed storage of the solver's iterates in two alternating stores:
+// x_k in store st->scur, x_{k-1} in the other one until the gradient step has
+// read it, which is then cleared and receives x_{k+1}.  Only the rows holding
+// a non-zero voxel are kept, in a pool of `cap` rows of nx floats;
+// slot[k][row] is the pool row of a volume row (z * ny + y) or -1 for an
+// all-zero row.  The final TV pass allocates a row when a segment first stores
+// a non-zero value into it (claim of the slot, atomic counter, zero fill,
+// publication); readers take a row from the pool or read zeros.  The gradient
+// step's output v goes to a dense volume (the caller's x_inout).  on == 0:
+// dense iterates (vol[3]).
+struct RowStores {
+  float* pool[2];
+  int32_t* slot[2];     // [nz * ny]
+  uint32_t* count;      // [2] pool rows taken
+  uint32_t* overflow;   // set when a pool ran out of rows
+  uint32_t cap;
+  int nx;
+  float* v;             // dense gradient-step output (the prox input)
+  int on;
+};
+
+// Row `row` of store k, or nullptr when the row is all zero.
+__device__ __forceinline__ const float* store_row(const RowStores& rs, int k, size_t row) {
+  const int32_t* sl = k == 0 ? rs.slot[0] : rs.slot[1];
+  float* pl = k == 0 ? rs.pool[0] : rs.pool[1];
+  const int32_t s = sl[row];
+  return s >= 0 ? pl + (size_t)s * rs.nx : nullptr;
+}
 
 // Device pointers of a plan's tables.
 struct PlanTables {
@@ -108,6 +138,7 @@ struct RowsR2CArgs {
   const uint8_t* rowflag;    // nullable
   const SolveState* st;      // nullable (mode 0 outside a solve)
   int mode;
+  RowStores rs;              // mode 2 with rs.on: the iterate's rows come from its store
   PlanTables pt;
   int gx, gy;
 };
@@ -181,6 +212,7 @@ struct AdjRowsArgs {
   double step;
   int mode;
   float scale;
+  RowStores rs;                   // mode 1 with rs.on: x_k, x_{k-1} from their stores, v to rs.v
   PlanTables pt;
   int gx, gy;
 };
@@ -196,6 +228,7 @@ struct ObjArgs {
   const SolveState* st;
   int first_only;             // solver: only x_0 (later iterates are summed by the prox)
   int tv2;                    // per-plane 2D TV: no z differences
+  RowStores rs;               // rs.on: x_it from store it & 1
   int gx, gy;
 };
 dim3 grid_obj(int nx, int ny, int nz);
@@ -211,6 +244,8 @@ struct ScalarArgs {
   const double* psum; const double* ptv; int n_obj;      // objective partials of x_0
   const double* qsum; const double* qtv; int n_prox;     // ... of x_it, it > 0 (prox final pass)
   double* hist;   // [kHistCap]
+  const uint32_t* overflow;   // nullable: a row store ran out of rows (the solve stops with an error)
+  const uint32_t* count;      // nullable: rows taken in each row store (for the peak)
   int gx, gy;
 };
 hipError_t launch_scalars(ScalarArgs a, hipStream_t s);
@@ -236,6 +271,12 @@ hipError_t launch_flags_from_x(const float* x, int nx, int ny, int nz, uint8_t* 
 // Copy the final iterate x[st->cur] into dst if it is not already there.
 hipError_t launch_copy_final(const float* x0, const float* x1, const float* x2, float* dst,
                              size_t n, const SolveState* st, hipStream_t s);
+// Row stores: dense copy of store st->scur (all-zero rows written as zeros);
+// compress a dense volume into store 0 and duplicate it into store 1 (the start
+// x_0 = x_{-1}); clear store st->scur ^ 1 before the prox writes x_{k+1} to it.
+hipError_t launch_store_expand(const RowStores& rs, float* dst, int ny, int nz, const SolveState* st, hipStream_t s);
+hipError_t launch_store_start(const RowStores& rs, const float* x, int ny, int nz, hipStream_t s);
+hipError_t launch_store_clear_next(const RowStores& rs, int ny, int nz, const SolveState* st, hipStream_t s);
 
 // Lipschitz constant on the device: max_f sum_j cos^2(phase_j(f)) in FP64.
 hipError_t launch_lipschitz(const PlanTables& pt, int m, int ny, int nz, double* partial_max,
@@ -265,6 +306,7 @@ struct ProxArgs {
   int cus;               // compute units of the device (shapes the final pass's grid; <= 0: uniform)
   int dual_bf16;         // dual buffers hold bfloat16
   int fgp;               // accelerated dual iteration (one step per pass; pa2 / pb2 hold p)
+  RowStores rs;          // solver with rs.on: v from rs.v, x_{k+1} into store st->scur ^ 1
   int warm;              // solver: the dual starts from the previous prox's (kept in pa / pb,
                          // the sets alternating by outer iteration when the pass count is odd)
 };
@@ -289,7 +331,7 @@ size_t tv_pass_args_size();
 // for one frame and returns the number of passes; blocks_per_pass (nullable,
 // npass entries) receives the frame's blocks of each pass.
 int prox_pass_args(const ProxArgs& a, void* out, int* blocks_per_pass);
-hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, const void* args,
-                                  BatchMap map, int nblocks, hipStream_t s);
+hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, bool sparse,
+                                  const void* args, BatchMap map, int nblocks, hipStream_t s);
 
 }  // namespace rihvr

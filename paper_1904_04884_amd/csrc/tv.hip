@@ -80,6 +80,7 @@ struct TvPassArgs {
   const float* pin2[3];           // FGP: p_prev read with r (= pin)
   float* pout2[3];                // FGP: p written beside r_next (= pout)
   float fgp_w;                    // FGP: extrapolation weight of this pass
+  RowStores rs;                   // final pass with rs.on: x_{k+1} into row store st->scur ^ 1
   int fgp;                        // FGP dual pass (one step; never the final pass)
   int zchunk;                     // output planes per block (the first nfull tiles)
   int nfull;                      // tiles (in raster order) cut into chunks of zchunk planes; the
@@ -160,7 +161,11 @@ __device__ __forceinline__ void dual_st(__amdgpu_buffer_rsrc_t r, unsigned off, 
 // neighbour lies in the computed tile: the final pass fuses at most H - 1
 // steps for its halo of H, so x is exact one point beyond the stored region.
 
-template <int H, int LV, bool EDGE, bool FIRST, bool FINAL, bool TV2, bool FGP, bool BF>
+// Bound on a wave's wait for another segment to publish a row-store index
+// (about 2^20 * 128 clocks; the publisher needs a few hundred).
+constexpr int kStoreSpinLimit = 1 << 20;
+
+template <int H, int LV, bool EDGE, bool FIRST, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by, int zb, int ze, int blk,
                                              float (*s_py)[2][kTvWaves][64], float (*s_ut)[2][kTvWaves][64],
                                              float* s_v, float (*s_x)[kTvWaves][64], double (*s_red)[kTvWaves],
@@ -411,6 +416,57 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       store3(pout, m, c3);
     }
   };
+  // Row-compressed store of x_{k+1} (A.rs.on): this wave's segments of rows
+  // ybase .. ybase + Q - 1 of plane m; bit q of nzm: segment q holds a
+  // non-zero value.  Lane q claims row q's slot (-1 -> -2) when it is still
+  // absent; the claimed rows take consecutive pool rows with one counter
+  // update and their indices are published; a row found claimed by another
+  // segment is waited for (its claimer depends on nothing, so the wait ends;
+  // a bound on it reports an overflow instead).  Slot -3: the pool ran out.
+  // Pool rows not in use are zero (zeroed at the start and when a store is
+  // recycled), so a segment writes only its values and no ordering beyond the
+  // slots' atomics is needed; every occupied row takes exactly one pool row.
+  auto store_rows = [&](int m, const float (&xs)[Q], unsigned nzm, bool zstore) {
+    const int k = A.st->scur ^ 1;
+    float* pool = k == 0 ? A.rs.pool[0] : A.rs.pool[1];
+    const bool mine = lane < Q && ((nzm >> lane) & 1u);
+    int32_t* tab = (k == 0 ? A.rs.slot[0] : A.rs.slot[1]) + (size_t)m * ny + (mine ? ybase + lane : 0);
+    int idx = -1;
+    if (mine) idx = __hip_atomic_load(tab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (mine && idx == -1) {
+      idx = atomicCAS(tab, -1, -2);
+      idx = idx == -1 ? -4 : idx;          // -4: this lane won the claim
+    }
+    const uint64_t wm = __ballot(mine && idx == -4);
+    if (wm != 0) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(&A.rs.count[k], (uint32_t)__popcll(wm));
+      base = __builtin_amdgcn_readfirstlane(base);
+      if (mine && idx == -4) {
+        const uint32_t sn = base + (uint32_t)__popcll(wm & ((1ull << lane) - 1ull));
+        idx = sn < A.rs.cap ? (int)sn : -3;
+        if (idx < 0) atomicOr(A.rs.overflow, 1u);
+        __hip_atomic_store(tab, idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    }
+    for (int spin = 0; __ballot(mine && idx == -2) != 0; ++spin) {
+      if (spin >= kStoreSpinLimit) {
+        if (mine && idx == -2) {
+          atomicOr(A.rs.overflow, 2u);
+          idx = -3;
+        }
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+      if (mine && idx == -2) idx = __hip_atomic_load(tab, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      if (!((nzm >> q) & 1u)) continue;
+      const int r = __builtin_amdgcn_readlane(idx, q);
+      if (r >= 0 && zstore && ys[q]) pool[(size_t)r * nx + x] = xs[q];
+    }
+  };
   auto output = [&](int m, int par, float (&c3)[Q][3]) {
     const bool zstore = m >= zb && m < ze;
     if constexpr (!FINAL) {
@@ -424,6 +480,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
       __syncthreads();
       const __amdgpu_buffer_rsrc_t rx = plane_rsrc(xo, m, sz);
       float xs[Q];
+      unsigned nzm = 0;   // row-compressed store: segments holding a non-zero
 #pragma unroll
       for (int q = 0; q < Q; ++q) {
         float u = vm[q];
@@ -444,14 +501,21 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
         }
         xs[q] = xv;
         const bool st = zstore && ys[q];
-        if (zstore) buf_st(rx, offs[q], xv);
+        const bool nzr = __ballot(st && xv != 0.f) != 0;   // this wave's segment of the row holds a non-zero
+        if constexpr (SP) {
+          nzm |= nzr ? 1u << q : 0u;   // stored below, the wave's rows together
+        } else if (zstore) {
+          buf_st(rx, offs[q], xv);
+        }
         if (A.rowflag != nullptr) {
-          const bool nzr = __ballot(st && xv != 0.f) != 0;
           if (nzr && lane == 0) {
             A.rowflag[(size_t)m * ny + ybase + q] = 1;
             A.planeflag[m] = 1;
           }
         }
+      }
+      if constexpr (SP) {
+        if (nzm != 0) store_rows(m, xs, nzm, zstore);
       }
       if (obj) {
         // plane m - 1 is complete now; its first rows went to slot par ^ 1
@@ -563,7 +627,7 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
 
 // HT: tile halo, LV: fused-step register slots.  Dual passes use HT = LV = H;
 // the final pass HT = H + 1, LV = H.
-template <int HT, int LV, bool FINAL, bool TV2, bool FGP, bool BF>
+template <int HT, int LV, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int by, int zb, int ze, int blk) {
   __shared__ float s_py[LV + 1][2][kTvWaves][64];  // bottom-row p_y per wave, per step (+ final), parity
   __shared__ float s_ut[LV][2][kTvWaves][64];      // top-row u per wave, per step, parity
@@ -579,7 +643,8 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
   const bool interior = x0 >= 1 && x0 + kTvRX <= A.nx - 1 && y0 >= 1 && y0 + kTvRY <= A.ny - 1;
   auto* sx = reinterpret_cast<float (*)[kTvWaves][64]>(&s_x[0][0][0]);
 #define RIHVR_TV_BODY(E, F) \
-  tv_pass_body<HT, LV, E, F, FINAL, TV2, FGP, BF>(A, bx, by, zb, ze, blk, s_py, s_ut, s_v, sx, s_red, s_fin, s_sum)
+  tv_pass_body<HT, LV, E, F, FINAL, TV2, FGP, BF, SP>(A, bx, by, zb, ze, blk, s_py, s_ut, s_v, sx, s_red, s_fin, \
+                                                       s_sum)
   if (A.first) {
     if (interior) RIHVR_TV_BODY(false, true);
     else RIHVR_TV_BODY(true, true);
@@ -625,16 +690,16 @@ __device__ __forceinline__ TvWork tv_work(const TvPassArgs& A, uint32_t t) {
 // The first part of the grid (whole rounds of tiles) takes the XCD-contiguous
 // order; the thin chunks of the split tiles, dispatched last, keep the
 // hardware order so that they spread over every XCD.
-template <int H, bool FINAL, bool TV2, bool FGP, bool BF>
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass(TvPassArgs A) {
   const uint32_t hw = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   const uint32_t n1 = (uint32_t)A.nfull * (uint32_t)((A.nz + A.zchunk - 1) / A.zchunk);
   const uint32_t t = hw < n1 ? xcd_tile(hw, n1) : hw;
   const TvWork w = tv_work(A, t);
-  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF>(A, w.bx, w.by, w.zb, w.ze, (int)t);
+  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF, SP>(A, w.bx, w.by, w.zb, w.ze, (int)t);
 }
 
-template <int H, bool FINAL, bool TV2, bool FGP, bool BF>
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(const TvPassArgs* __restrict__ args,
                                                                                   BatchMap map) {
   const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
@@ -650,7 +715,7 @@ __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(co
   const TvPassArgs& A = args[lo];
   const int lb = (int)(b - (uint32_t)__builtin_amdgcn_readfirstlane(map.offs[lo]));
   const TvWork w = tv_work(A, (uint32_t)lb);
-  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF>(A, w.bx, w.by, w.zb, w.ze, lb);
+  tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF, SP>(A, w.bx, w.by, w.zb, w.ze, lb);
 }
 
 // Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut into
@@ -752,6 +817,7 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
   a.tau = (float)tau;
   a.tv2 = pa.tv2 ? 1 : 0;
   a.dual_bf16 = pa.dual_bf16 ? 1 : 0;
+  a.rs = pa.rs;
   a.c = use_tv ? (float)(1.0 / ((pa.tv2 ? 8.0 : 12.0) * tau)) : 0.f;
   a.thr = (float)thr;
   const int want = pa.blocks > 0 ? pa.blocks : kTvDefaultBlocks;
@@ -796,53 +862,60 @@ int prox_pass_args(const ProxArgs& pa, void* out, int* blocks_per_pass) {
 }
 
 // Kernel selection: fusion depth, final / dual pass, 2D or 3D TV, FGP (dual
-// passes of depth-2 tiles only), bfloat16 dual.  BATCH picks the batched form.
-template <bool BATCH, bool FINAL, bool TV2, bool FGP, bool BF>
+// passes of depth-2 tiles only), bfloat16 dual, row-compressed output (final
+// passes with an FP32 dual only).  BATCH picks the batched form.
+template <bool BATCH, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 static void launch_k(int H, dim3 g, const TvPassArgs* a, BatchMap map, hipStream_t s) {
   const dim3 b(kTvWaves * 64);
   if constexpr (FGP) {
-    if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, true, BF>), g, b, 0, s, a, map);
-    else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, true, BF>), g, b, 0, s, *a);
+    if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, true, BF, false>), g, b, 0, s, a, map);
+    else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, true, BF, false>), g, b, 0, s, *a);
   } else {
     switch (H) {
       case 2:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
-        else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
       case 3:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<3, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
-        else hipLaunchKernelGGL((k_tv_pass<3, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<3, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<3, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
       default:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<4, FINAL, TV2, false, BF>), g, b, 0, s, a, map);
-        else hipLaunchKernelGGL((k_tv_pass<4, FINAL, TV2, false, BF>), g, b, 0, s, *a);
+        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<4, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        else hipLaunchKernelGGL((k_tv_pass<4, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
     }
   }
 }
 
 template <bool BATCH, bool FINAL, bool TV2>
-static void launch_sel(bool fgp, bool bf, int H, dim3 g, const TvPassArgs* a, BatchMap map, hipStream_t s) {
+static void launch_sel(bool fgp, bool bf, bool sp, int H, dim3 g, const TvPassArgs* a, BatchMap map,
+                       hipStream_t s) {
   if constexpr (!FINAL) {
     if (fgp) {
-      if (bf) launch_k<BATCH, false, TV2, true, true>(H, g, a, map, s);
-      else launch_k<BATCH, false, TV2, true, false>(H, g, a, map, s);
+      if (bf) launch_k<BATCH, false, TV2, true, true, false>(H, g, a, map, s);
+      else launch_k<BATCH, false, TV2, true, false, false>(H, g, a, map, s);
+      return;
+    }
+  } else {
+    if (sp && !bf) {
+      launch_k<BATCH, true, TV2, false, false, true>(H, g, a, map, s);
       return;
     }
   }
-  if (bf) launch_k<BATCH, FINAL, TV2, false, true>(H, g, a, map, s);
-  else launch_k<BATCH, FINAL, TV2, false, false>(H, g, a, map, s);
+  if (bf) launch_k<BATCH, FINAL, TV2, false, true, false>(H, g, a, map, s);
+  else launch_k<BATCH, FINAL, TV2, false, false, false>(H, g, a, map, s);
 }
 
 template <bool BATCH>
-static void launch_any(bool final_pass, bool tv2, bool fgp, bool bf, int H, dim3 g, const TvPassArgs* a,
+static void launch_any(bool final_pass, bool tv2, bool fgp, bool bf, bool sp, int H, dim3 g, const TvPassArgs* a,
                        BatchMap map, hipStream_t s) {
   if (final_pass) {
-    if (tv2) launch_sel<BATCH, true, true>(false, bf, H, g, a, map, s);
-    else launch_sel<BATCH, true, false>(false, bf, H, g, a, map, s);
+    if (tv2) launch_sel<BATCH, true, true>(false, bf, sp, H, g, a, map, s);
+    else launch_sel<BATCH, true, false>(false, bf, sp, H, g, a, map, s);
   } else {
-    if (tv2) launch_sel<BATCH, false, true>(fgp, bf, H, g, a, map, s);
-    else launch_sel<BATCH, false, false>(fgp, bf, H, g, a, map, s);
+    if (tv2) launch_sel<BATCH, false, true>(fgp, bf, false, H, g, a, map, s);
+    else launch_sel<BATCH, false, false>(fgp, bf, false, H, g, a, map, s);
   }
 }
 
@@ -855,15 +928,15 @@ hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
   std::vector<int> nb(np);
   const int npass = prox_pass_args(pa, args.data(), nb.data());
   for (int p = 0; p < npass; ++p)
-    launch_any<false>(args[p].final_ != 0, args[p].tv2 != 0, args[p].fgp != 0, args[p].dual_bf16 != 0, H,
-                      dim3(nb[p]), &args[p], BatchMap{nullptr, 0}, s);
+    launch_any<false>(args[p].final_ != 0, args[p].tv2 != 0, args[p].fgp != 0, args[p].dual_bf16 != 0,
+                      args[p].rs.on != 0, H, dim3(nb[p]), &args[p], BatchMap{nullptr, 0}, s);
   if (launches) *launches = npass;
   return hipGetLastError();
 }
 
-hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, const void* args,
-                                  BatchMap map, int nblocks, hipStream_t s) {
-  launch_any<true>(final_pass, tv2, fgp && !final_pass, bf16, clamp_levels(levels), dim3(nblocks),
+hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, bool sparse,
+                                  const void* args, BatchMap map, int nblocks, hipStream_t s) {
+  launch_any<true>(final_pass, tv2, fgp && !final_pass, bf16, sparse, clamp_levels(levels), dim3(nblocks),
                    static_cast<const TvPassArgs*>(args), map, s);
   return hipGetLastError();
 }

@@ -48,7 +48,7 @@ PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 
 EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size", "ri_workspace_size_op",
-    "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_autotune",
+    "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_set_storage", "ri_plan_get_storage", "ri_plan_autotune",
     "ri_forward", "ri_forward_noalloc", "ri_forward_noalloc_max_scratch", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
     "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
@@ -87,10 +87,12 @@ class ri_solve_report(C.Structure):
     _fields_ = [("iters", C.c_int32), ("converged", C.c_int32), ("objective", C.c_double),
                 ("objective_min", C.c_double), ("gap", C.c_double),
                 ("lipschitz", C.c_double), ("empty_plane_frac", C.c_double), ("empty_row_frac", C.c_double),
-                ("phase_ms", C.c_double * RI_NUM_PHASES), ("phase_launches", C.c_int32 * RI_NUM_PHASES)]
+                ("phase_ms", C.c_double * RI_NUM_PHASES), ("phase_launches", C.c_int32 * RI_NUM_PHASES),
+                ("store_rows_peak", C.c_int32)]
 
     def as_dict(self):
         return {
+            "store_rows_peak": self.store_rows_peak,
             "iters": self.iters, "converged": bool(self.converged), "objective": self.objective,
             "objective_min": self.objective_min,
             "gap": self.gap, "lipschitz": self.lipschitz, "empty_plane_frac": self.empty_plane_frac,
@@ -147,6 +149,8 @@ def lib():
     L.ri_workspace_size_op.argtypes = [vp, C.c_int, C.POINTER(sz)]
     L.ri_plan_get_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
     L.ri_plan_set_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
+    L.ri_plan_set_storage.argtypes = [vp, C.c_double]
+    L.ri_plan_get_storage.argtypes = [vp, C.POINTER(C.c_double)]
     L.ri_plan_autotune.argtypes = [vp, C.c_int32, C.c_char_p, vp, sz, vp, C.POINTER(ri_autotune_report)]
     L.ri_forward.argtypes = [vp, vp, vp, vp, sz, vp]
     L.ri_forward_noalloc.argtypes = [vp, vp, vp, vp]
@@ -229,6 +233,16 @@ def ri_plan_get_tuning(plan: int) -> ri_tuning:
 
 def ri_plan_set_tuning(plan: int, tuning: ri_tuning) -> int:
     return lib().ri_plan_set_tuning(plan, C.byref(tuning))
+
+
+def ri_plan_set_storage(plan: int, row_fraction: float) -> int:
+    return lib().ri_plan_set_storage(plan, float(row_fraction))
+
+
+def ri_plan_get_storage(plan: int) -> float:
+    v = C.c_double()
+    _check(lib().ri_plan_get_storage(plan, C.byref(v)), "ri_plan_get_storage")
+    return v.value
 
 
 def ri_plan_autotune(plan, inner_iters, cache_path, ws, ws_bytes, stream, report=None) -> int:
@@ -375,6 +389,16 @@ class Plan:
     def tuning(self, t: dict):
         _check(ri_plan_set_tuning(self.handle, ri_tuning(int(t["tv_levels"]), int(t["tv_blocks"]),
                                                          int(t["col_blocks"]))), "ri_plan_set_tuning")
+
+    @property
+    def row_fraction(self) -> float:
+        """Storage of the solver's iterates: 0 dense, else the fraction of rows
+        each row store holds (see ri_plan_set_storage)."""
+        return ri_plan_get_storage(self.handle)
+
+    @row_fraction.setter
+    def row_fraction(self, f: float):
+        _check(ri_plan_set_storage(self.handle, f), "ri_plan_set_storage")
 
     def autotune(self, inner_iters: int, cache_path=None) -> dict:
         """Time the candidate launch shapes on the device and keep the fastest (see ri_plan_autotune)."""
