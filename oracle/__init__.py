@@ -10,6 +10,9 @@ Modules:
   fista   - objective and the FISTA iteration
   detect  - threshold / connected components / weighted centroids / matching
   unet    - warm-start 3D U-Net forward and analytic backward
+  complex_object - the complex-valued object: forward, adjoint, complex TV
+            prox, complex shrinkage, objective and FISTA
 """
 from . import optics, prox, fista, detect  # noqa: F401
+from . import complex_object  # noqa: F401,E402
 from . import unet  # noqa: F401,E402
