@@ -484,6 +484,45 @@ def run_warmstart(args, torch, rihvr, scenes):
     }
 
 
+def complex_leg(torch, rihvr, scenes, g, cfg, sc, iters=8):
+    """The same scene with a complex amplitude (a phase per plane) on an
+    RI_COMPLEX plan: per-iteration phase times of a short timed solve.  The
+    complex TV prox is unfused: each dual step streams u = v - tau D^T p
+    (read v 8 B, p 24 B; write u 8 B) and the dual update (read u 8 B, p 24 B;
+    write p 24 B), 96 B per complex voxel per step."""
+    gc = g.with_(complex_object=True)
+    p = rihvr.Plan(gc)
+    try:
+        nvox = g.nx * g.ny * g.nz
+        lin = np.ravel_multi_index((sc.idx[:, 0], sc.idx[:, 1], sc.idx[:, 2]), g.shape)
+        psi = np.random.default_rng(7).uniform(-0.8, 0.8, g.nz)
+        xt = torch.zeros((2, nvox), dtype=torch.float32, device="cuda")
+        ph = np.exp(1j * psi[sc.idx[:, 0]]) * sc.val
+        xt[0, torch.from_numpy(lin).cuda()] = torch.from_numpy(ph.real.astype(np.float32)).cuda()
+        xt[1, torch.from_numpy(lin).cuda()] = torch.from_numpy(ph.imag.astype(np.float32)).cuda()
+        b = (p.forward(xt.view(p.shape)) + torch.from_numpy(sc.noise.astype(np.float32)).cuda()).contiguous()
+        del xt
+        p.solve(b, cfg.l1, cfg.tv, 2, cfg.inner_iters, nonneg=False)       # capture
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, rep, _ = p.solve(b, cfg.l1, cfg.tv, iters, cfg.inner_iters, nonneg=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        _, rt, _ = p.solve(b, cfg.l1, cfg.tv, iters, cfg.inner_iters, nonneg=False, flags=rihvr.RI_SOLVE_TIMING)
+        ph_ms = {k: v / iters for k, v in rt["phase_ms"].items()}
+        prox_bytes = (96.0 * cfg.inner_iters + 40.0) * nvox
+        out = {"iters": iters, "ms_per_iter": 1000.0 * dt / iters, "phase_ms_per_iter": ph_ms,
+               "prox_GB_per_s": prox_bytes / (ph_ms["prox"] * 1e-3) / 1e9,
+               "prox_bytes_model": "96 B per complex voxel per dual step + 40 B final",
+               "objective": rep["objective"]}
+        log(f"complex object: {out['ms_per_iter']:.1f} ms per iteration (prox {ph_ms['prox']:.1f} ms, "
+            f"{out['prox_GB_per_s']:.0f} GB/s by the unfused byte model)")
+        return out
+    finally:
+        p.close()
+        torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -517,6 +556,8 @@ def main():
                     help="timed solves use function-value restart of the momentum (FISTA variant; not the default)")
     ap.add_argument("--tuning", type=str, default=None,
                     help="fixed launch shapes tv_levels,tv_blocks,col_blocks (no autotuning; for profiling)")
+    ap.add_argument("--no-complex", dest="complex_leg", action="store_false",
+                    help="skip the complex-object leg (RI_COMPLEX plan at the same size, a few iterations)")
     ap.add_argument("--no-row-store", dest="row_store", action="store_false",
                     help="skip the row-store leg (the same solve with row-compressed iterates)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -669,6 +710,7 @@ def main():
                      "value_over_row_store": value * dts}
         log(f"row stores: peak {peak} of {rows} rows; {1.0 / dts:.4f} holograms/s, {rep_s['iters']} iterations, "
             f"status {row_store['status']}; solve workspace {store_ws / 2**30:.2f} GiB vs {dense_ws / 2**30:.2f} GiB")
+    cplx = complex_leg(torch, rihvr, scenes, g, cfg, sc) if args.complex_leg else None
     fft = fft_rates(torch, plan, g)
     log("FFT: " + ", ".join(f"{k} {v['tflops']:.2f} TFLOP/s ({v['ms']:.3f} ms)"
                             for k, v in fft.items() if isinstance(v, dict)))
@@ -714,6 +756,7 @@ def main():
         "cpu_baseline": cpu,
         "plain_fista": plain,
         "row_store": row_store,
+        "complex_object": cplx,
         "fft": fft,
         "copy_bandwidth": copy_bw,
     }

@@ -74,13 +74,29 @@ typedef enum { RI_F32 = 0, RI_F64 = 1 } ri_dtype;
                                step per pass over memory, two duals per set in the workspace */
 #define RI_TV_DUAL_BF16 0x8u /* keep the TV dual in bfloat16 between passes over memory (the
                                arithmetic stays FP32; the dual's bytes halve) */
+#define RI_COMPLEX    0x10u /* complex-valued object (absorption and phase; section
+                               "Methodology": the volume is stored as complex values and
+                               Eq. (8) shrinks the modulus).  Every volume argument (x, v,
+                               x_out, x_inout, A^T y) is then [2][nz][ny][nx] FP32: the real
+                               parts of the nz planes, then their imaginary parts.  A x =
+                               Re(sum_j IFFT2(FFT2(x_j) H_j)) and its adjoint under the real
+                               inner product; ||x||_1 = sum |x_i|; TV(x) = sum over voxels of
+                               sqrt(sum_d |D_d x|^2) (the modulus of complex differences, 3D
+                               or with RI_TV2D per plane); prox = (1 - t l1/|u|)_+ u of the
+                               complex TV prox u, computed by gradient projection on a
+                               complex dual (one complex value per direction, projected
+                               jointly), one step per two passes over memory.  ||A||^2 = nz.
+                               nonneg must be 0.  Not combinable with RI_TV_FGP or
+                               RI_TV_DUAL_BF16; ri_solve rejects RI_SOLVE_DUAL_WARM and row
+                               stores, ri_solve_batched and ri_plan_autotune reject the plan
+                               (RI_ERR_INVALID_ARG). */
 
 typedef struct {
   int32_t nx, ny, nz;       /* hologram width, height; number of planes */
   double pixel_um;          /* lateral pixel pitch, micrometres */
   double wavelength_um;     /* illumination wavelength, micrometres */
   double z0_um, dz_um;      /* plane j at z0 + j*dz from the sensor */
-  uint32_t flags;           /* RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16 */
+  uint32_t flags;           /* RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16 | RI_COMPLEX */
 } ri_geometry;
 
 /* Fused-lasso proximal operator settings (Eq. 5, Eq. 6). */

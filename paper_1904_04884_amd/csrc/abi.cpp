@@ -89,6 +89,7 @@ struct ri_plan {
   GraphCache gc;
   ri_tuning tune{kTvDefaultLevels, kTvDefaultBlocks, kColDefaultBlocks};
   double store_frac = 0.0;   // > 0: row-compressed iterates with room for this fraction of rows
+  bool cplx = false;         // complex object: g.nz counts the planes of both parts
   PlanTables tables() const { return PlanTables{theta, zc, tw_row, tw_col}; }
 };
 
@@ -136,8 +137,12 @@ static ri_status validate_geometry(const ri_geometry* g) {
   if (!(fmax2 < 1.0 / (g->wavelength_um * g->wavelength_um)))
     return fail(RI_ERR_INVALID_ARG, "pixel %.4g um <= lambda/sqrt(2): evanescent frequencies are not supported",
                 g->pixel_um);
-  if (g->flags & ~(RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16))
+  if (g->flags & ~(RI_NO_CARRIER | RI_TV2D | RI_TV_FGP | RI_TV_DUAL_BF16 | RI_COMPLEX))
     return fail(RI_ERR_INVALID_ARG, "unknown geometry flags 0x%x", g->flags);
+  if ((g->flags & RI_COMPLEX) && (g->flags & (RI_TV_FGP | RI_TV_DUAL_BF16)))
+    return fail(RI_ERR_INVALID_ARG, "RI_COMPLEX plans take neither RI_TV_FGP nor RI_TV_DUAL_BF16");
+  if ((g->flags & RI_COMPLEX) && g->nz > (1 << 30))
+    return fail(RI_ERR_INVALID_ARG, "nz=%d too large for a complex plan", g->nz);
   return RI_OK;
 }
 
@@ -151,7 +156,12 @@ extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_pla
   ri_plan* p = new ri_plan();
   p->g = *g;
   p->m = g->nx / 2;
-  const int nx = g->nx, ny = g->ny, nz = g->nz, m = p->m;
+  // A complex object is two real volumes (real parts, imaginary parts): the
+  // plan covers 2 nz planes, the second nz with the carrier a quarter cycle on
+  // (i H_j), so A acting on the imaginary parts is Re(IFFT2(FFT2(i x_j) H_j)).
+  p->cplx = (g->flags & RI_COMPLEX) != 0;
+  if (p->cplx) p->g.nz = 2 * g->nz;
+  const int nx = g->nx, ny = g->ny, nz = p->g.nz, m = p->m;
   hipError_t e = hipGetDevice(&p->device);
   if (e != hipSuccess) { free_plan(p); return fail(RI_ERR_HIP, "hipGetDevice: %s", hipGetErrorString(e)); }
   e = hipDeviceGetAttribute(&p->cus, hipDeviceAttributeMultiprocessorCount, p->device);
@@ -170,11 +180,16 @@ extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_pla
   }
   std::vector<double2> zc(nz);
   for (int j = 0; j < nz; ++j) {
-    const double z = g->z0_um + g->dz_um * j;
+    const int jp = p->cplx ? j % g->nz : j;              // plane of the part
+    const double z = g->z0_um + g->dz_um * jp;
     double c = 0.0;
     if (!(g->flags & RI_NO_CARRIER)) {
       const double t = z / g->wavelength_um;
       c = t - std::floor(t);
+    }
+    if (p->cplx && j >= g->nz) {
+      c += 0.25;
+      c -= std::floor(c);
     }
     zc[j] = make_double2(z, c);
   }
@@ -582,6 +597,7 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   const float* v = static_cast<const float*>(vv);
   float* x_out = static_cast<float*>(xv);
   if (!pp) return fail(RI_ERR_INVALID_ARG, "params is NULL");
+  if (p->cplx && pp->nonneg) return fail(RI_ERR_INVALID_ARG, "nonneg has no meaning for a complex object (pass 0)");
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float);
   ri_status st = check_common(p, v, x_out, ws, ws_bytes, RI_OP_PROX, vb, vb);
   if (st != RI_OK) return st;
@@ -610,6 +626,10 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   // final pass writes its result into the dual set it does not use (its
   // output set: it stores no dual) -- or, with bfloat16 duals, too small for
   // x, into a staging volume -- which is then copied over v.
+  if (p->cplx) {   // in place is safe: the final launch reads only a voxel's own v
+    HIP_TRY(launch_cprox(a, (hipStream_t)stream, nullptr));
+    return RI_OK;
+  }
   const double tau = step * pp->tv;
   const int K = (tau > 0.0 && pp->inner_iters > 0) ? pp->inner_iters : 0;
   float* staged = nullptr;
@@ -778,6 +798,7 @@ static IterArgs iteration_args(const SolveCtx& c) {
   sa.qtv = at<double>(c.ws, L.qtv);
   sa.n_prox = tv_final_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks, p->cus);
   sa.hist = at<double>(c.ws, L.hist);
+  if (p->cplx) sa.qsum = sa.qtv = nullptr;   // the objective kernel runs every iteration
   sa.overflow = c.rs.on ? c.rs.overflow : nullptr;
   sa.count = c.rs.on ? c.rs.count : nullptr;
   RowsR2CArgs& rr = I.resid;
@@ -847,7 +868,7 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
     if (e != hipSuccess) return e;   \
   } while (0)
   if (tm) tm->begin(PH_OBJ);
-  LTRY(launch_obj(I.obj, s));
+  LTRY(p->cplx ? launch_cobj(I.obj, c.L.n_obj, s) : launch_obj(I.obj, s));
   if (tm) tm->end(1);
   if (tm) tm->begin(PH_FORWARD);
   LTRY(launch_rows_r2c(m, I.fwd_rows, s));
@@ -866,7 +887,7 @@ static hipError_t enqueue_iteration(const SolveCtx& c, hipStream_t s, PhaseTimer
   if (tm) tm->begin(PH_PROX);
   int nl = 0;
   if (c.rs.on) LTRY(launch_store_clear_next(c.rs, ny, p->g.nz, c.st, s));
-  LTRY(launch_prox(I.prox, s, &nl));
+  LTRY(p->cplx ? launch_cprox(I.prox, s, &nl) : launch_prox(I.prox, s, &nl));
   if (tm) tm->end(nl);
 #undef LTRY
   return hipSuccess;
@@ -893,6 +914,11 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
     return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_TV_FGP plans");
   if (p->store_frac > 0.0 && (p->g.flags & RI_TV_DUAL_BF16))
     return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_TV_DUAL_BF16 plans");
+  if (p->cplx && sp->nonneg) return fail(RI_ERR_INVALID_ARG, "nonneg has no meaning for a complex object (pass 0)");
+  if (p->cplx && (sp->flags & RI_SOLVE_DUAL_WARM))
+    return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_COMPLEX plans");
+  if (p->cplx && p->store_frac > 0.0)
+    return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_COMPLEX plans");
   return RI_OK;
 }
 
@@ -1234,6 +1260,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     const size_t fb = frame_ws_bytes(p);
     vs = validate_solve(p, &params[i], b[i], x_inout[i], base + off, fb);
     if (vs != RI_OK) return vs;
+    if (p->cplx) return fail(RI_ERR_INVALID_ARG, "frame %d: RI_COMPLEX plans are solved one by one (ri_solve)", i);
     if (p->device != plans[0]->device) return fail(RI_ERR_INVALID_ARG, "plans on different devices");
     SolveCtx& c = ctx[i];
     c.p = p;
@@ -1598,6 +1625,7 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
   const auto t0 = std::chrono::steady_clock::now();
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
   if (inner_iters < 0) return fail(RI_ERR_INVALID_ARG, "inner_iters=%d must be >= 0", inner_iters);
+  if (p->cplx) return fail(RI_ERR_INVALID_ARG, "RI_COMPLEX plans have no launch shapes to tune");
   const Layout LT = make_layout(p, RI_OP_AUTOTUNE);
   if (!ws) return fail(RI_ERR_INVALID_ARG, "workspace is NULL (needs %zu bytes)", LT.total);
   if (ws_bytes < LT.total) return fail(RI_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", ws_bytes, LT.total);

@@ -334,4 +334,12 @@ int prox_pass_args(const ProxArgs& a, void* out, int* blocks_per_pass);
 hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fgp, bool bf16, bool sparse,
                                   const void* args, BatchMap map, int nblocks, hipStream_t s);
 
+// Complex-valued object (cplx.hip): volumes [2][nz/2][ny][nx] (real parts, then
+// imaginary parts; `nz` in the argument structs counts the planes of both).
+// The fused-lasso prox with the complex TV (GP on a complex dual, pa[] the
+// dual, pb[0] a scratch volume for u) and the complex shrinkage; the solver's
+// objective partials of sum |x| and the complex TV in `nblocks` blocks.
+hipError_t launch_cprox(const ProxArgs& a, hipStream_t s, int* launches);
+hipError_t launch_cobj(const ObjArgs& a, int nblocks, hipStream_t s);
+
 }  // namespace rihvr

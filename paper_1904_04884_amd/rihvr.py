@@ -34,6 +34,7 @@ RI_NO_CARRIER = 0x1
 RI_TV2D = 0x2
 RI_TV_FGP = 0x4
 RI_TV_DUAL_BF16 = 0x8
+RI_COMPLEX = 0x10
 RI_INIT_ZERO = 0
 RI_INIT_GIVEN = 1
 RI_SOLVE_DENSE = 0x1
@@ -342,6 +343,8 @@ def geometry_struct(geom) -> ri_geometry:
         flags |= RI_TV_FGP
     if getattr(geom, "dual_bf16", False):
         flags |= RI_TV_DUAL_BF16
+    if getattr(geom, "complex_object", False):
+        flags |= RI_COMPLEX
     return ri_geometry(int(geom.nx), int(geom.ny), int(geom.nz), float(geom.pixel_um),
                        float(geom.wavelength_um), float(geom.z0_um), float(geom.dz_um), flags)
 
@@ -371,6 +374,10 @@ class Plan:
 
     @property
     def shape(self):
+        """Shape of a volume argument: [nz][ny][nx], or [2][nz][ny][nx] (real
+        parts, imaginary parts) for a complex object."""
+        if getattr(self.geom, "complex_object", False):
+            return (2, self.geom.nz, self.geom.ny, self.geom.nx)
         return (self.geom.nz, self.geom.ny, self.geom.nx)
 
     def workspace(self, op: int):

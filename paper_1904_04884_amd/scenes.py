@@ -37,6 +37,8 @@ class Geometry:
     tv_dims: 3 for the 3D TV, 2 for the per-plane 2D TV of the paper's Eq. (4).
     tv_fgp, dual_bf16: inner-solver options of the library (accelerated dual
     iteration; dual stored in bfloat16).
+    complex_object: the object is complex (absorption and phase); the library
+    then holds a volume as [2][nz][ny][nx] (real parts, imaginary parts).
     """
     nx: int
     ny: int
@@ -49,6 +51,7 @@ class Geometry:
     tv_dims: int = 3
     tv_fgp: bool = False
     dual_bf16: bool = False
+    complex_object: bool = False
 
     @property
     def shape(self):

@@ -1,0 +1,196 @@
+"""Complex-valued object (geometry flag RI_COMPLEX) against the complex oracle
+(oracle/complex_object.py).
+
+Volumes are [2][nz][ny][nx] on the device (real parts, imaginary parts).
+Bars as for the real path: forward, adjoint and prox within 1e-5 relative L2
+of the FP64 oracle (FP32 data, FP64 phase reduction); whole solves within
+1e-3 on the iterate and 1e-4 on the objective after the same outer and inner
+iterations.
+"""
+import numpy as np
+import pytest
+
+from oracle import complex_object as co
+from paper_1904_04884_amd import rihvr, scenes
+
+pytestmark = pytest.mark.gpu
+
+
+def rel_l2(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(torch, z):
+    """complex [nz][ny][nx] -> device [2][nz][ny][nx] FP32"""
+    z = np.asarray(z)
+    return torch.from_numpy(np.ascontiguousarray(np.stack([z.real, z.imag]).astype(np.float32))).cuda()
+
+
+def to_host(t):
+    a = t.detach().cpu().numpy().astype(np.float64)
+    return a[0] + 1j * a[1]
+
+
+def cgeom(nx, ny, nz, **kw):
+    return scenes.geometry_c1().with_(nx=nx, ny=ny, nz=nz, complex_object=True, **kw)
+
+
+def crandn(rng, shape, scale=1.0):
+    return scale * (rng.standard_normal(shape) + 1j * rng.standard_normal(shape))
+
+
+SHAPES = [(64, 48, 6), (128, 96, 9), (48, 64, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("carrier", [True, False])
+def test_forward_and_adjoint(torch_cuda, shape, carrier):
+    torch = torch_cuda
+    g = cgeom(*shape, carrier=carrier)
+    rng = np.random.default_rng(sum(shape) + carrier)
+    x = crandn(rng, g.shape)
+    r = rng.standard_normal((g.ny, g.nx))
+    p = rihvr.Plan(g)
+    try:
+        assert p.shape == (2, g.nz, g.ny, g.nx)
+        assert p.lipschitz == pytest.approx(float(g.nz), rel=1e-9)
+        b = p.forward(to_dev(torch, x)).cpu().numpy().astype(np.float64)
+        assert rel_l2(b, co.forward(g, x)) <= 1e-5
+        xt = to_host(p.adjoint(torch.from_numpy(r.astype(np.float32)).cuda()))
+        assert rel_l2(xt, co.adjoint(g, r)) <= 1e-5
+    finally:
+        p.close()
+
+
+@pytest.mark.parametrize("shape", [(64, 48, 6), (96, 64, 11)])
+@pytest.mark.parametrize("dims", [3, 2])
+@pytest.mark.parametrize("k", [0, 1, 5, 20])
+def test_prox(torch_cuda, shape, dims, k):
+    torch = torch_cuda
+    g = cgeom(*shape, tv_dims=dims)
+    rng = np.random.default_rng(7 * k + dims + shape[2])
+    v = crandn(rng, g.shape, 0.3)
+    step, l1, tv = 0.6, 0.05, 0.3
+    ref = co.prox_fused_lasso(v, step, l1, tv, k, dims)
+    p = rihvr.Plan(g)
+    try:
+        vd = to_dev(torch, v)
+        out = p.prox(vd, step, l1, tv, k, nonneg=False)
+        assert rel_l2(to_host(out), ref) <= 1e-5
+        # in place gives the same bits
+        w = vd.clone()
+        p.prox(w, step, l1, tv, k, nonneg=False, out=w)
+        assert torch.equal(w, out)
+        # shrinkage only (no TV): (1 - thr/|v|)_+ v elementwise
+        if k == 0:
+            sh = co.shrink(v.astype(np.complex64).astype(np.complex128), step * l1)
+            np.testing.assert_allclose(to_host(out), sh, rtol=0, atol=1e-6)
+    finally:
+        p.close()
+
+
+def test_prox_global_phase(torch_cuda):
+    """The complex TV and l1 are blind to a global phase: rotating v rotates the
+    prox (to FP32 rounding), which separate projections of the two parts
+    would not do."""
+    torch = torch_cuda
+    g = cgeom(64, 64, 5)
+    rng = np.random.default_rng(3)
+    v = crandn(rng, g.shape, 0.3)
+    ph = np.exp(1j * 1.1)
+    p = rihvr.Plan(g)
+    try:
+        a = to_host(p.prox(to_dev(torch, v), 0.5, 0.05, 0.4, 12, nonneg=False))
+        b = to_host(p.prox(to_dev(torch, ph * v), 0.5, 0.05, 0.4, 12, nonneg=False))
+        assert rel_l2(b, ph * a) <= 2e-6
+    finally:
+        p.close()
+
+
+def complex_scene(seed, geom=None):
+    """C1 particles with a complex amplitude: absorption and a phase that
+    varies from particle to particle (per plane here, the particles being
+    sparse), plus the hologram of the oracle's forward model."""
+    sc = scenes.scene_c1(seed=seed, geom=geom)
+    g = sc.geometry.with_(complex_object=True)
+    rng = np.random.default_rng(100 + seed)
+    psi = rng.uniform(-0.8, 0.8, g.nz)
+    x = sc.dense() * np.exp(1j * psi)[:, None, None]
+    b = co.forward(g, x) + sc.noise
+    return g, sc.config, x, b.astype(np.float32)
+
+
+@pytest.mark.parametrize("dims", [3, 2])
+def test_solve_matches_oracle(torch_cuda, dims):
+    torch = torch_cuda
+    g, cfg, _, b = complex_scene(2)
+    g = g.with_(tv_dims=dims)
+    iters, k_in = 20, 5
+    ref = co.fista(g, b.astype(np.float64), cfg.l1, cfg.tv, iters, k_in, dims=dims)
+    p = rihvr.Plan(g)
+    try:
+        x, rep, _ = p.solve(torch.from_numpy(b).cuda(), cfg.l1, cfg.tv, iters, k_in, nonneg=False)
+        assert rep["iters"] == iters
+        got = to_host(x)
+        assert rel_l2(got, ref) <= 1e-3
+        F = co.objective(g, ref, b.astype(np.float64), cfg.l1, cfg.tv, dims)
+        assert rep["objective"] == pytest.approx(F, rel=1e-4)
+        assert np.abs(ref.imag).max() > 0.1 * np.abs(ref.real).max()    # the phase is reconstructed
+        # with and without the graph, with and without row skipping: the same bits
+        x2, _, _ = p.solve(torch.from_numpy(b).cuda(), cfg.l1, cfg.tv, iters, k_in, nonneg=False,
+                           flags=rihvr.RI_SOLVE_NO_GRAPH | rihvr.RI_SOLVE_DENSE)
+        assert torch.equal(x, x2)
+    finally:
+        p.close()
+
+
+def test_solve_given_start_and_gap_stop(torch_cuda):
+    torch = torch_cuda
+    g, cfg, x_true, b = complex_scene(4)
+    ref5 = co.fista(g, b.astype(np.float64), cfg.l1, cfg.tv, 5, 4)
+    p = rihvr.Plan(g)
+    try:
+        x0 = to_dev(torch, ref5)
+        x, rep, _ = p.solve(torch.from_numpy(b).cuda(), cfg.l1, cfg.tv, 6, 4, x=x0, nonneg=False)
+        ref = co.fista(g, b.astype(np.float64), cfg.l1, cfg.tv, 6, 4,
+                       x0=ref5.astype(np.complex64).astype(np.complex128))
+        assert rel_l2(to_host(x), ref) <= 1e-3
+        # stop at an objective gap against a reference value
+        _, r_long, _ = p.solve(torch.from_numpy(b).cuda(), cfg.l1, cfg.tv, 200, 4, nonneg=False)
+        f_ref = r_long["objective_min"]
+        _, r_gap, _ = p.solve(torch.from_numpy(b).cuda(), cfg.l1, cfg.tv, 200, 4, nonneg=False,
+                              f_ref=f_ref, gap_tol=1e-2, check_every=1)
+        assert r_gap["converged"] and r_gap["iters"] < 200 and r_gap["gap"] <= 1e-2
+    finally:
+        p.close()
+
+
+def test_rejections(torch_cuda):
+    torch = torch_cuda
+    g = cgeom(64, 64, 4)
+    for bad in (g.with_(tv_fgp=True), g.with_(dual_bf16=True)):
+        with pytest.raises(rihvr.RihvrError):
+            rihvr.Plan(bad)
+    p = rihvr.Plan(g)
+    try:
+        v = torch.zeros(p.shape, dtype=torch.float32, device="cuda")
+        with pytest.raises(rihvr.RihvrError):
+            p.prox(v, 0.5, 0.1, 0.1, 3, nonneg=True)
+        b = torch.zeros((g.ny, g.nx), dtype=torch.float32, device="cuda")
+        with pytest.raises(rihvr.RihvrError):
+            p.solve(b, 0.1, 0.1, 3, 3)                      # nonneg defaults to 1
+        with pytest.raises(rihvr.RihvrError):
+            p.solve(b, 0.1, 0.1, 3, 3, nonneg=False, flags=rihvr.RI_SOLVE_DUAL_WARM)
+        params = [p.solve_params(0.1, 0.1, 3, 3, nonneg=False)]
+        nbytes = rihvr.ri_workspace_size_batched(1, [p.handle], params)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        x = torch.empty(p.shape, dtype=torch.float32, device="cuda")
+        st = rihvr.ri_solve_batched(1, [p.handle], params, [b.data_ptr()], [x.data_ptr()], ws.data_ptr(), nbytes,
+                                    torch.cuda.current_stream().cuda_stream, None)
+        assert st == rihvr.RI_ERR_INVALID_ARG
+        with pytest.raises(rihvr.RihvrError):
+            p.autotune(5)
+    finally:
+        p.close()
