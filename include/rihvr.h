@@ -58,10 +58,20 @@ typedef enum {
   RI_ERR_NOT_CONVERGED = 7       /* the objective diverged (grew past 10x F(x0)) */
 } ri_status;
 
-/* Element type of a plan's arrays.  RI_F32 is the path this library computes
- * in (FP32 data, FP64 phase reduction and accumulations).  RI_F64 is part of
- * the interface but not built: ri_plan_create rejects it with
- * RI_ERR_INVALID_ARG. */
+/* Element type of a plan's arrays (every volume, hologram and spectrum argument).
+ * RI_F32: the fast path (FP32 data, FP64 phase reduction and accumulations).
+ * RI_F64: every array is double and every step computes in double, for telling
+ * defects from FP32 rounding (it agrees with the FP64 reference to ~1e-12):
+ * the same model from the same FP64 tables, but with plain complex transforms
+ * of whole planes (every plane's spectrum held in the workspace), the
+ * gradient-projection prox one step per two passes over memory, and the FISTA
+ * scalars, objective and stop tests on the host (ri_solve synchronises once
+ * per outer iteration when a gap stop or the restart needs the objective, and
+ * evaluates the objective of the returned iterate for the report; no graph,
+ * no row skipping, report.phase_ms stays 0).  RI_F64 plans take neither
+ * RI_TV_FGP nor RI_TV_DUAL_BF16; ri_forward_noalloc, ri_solve_batched,
+ * ri_plan_autotune, row stores and RI_SOLVE_DUAL_WARM reject them
+ * (RI_ERR_INVALID_ARG). */
 typedef enum { RI_F32 = 0, RI_F64 = 1 } ri_dtype;
 
 /* Geometry flags */

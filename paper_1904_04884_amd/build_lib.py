@@ -17,7 +17,7 @@ from pathlib import Path
 HERE = Path(__file__).resolve().parent
 CSRC = HERE / "csrc"
 OUT = HERE / "librihvr.so"
-SOURCES = ["kernels.hip", "tv.hip", "cplx.hip", "unet.hip", "track.hip", "abi.cpp", "unet.cpp"]
+SOURCES = ["kernels.hip", "tv.hip", "cplx.hip", "f64.hip", "unet.hip", "track.hip", "abi.cpp", "unet.cpp"]
 ARCH = "gfx950"
 
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -90,6 +90,9 @@ struct ri_plan {
   ri_tuning tune{kTvDefaultLevels, kTvDefaultBlocks, kColDefaultBlocks};
   double store_frac = 0.0;   // > 0: row-compressed iterates with room for this fraction of rows
   bool cplx = false;         // complex object: g.nz counts the planes of both parts
+  ri_dtype dtype = RI_F32;
+  double2* tw64x = nullptr;  // FP64 plans: exp(-2 pi i k / nx), k < nx
+  double2* tw64y = nullptr;  //             exp(-2 pi i k / ny), k < ny
   PlanTables tables() const { return PlanTables{theta, zc, tw_row, tw_col}; }
 };
 
@@ -106,6 +109,8 @@ static void free_plan(ri_plan* p) {
   if (p->zc) hipFree(p->zc);
   if (p->tw_row) hipFree(p->tw_row);
   if (p->tw_col) hipFree(p->tw_col);
+  if (p->tw64x) hipFree(p->tw64x);
+  if (p->tw64y) hipFree(p->tw64y);
   if (p->host_flag) hipHostFree(p->host_flag);
   delete p;
 }
@@ -150,11 +155,13 @@ extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_pla
   if (!out) return fail(RI_ERR_INVALID_ARG, "out is NULL");
   *out = nullptr;
   if (dtype != RI_F32 && dtype != RI_F64) return fail(RI_ERR_INVALID_ARG, "unknown dtype %d", (int)dtype);
-  if (dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "RI_F64 plans are not available in this build");
   ri_status vs = validate_geometry(g);
   if (vs != RI_OK) return vs;
+  if (dtype == RI_F64 && (g->flags & (RI_TV_FGP | RI_TV_DUAL_BF16)))
+    return fail(RI_ERR_INVALID_ARG, "RI_F64 plans take neither RI_TV_FGP nor RI_TV_DUAL_BF16");
   ri_plan* p = new ri_plan();
   p->g = *g;
+  p->dtype = dtype;
   p->m = g->nx / 2;
   // A complex object is two real volumes (real parts, imaginary parts): the
   // plan covers 2 nz planes, the second nz with the carrier a quarter cycle on
@@ -216,6 +223,22 @@ extern "C" ri_status ri_plan_create(const ri_geometry* g, ri_dtype dtype, ri_pla
   PLAN_TRY(hipMemcpy(p->tw_row, twr.data(), twr.size() * sizeof(float2), hipMemcpyHostToDevice));
   PLAN_TRY(hipMemcpy(p->tw_col, twc.data(), twc.size() * sizeof(float2), hipMemcpyHostToDevice));
   PLAN_TRY(hipStreamCreateWithFlags(&p->capture, hipStreamNonBlocking));
+  if (dtype == RI_F64) {
+    auto tw64 = [](int n, std::vector<double2>& out) {
+      out.resize(n);
+      for (int k = 0; k < n; ++k) {
+        const double a = 2.0 * M_PI * (double)k / (double)n;
+        out[k] = make_double2(std::cos(a), -std::sin(a));
+      }
+    };
+    std::vector<double2> t64x, t64y;
+    tw64(nx, t64x);
+    tw64(ny, t64y);
+    PLAN_TRY(hipMalloc(&p->tw64x, t64x.size() * sizeof(double2)));
+    PLAN_TRY(hipMalloc(&p->tw64y, t64y.size() * sizeof(double2)));
+    PLAN_TRY(hipMemcpy(p->tw64x, t64x.data(), t64x.size() * sizeof(double2), hipMemcpyHostToDevice));
+    PLAN_TRY(hipMemcpy(p->tw64y, t64y.data(), t64y.size() * sizeof(double2), hipMemcpyHostToDevice));
+  }
 
   // ||A||^2 = max over the grid of sum_j cos^2(phase_j) (FP64, on the device)
   double* pmax = nullptr;
@@ -298,7 +321,54 @@ static uint32_t store_cap(const ri_plan* p) {
   return (uint32_t)std::max(1.0, std::min(rows, std::ceil(p->store_frac * rows - 1e-6)));
 }
 
+struct Layout64 {
+  size_t X = 0, S = 0, hol = 0, y = 0, xp = 0, v = 0, u = 0, p[3] = {0, 0, 0}, part = 0, psum = 0, ptv = 0;
+  int nblk = 0;
+  size_t total = 0;
+};
+
+// Workspace of an FP64 plan: every plane's complex spectrum and a hologram
+// spectrum (A, A^T), the prox's u and dual, the solver's y, x_{k-1} (then
+// x_{k+1}), v, a hologram and per-block partials.  Volumes hold both parts.
+static Layout64 layout64(const ri_plan* p, ri_op op) {
+  Layout64 L;
+  const size_t nx = p->g.nx, ny = p->g.ny, nzp = p->g.nz;
+  const size_t vol = nx * ny * nzp * sizeof(double), np = nx * ny;
+  size_t off = 256;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align_up(off + bytes);
+    return o;
+  };
+  if (op == RI_OP_FORWARD || op == RI_OP_ADJOINT || op == RI_OP_SOLVE) {
+    L.X = take(2 * vol);
+    L.S = take(np * sizeof(double2));
+  }
+  if (op == RI_OP_PROX || op == RI_OP_SOLVE) {
+    L.u = take(vol);
+    const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
+    for (int k = 0; k < nc; ++k) L.p[k] = take(vol);
+  }
+  if (op == RI_OP_SOLVE) {
+    L.hol = take(np * sizeof(double));
+    L.y = take(vol);
+    L.xp = take(vol);
+    L.v = take(vol);
+    L.nblk = 1024;
+    L.part = take((size_t)L.nblk * sizeof(double));
+    L.psum = take((size_t)L.nblk * sizeof(double));
+    L.ptv = take((size_t)L.nblk * sizeof(double));
+  }
+  L.total = off;
+  return L;
+}
+
 static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0, bool dense_iterates = false) {
+  if (p->dtype == RI_F64) {   // only the size is used; the FP64 entry points take layout64
+    Layout L64;
+    L64.total = layout64(p, op).total;
+    return L64;
+  }
   if (op == RI_OP_AUTOTUNE) return make_layout(p, RI_OP_SOLVE, kColTuneMax, true);  // room for every candidate
   Layout L;
   const size_t nx = p->g.nx, ny = p->g.ny, nz = p->g.nz, m = p->m;
@@ -473,9 +543,220 @@ static hipError_t enqueue_forward(ri_plan* p, const Layout& L, void* ws, const f
   return launch_rows_c2r(m, ca, s);
 }
 
+// ---------------------------------------------------------------------------
+// FP64 plans: the same operator from the same FP64 tables, computed plainly in
+// double (f64.hip), with the unfused gradient-projection prox (cplx.hip) and a
+// FISTA loop driven from the host (scalars, objective and stop in FP64 on the
+// host; no graph).
+// ---------------------------------------------------------------------------
+static size_t elem_bytes(const ri_plan* p) { return p->dtype == RI_F64 ? sizeof(double) : sizeof(float); }
+
+static Plan64Tables tables64(const ri_plan* p) {
+  return Plan64Tables{p->theta, p->zc, p->tw64x, p->tw64y, p->g.nx, p->g.ny, p->m, p->g.nz};
+}
+
+static ri_status forward_f64(ri_plan* p, const void* xv, void* bv, void* ws, size_t ws_bytes, void* stream) {
+  const double* x = static_cast<const double*>(xv);
+  double* b = static_cast<double*>(bv);
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(double), hb = (size_t)p->g.nx * p->g.ny * sizeof(double);
+  ri_status st = check_common(p, x, b, ws, ws_bytes, RI_OP_FORWARD, vb, hb);
+  if (st != RI_OK) return st;
+  if (overlaps(x, vb, b, hb)) return fail(RI_ERR_INVALID_ARG, "x and b_out overlap");
+  const Layout64 L = layout64(p, RI_OP_FORWARD);
+  HIP_TRY(forward64(tables64(p), x, b, at<double2>(ws, L.X), at<double2>(ws, L.S), (hipStream_t)stream));
+  return RI_OK;
+}
+
+static ri_status adjoint_f64(ri_plan* p, const void* yv, void* xv, void* ws, size_t ws_bytes, void* stream) {
+  const double* y = static_cast<const double*>(yv);
+  double* x = static_cast<double*>(xv);
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(double), hb = (size_t)p->g.nx * p->g.ny * sizeof(double);
+  ri_status st = check_common(p, y, x, ws, ws_bytes, RI_OP_ADJOINT, hb, vb);
+  if (st != RI_OK) return st;
+  if (overlaps(y, hb, x, vb)) return fail(RI_ERR_INVALID_ARG, "y and x_out overlap");
+  const Layout64 L = layout64(p, RI_OP_ADJOINT);
+  HIP_TRY(adjoint64(tables64(p), y, x, at<double2>(ws, L.X), at<double2>(ws, L.S), (hipStream_t)stream));
+  return RI_OK;
+}
+
+static Prox64Args prox64_args(const ri_plan* p, const Layout64& L, void* ws, int nonneg, int inner, double step,
+                              double l1, double tv) {
+  Prox64Args a{};
+  const int parts = p->cplx ? 2 : 1;
+  a.u = at<double>(ws, L.u);
+  for (int k = 0; k < 3; ++k) a.p[k] = L.p[k] ? at<double>(ws, L.p[k]) : nullptr;
+  a.nx = p->g.nx;
+  a.ny = p->g.ny;
+  a.nz = p->g.nz / parts;
+  a.parts = parts;
+  a.tv2 = (p->g.flags & RI_TV2D) ? 1 : 0;
+  a.nonneg = nonneg;
+  a.inner_iters = inner;
+  a.step = step;
+  a.l1 = l1;
+  a.tv = tv;
+  return a;
+}
+
+static ri_status prox_f64(ri_plan* p, const ri_prox_params* pp, double step, const void* vv, void* xv, void* ws,
+                          size_t ws_bytes, void* stream) {
+  const double* v = static_cast<const double*>(vv);
+  double* x = static_cast<double*>(xv);
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(double);
+  ri_status st = check_common(p, v, x, ws, ws_bytes, RI_OP_PROX, vb, vb);
+  if (st != RI_OK) return st;
+  if (v != x && overlaps(v, vb, x, vb)) return fail(RI_ERR_INVALID_ARG, "v and x_out partially overlap");
+  if (!(step >= 0) || !std::isfinite(step) || !(pp->l1 >= 0) || !(pp->tv >= 0) || !std::isfinite(pp->l1) ||
+      !std::isfinite(pp->tv) || pp->inner_iters < 0)
+    return fail(RI_ERR_INVALID_ARG, "step, l1, tv must be finite and >= 0; inner_iters >= 0");
+  Prox64Args a = prox64_args(p, layout64(p, RI_OP_PROX), ws, pp->nonneg ? 1 : 0, pp->inner_iters, step, pp->l1,
+                             pp->tv);
+  a.v = v;
+  a.x = x;   // in place is allowed: the last launch reads only a voxel's own v
+  HIP_TRY(launch_prox64(a, (hipStream_t)stream));
+  return RI_OK;
+}
+
+// FISTA in FP64: x_k = prox(y_k - t A^T (A y_k - b)), s_{k+1} = (1 + sqrt(1 +
+// 4 s_k^2)) / 2, y_{k+1} = x_k + ((s_k - 1)/s_{k+1}) (x_k - x_{k-1}), from
+// x_0 = 0 or the given start (scaled).  The objective is evaluated (a forward
+// model and the partials of sum |x| and TV) when a gap stop or the restart
+// needs it, and for the returned iterate.
+static ri_status solve_f64(ri_plan* p, const ri_solve_params* sp, const double* b, double* x, void* ws, hipStream_t s,
+                           ri_solve_report* report) {
+  const Layout64 L = layout64(p, RI_OP_SOLVE);
+  const Plan64Tables t = tables64(p);
+  const int parts = p->cplx ? 2 : 1;
+  const int nzq = p->g.nz / parts;
+  const int tv2 = (p->g.flags & RI_TV2D) ? 1 : 0;
+  const size_t n = (size_t)p->g.nx * p->g.ny * p->g.nz, np = (size_t)p->g.nx * p->g.ny;
+  double2* X = at<double2>(ws, L.X);
+  double2* S = at<double2>(ws, L.S);
+  double* hol = at<double>(ws, L.hol);
+  double* y = at<double>(ws, L.y);
+  double* xb = at<double>(ws, L.xp);
+  double* v = at<double>(ws, L.v);
+  double* part = at<double>(ws, L.part);
+  double* psum = at<double>(ws, L.psum);
+  double* ptv = at<double>(ws, L.ptv);
+  const double tstep = 1.0 / p->lipschitz;
+  Prox64Args pa = prox64_args(p, L, ws, sp->nonneg ? 1 : 0, sp->inner_iters, tstep, sp->l1, sp->tv);
+  std::vector<double> h(3 * (size_t)L.nblk);
+  auto objective = [&](const double* xv, double* F) -> hipError_t {
+    hipError_t e = forward64(t, xv, hol, X, S, s);
+    if (e == hipSuccess) e = sqdist64(hol, b, np, part, L.nblk, s);
+    if (e == hipSuccess) e = launch_obj64(xv, p->g.nx, p->g.ny, nzq, parts, tv2, psum, ptv, L.nblk, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), part, (size_t)L.nblk * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h.data() + L.nblk, psum, (size_t)L.nblk * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(h.data() + 2 * L.nblk, ptv, (size_t)L.nblk * sizeof(double), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    double d = 0.0, a1 = 0.0, a2 = 0.0;
+    for (int i = 0; i < L.nblk; ++i) {
+      d += h[i];
+      a1 += h[L.nblk + i];
+      a2 += h[2 * L.nblk + i];
+    }
+    *F = 0.5 * d + sp->l1 * a1 + sp->tv * a2;
+    return hipSuccess;
+  };
+  // start
+  if (sp->init == RI_INIT_ZERO) HIP_TRY(fill64(x, 0.0, n, s));
+  else if (sp->x0_scale != 1.0) HIP_TRY(axpby64(x, sp->x0_scale, x, 0.0, x, n, s));
+  HIP_TRY(hipMemcpyAsync(y, x, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const bool restart = (sp->flags & RI_SOLVE_RESTART) != 0;
+  const bool gap_stop = sp->f_ref > 0.0;
+  const bool need_f = gap_stop || restart;
+  double f0 = 0.0, f_prev = 0.0, f_cur = std::nan(""), f_min = INFINITY;
+  int status = RI_OK, converged = 0, it = 0;
+  auto judge = [&](double F) {   // after F(x_it): history, stop tests
+    f_cur = F;
+    f_min = std::min(f_min, F);
+    if (!std::isfinite(F)) { status = RI_ERR_NONFINITE; return true; }
+    if (it == 0) f0 = F;
+    else if (F > 10.0 * f0 && F > 0.0) { status = RI_ERR_NOT_CONVERGED; return true; }
+    if (gap_stop && (F - sp->f_ref) / sp->f_ref <= sp->gap_tol) { converged = 1; return true; }
+    return false;
+  };
+  bool stop = false;
+  if (need_f) {
+    double F;
+    HIP_TRY(objective(x, &F));
+    stop = judge(F);
+    f_prev = F;
+  }
+  double* xc = x;    // x_k
+  double* xn = xb;   // x_{k+1} (held x_{k-1} until the prox writes it)
+  double sk = 1.0;
+  while (!stop && it < sp->max_iters) {
+    HIP_TRY(forward64(t, y, hol, X, S, s));
+    HIP_TRY(axpby64(hol, 1.0, hol, -1.0, b, np, s));          // r = A y - b
+    HIP_TRY(adjoint64(t, hol, v, X, S, s));                   // A^T r
+    HIP_TRY(axpby64(v, 1.0, y, -tstep, v, n, s));             // v = y - t A^T r
+    pa.v = v;
+    pa.x = xn;
+    HIP_TRY(launch_prox64(pa, s));
+    double s_new = 0.5 * (1.0 + std::sqrt(1.0 + 4.0 * sk * sk));
+    double beta = (sk - 1.0) / s_new;
+    ++it;
+    if (need_f) {
+      double F;
+      HIP_TRY(objective(xn, &F));
+      stop = judge(F);
+      if (restart && F > f_prev) {
+        s_new = 1.0;
+        beta = 0.0;
+      }
+      f_prev = F;
+    }
+    HIP_TRY(axpby64(y, 1.0 + beta, xn, -beta, xc, n, s));    // y = x_new + beta (x_new - x)
+    std::swap(xc, xn);
+    sk = s_new;
+  }
+  if (xc != x) HIP_TRY(hipMemcpyAsync(x, xc, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (!report) {
+    HIP_TRY(hipStreamSynchronize(s));
+    return RI_OK;
+  }
+  if (!need_f || !std::isfinite(f_cur)) {
+    double F;
+    HIP_TRY(objective(x, &F));
+    f_cur = F;
+    f_min = std::min(f_min, F);
+  }
+  std::vector<double> hx(n);
+  HIP_TRY(hipMemcpyAsync(hx.data(), x, n * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  size_t empty_rows = 0, empty_planes = 0;
+  const int nrow = p->g.ny * p->g.nz;
+  for (int r = 0; r < nrow; ++r) {
+    bool any = false;
+    for (int i = 0; i < p->g.nx && !any; ++i) any = hx[(size_t)r * p->g.nx + i] != 0.0;
+    empty_rows += !any;
+  }
+  for (int z = 0; z < p->g.nz; ++z) {
+    bool any = false;
+    for (size_t i = 0; i < np && !any; ++i) any = hx[(size_t)z * np + i] != 0.0;
+    empty_planes += !any;
+  }
+  std::memset(report, 0, sizeof(*report));
+  report->iters = it;
+  report->converged = converged;
+  report->objective = f_cur;
+  report->objective_min = f_min;
+  report->gap = gap_stop ? (f_cur - sp->f_ref) / sp->f_ref : std::nan("");
+  report->lipschitz = p->lipschitz;
+  report->empty_row_frac = (double)empty_rows / (double)nrow;
+  report->empty_plane_frac = (double)empty_planes / (double)p->g.nz;
+  return (ri_status)status;
+}
+
 extern "C" ri_status ri_forward(ri_plan* p, const void* xv, void* bv, void* ws, size_t ws_bytes,
                                 void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (p->dtype == RI_F64) return forward_f64(p, xv, bv, ws, ws_bytes, stream);
   const float* x = static_cast<const float*>(xv);
   float* b_out = static_cast<float*>(bv);
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
@@ -522,6 +803,7 @@ extern "C" size_t ri_forward_noalloc_max_scratch(void) { return kStaticScratchBy
 
 extern "C" ri_status ri_forward_noalloc(ri_plan* p, const void* xv, void* bv, void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (p->dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "ri_forward_noalloc takes RI_F32 plans only");
   const float* x = static_cast<const float*>(xv);
   float* b_out = static_cast<float*>(bv);
   if (!x || !b_out) return fail(RI_ERR_INVALID_ARG, "input or output pointer is NULL");
@@ -581,6 +863,7 @@ static hipError_t enqueue_adjoint(ri_plan* p, const Layout& L, void* ws, const f
 
 extern "C" ri_status ri_adjoint(ri_plan* p, const void* yv, void* xv, void* ws, size_t ws_bytes, void* stream) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (p->dtype == RI_F64) return adjoint_f64(p, yv, xv, ws, ws_bytes, stream);
   const float* y = static_cast<const float*>(yv);
   float* x_out = static_cast<float*>(xv);
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
@@ -598,6 +881,7 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   float* x_out = static_cast<float*>(xv);
   if (!pp) return fail(RI_ERR_INVALID_ARG, "params is NULL");
   if (p->cplx && pp->nonneg) return fail(RI_ERR_INVALID_ARG, "nonneg has no meaning for a complex object (pass 0)");
+  if (p->dtype == RI_F64) return prox_f64(p, pp, step, vv, xv, ws, ws_bytes, stream);
   const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float);
   ri_status st = check_common(p, v, x_out, ws, ws_bytes, RI_OP_PROX, vb, vb);
   if (st != RI_OK) return st;
@@ -897,10 +1181,13 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
                                 size_t ws_bytes) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
   if (!sp) return fail(RI_ERR_INVALID_ARG, "params is NULL");
-  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * sizeof(float), hb = (size_t)p->g.nx * p->g.ny * sizeof(float);
+  const size_t es = elem_bytes(p);
+  const size_t vb = (size_t)p->g.nx * p->g.ny * p->g.nz * es, hb = (size_t)p->g.nx * p->g.ny * es;
   ri_status st = check_common(p, b, x, ws, ws_bytes, RI_OP_SOLVE, hb, vb);
   if (st != RI_OK) return st;
   if (overlaps(b, hb, x, vb)) return fail(RI_ERR_INVALID_ARG, "b and x_inout overlap");
+  if (p->dtype == RI_F64 && (sp->flags & RI_SOLVE_DUAL_WARM))
+    return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_F64 plans");
   if (!(sp->l1 >= 0) || !(sp->tv >= 0) || !std::isfinite(sp->l1) || !std::isfinite(sp->tv))
     return fail(RI_ERR_INVALID_ARG, "l1 and tv must be finite and >= 0");
   if (sp->max_iters < 0 || sp->inner_iters < 0) return fail(RI_ERR_INVALID_ARG, "iteration counts must be >= 0");
@@ -1046,6 +1333,8 @@ extern "C" ri_status ri_solve(ri_plan* p, const ri_solve_params* sp, const void*
   float* x_inout = static_cast<float*>(xv);
   ri_status vs = validate_solve(p, sp, b, x_inout, ws, ws_bytes);
   if (vs != RI_OK) return vs;
+  if (p->dtype == RI_F64)
+    return solve_f64(p, sp, static_cast<const double*>(bv), static_cast<double*>(xv), ws, (hipStream_t)stream, report);
   hipStream_t s = (hipStream_t)stream;
   SolveCtx c{};
   c.p = p;
@@ -1261,6 +1550,7 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     vs = validate_solve(p, &params[i], b[i], x_inout[i], base + off, fb);
     if (vs != RI_OK) return vs;
     if (p->cplx) return fail(RI_ERR_INVALID_ARG, "frame %d: RI_COMPLEX plans are solved one by one (ri_solve)", i);
+    if (p->dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "frame %d: RI_F64 plans are solved one by one (ri_solve)", i);
     if (p->device != plans[0]->device) return fail(RI_ERR_INVALID_ARG, "plans on different devices");
     SolveCtx& c = ctx[i];
     c.p = p;
@@ -1493,6 +1783,8 @@ extern "C" ri_status ri_plan_set_storage(ri_plan* p, double row_fraction) {
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
   if (!(row_fraction >= 0.0 && row_fraction <= 1.0))
     return fail(RI_ERR_INVALID_ARG, "row_fraction=%g must be in [0, 1]", row_fraction);
+  if (row_fraction > 0.0 && p->dtype == RI_F64)
+    return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_F64 plans");
   p->store_frac = row_fraction;
   drop_graph(p);
   return RI_OK;
@@ -1626,6 +1918,7 @@ extern "C" ri_status ri_plan_autotune(ri_plan* p, int32_t inner_iters, const cha
   if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
   if (inner_iters < 0) return fail(RI_ERR_INVALID_ARG, "inner_iters=%d must be >= 0", inner_iters);
   if (p->cplx) return fail(RI_ERR_INVALID_ARG, "RI_COMPLEX plans have no launch shapes to tune");
+  if (p->dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "RI_F64 plans have no launch shapes to tune");
   const Layout LT = make_layout(p, RI_OP_AUTOTUNE);
   if (!ws) return fail(RI_ERR_INVALID_ARG, "workspace is NULL (needs %zu bytes)", LT.total);
   if (ws_bytes < LT.total) return fail(RI_ERR_WORKSPACE_TOO_SMALL, "workspace %zu bytes < %zu required", ws_bytes, LT.total);

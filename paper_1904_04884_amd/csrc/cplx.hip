@@ -1,25 +1,28 @@
-// Complex-valued object (absorption and phase).
+// Unfused gradient-projection TV prox and objective partials, templated on the
+// element type T (float, double) and the number of parts NP (1: real object,
+// 2: complex object).  They serve the complex object in FP32 and every FP64
+// plan.
 //
-// A complex plan holds the object as two real volumes of nz planes, the real
-// parts and then the imaginary parts ([2][nz][ny][nx] FP32).  The hologram
-// model and its adjoint need no kernels of their own: Re(IFFT2(FFT2(i y) H_j))
-// is the real model with H_j multiplied by i, a carrier phase advanced by a
-// quarter cycle, so the plan gives its second nz planes the carriers c_j + 1/4
-// and the real kernels run on all 2 nz planes (their adjoint then returns the
-// real and imaginary parts of A^T r).  What is complex is the regulariser
-// (section "Methodology"): the l1 norm of Eq. (3) sums moduli, the TV of
-// Eq. (4) takes the modulus of complex differences, and the soft threshold of
-// Eq. (8) shrinks the modulus and keeps the phase.
+// Complex object.  A complex plan holds the object as two real volumes of nz
+// planes, the real parts and then the imaginary parts ([2][nz][ny][nx]).  The
+// hologram model and its adjoint need no kernels of their own:
+// Re(IFFT2(FFT2(i y) H_j)) is the real model with H_j multiplied by i, a
+// carrier phase advanced by a quarter cycle, so the plan gives its second nz
+// planes the carriers c_j + 1/4 and the real kernels run on all 2 nz planes
+// (their adjoint then returns the real and imaginary parts of A^T r).  What is
+// complex is the regulariser (section "Methodology"): the l1 norm of Eq. (3)
+// sums moduli, the TV of Eq. (4) takes the modulus of complex differences, and
+// the soft threshold of Eq. (8) shrinks the modulus and keeps the phase.
 //
-// The TV prox is gradient projection on a complex dual, one complex value per
-// direction, projected jointly on the unit ball of C^dims.  One step is two
-// launches: u = v - tau D^T p into a scratch volume, then
-// p <- (p + D u / (4 dims tau)) / max(1, |.|) in place (a voxel's new dual
-// needs only its own dual and u at its forward neighbours).  The last launch
-// forms u once more and writes the shrinkage of its modulus, with the
-// occupancy flags of both parts.  These kernels stream whole volumes per step
-// (no temporal blocking): the complex path is for parity and for
-// complex-object work, not the benchmark's real path.
+// The TV prox is gradient projection on the dual, one value per part and
+// direction, projected jointly on the unit ball.  One step is two launches:
+// u = v - tau D^T p into a scratch volume, then p <- (p + D u / (4 dims tau)) /
+// max(1, |.|) in place (a voxel's new dual needs only its own dual and u at its
+// forward neighbours).  The last launch forms u once more and writes the
+// threshold (real: max(u - thr, 0) or the signed form; complex: the shrinkage
+// of the modulus), with the occupancy flags.  These kernels stream whole
+// volumes per step (no temporal blocking): they are the complex-object and
+// FP64 paths, not the benchmark's real FP32 path.
 #include <hip/hip_runtime.h>
 
 #include "rihvr_internal.h"
@@ -27,153 +30,177 @@
 namespace rihvr {
 namespace {
 
-constexpr int kCThreads = 256;
+constexpr int kGThreads = 256;
 
-struct CtvArgs {
-  const float* v;        // input [2][nz][ny][nx]; nullptr: vol[st->prev]
-  float* x;              // output; nullptr: vol[st->next]
-  float* vol[3];
+template <class T>
+struct GpArgs {
+  const T* v;            // input [NP][nz][ny][nx]; nullptr: vol[st->prev]
+  T* x;                  // output; nullptr: vol[st->next]
+  T* vol[3];
   const SolveState* st;
-  float* u;              // scratch [2][nz][ny][nx]
-  float* p[3];           // dual components [2][nz][ny][nx] each (p[2] unused in 2D)
-  uint8_t* rowflag;      // nullable: [2 nz][ny], set where a row of a part is non-zero
-  uint8_t* planeflag;    // [2 nz]
+  T* u;                  // scratch [NP][nz][ny][nx]
+  T* p[3];               // dual components [NP][nz][ny][nx] each (p[2] unused in 2D)
+  uint8_t* rowflag;      // nullable: [NP nz][ny], set where a row of a part is non-zero
+  uint8_t* planeflag;    // [NP nz]
   int nx, ny, nz;        // nz: planes of one part
   int tv2;
+  int nonneg;            // real object: x >= 0
   int first;             // the dual is zero (no step taken yet)
-  float tau, c, thr;
+  T tau, c, thr;
 };
 
 __device__ __forceinline__ bool done(const SolveState* st) { return st != nullptr && st->done != 0; }
 
-__device__ __forceinline__ const float* in_of(const CtvArgs& a) {
-  return a.v != nullptr ? a.v : pick3<float>(a.vol[0], a.vol[1], a.vol[2], a.st->prev);
+template <class T>
+__device__ __forceinline__ const T* in_of(const GpArgs<T>& a) {
+  return a.v != nullptr ? a.v : pick3<T>(a.vol[0], a.vol[1], a.vol[2], a.st->prev);
 }
-__device__ __forceinline__ float* out_of(const CtvArgs& a) {
-  return a.x != nullptr ? a.x : pick3<float>(a.vol[0], a.vol[1], a.vol[2], a.st->next);
+template <class T>
+__device__ __forceinline__ T* out_of(const GpArgs<T>& a) {
+  return a.x != nullptr ? a.x : pick3<T>(a.vol[0], a.vol[1], a.vol[2], a.st->next);
 }
+
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float sqrtT(float a) { return sqrtf(a); }
+__device__ __forceinline__ double sqrtT(double a) { return sqrt(a); }
 
 // -(D^T p) at voxel i of the part starting at offset o: the backward
 // differences of the dual, zero where the forward difference is not defined.
-__device__ __forceinline__ float neg_div(const CtvArgs& a, size_t i, size_t o, int x, int y, int z) {
+template <class T>
+__device__ __forceinline__ T neg_div(const GpArgs<T>& a, size_t i, size_t o, int x, int y, int z) {
   const size_t plane = (size_t)a.nx * a.ny;
-  const float* px = a.p[0] + o;
-  const float* py = a.p[1] + o;
-  float d = (x + 1 < a.nx ? px[i] : 0.f) - (x > 0 ? px[i - 1] : 0.f);
-  d += (y + 1 < a.ny ? py[i] : 0.f) - (y > 0 ? py[i - a.nx] : 0.f);
+  const T* px = a.p[0] + o;
+  const T* py = a.p[1] + o;
+  T d = (x + 1 < a.nx ? px[i] : T(0)) - (x > 0 ? px[i - 1] : T(0));
+  d += (y + 1 < a.ny ? py[i] : T(0)) - (y > 0 ? py[i - a.nx] : T(0));
   if (!a.tv2) {
-    const float* pz = a.p[2] + o;
-    d += (z + 1 < a.nz ? pz[i] : 0.f) - (z > 0 ? pz[i - plane] : 0.f);
+    const T* pz = a.p[2] + o;
+    d += (z + 1 < a.nz ? pz[i] : T(0)) - (z > 0 ? pz[i - plane] : T(0));
   }
   return d;
 }
 
-__global__ void __launch_bounds__(kCThreads) k_ctv_u(CtvArgs a) {
+template <class T, int NP>
+__global__ void __launch_bounds__(kGThreads) k_gp_u(GpArgs<T> a) {
   if (done(a.st)) return;
   const size_t n = (size_t)a.nx * a.ny * a.nz;
-  const float* __restrict__ v = in_of(a);
+  const T* __restrict__ v = in_of(a);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
-    for (int part = 0; part < 2; ++part) {
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
       const size_t o = part * n;
-      a.u[o + i] = a.first ? v[o + i] : fmaf(a.tau, neg_div(a, i, o, x, y, z), v[o + i]);
+      a.u[o + i] = a.first ? v[o + i] : fmaT(a.tau, neg_div(a, i, o, x, y, z), v[o + i]);
     }
   }
 }
 
-__global__ void __launch_bounds__(kCThreads) k_ctv_p(CtvArgs a) {
+template <class T, int NP>
+__global__ void __launch_bounds__(kGThreads) k_gp_p(GpArgs<T> a) {
   if (done(a.st)) return;
   const size_t n = (size_t)a.nx * a.ny * a.nz;
   const size_t plane = (size_t)a.nx * a.ny;
   const int nd = a.tv2 ? 2 : 3;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / plane);
-    float q[3][2];
-    float n2 = 0.f;
-    for (int part = 0; part < 2; ++part) {
-      const float* __restrict__ u = a.u + part * n;
-      const float uc = u[i];
-      const float g[3] = {x + 1 < a.nx ? u[i + 1] - uc : 0.f, y + 1 < a.ny ? u[i + a.nx] - uc : 0.f,
-                          (!a.tv2 && z + 1 < a.nz) ? u[i + plane] - uc : 0.f};
+    T q[3][NP];
+    T n2 = T(0);
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      const T* __restrict__ u = a.u + part * n;
+      const T uc = u[i];
+      const T g[3] = {x + 1 < a.nx ? u[i + 1] - uc : T(0), y + 1 < a.ny ? u[i + a.nx] - uc : T(0),
+                      (!a.tv2 && z + 1 < a.nz) ? u[i + plane] - uc : T(0)};
       for (int d = 0; d < nd; ++d) {
-        const float p0 = a.first ? 0.f : a.p[d][part * n + i];
-        q[d][part] = fmaf(a.c, g[d], p0);
-        n2 = fmaf(q[d][part], q[d][part], n2);
+        const T p0 = a.first ? T(0) : a.p[d][part * n + i];
+        q[d][part] = fmaT(a.c, g[d], p0);
+        n2 = fmaT(q[d][part], q[d][part], n2);
       }
     }
-    const float inv = 1.f / fmaxf(1.f, sqrtf(n2));
+    const T s = n2 > T(1) ? sqrtT(n2) : T(1);
     for (int d = 0; d < nd; ++d)
-      for (int part = 0; part < 2; ++part) a.p[d][part * n + i] = q[d][part] * inv;
+#pragma unroll
+      for (int part = 0; part < NP; ++part) a.p[d][part * n + i] = q[d][part] / s;
   }
 }
 
-// u once more, then the complex shrinkage (1 - thr/|u|)_+ u and the flags.
-// In place is allowed (a voxel reads only its own v).
-__global__ void __launch_bounds__(kCThreads) k_ctv_final(CtvArgs a) {
+// u once more, then the threshold and the flags.  In place is allowed (a
+// voxel reads only its own v).
+template <class T, int NP>
+__global__ void __launch_bounds__(kGThreads) k_gp_final(GpArgs<T> a) {
   if (done(a.st)) return;
   const size_t n = (size_t)a.nx * a.ny * a.nz;
-  const float* v = in_of(a);
-  float* xo = out_of(a);
+  const T* v = in_of(a);
+  T* xo = out_of(a);
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / ((size_t)a.nx * a.ny));
-    float ur = v[i], ui = v[n + i];
-    if (!a.first) {
-      ur = fmaf(a.tau, neg_div(a, i, 0, x, y, z), ur);
-      ui = fmaf(a.tau, neg_div(a, i, n, x, y, z), ui);
+    T u[NP], r[NP];
+    T m2 = T(0);
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      u[part] = v[part * n + i];
+      if (!a.first) u[part] = fmaT(a.tau, neg_div(a, i, part * n, x, y, z), u[part]);
+      m2 = fmaT(u[part], u[part], m2);
     }
-    const float mod = sqrtf(fmaf(ur, ur, ui * ui));
-    float xr = 0.f, xi = 0.f;
-    if (mod > a.thr) {
-      const float s = 1.f - a.thr / mod;
-      xr = s * ur;
-      xi = s * ui;
-    }
-    xo[i] = xr;
-    xo[n + i] = xi;
-    if (a.rowflag != nullptr) {
-      if (xr != 0.f) {
-        a.rowflag[(size_t)z * a.ny + y] = 1;
-        a.planeflag[z] = 1;
+    if constexpr (NP == 1) {
+      if (a.nonneg) {
+        r[0] = u[0] - a.thr > T(0) ? u[0] - a.thr : T(0);
+      } else {
+        const T m = u[0] < T(0) ? -u[0] : u[0];
+        r[0] = m > a.thr ? (u[0] < T(0) ? -(m - a.thr) : m - a.thr) : T(0);
       }
-      if (xi != 0.f) {
-        a.rowflag[(size_t)(a.nz + z) * a.ny + y] = 1;
-        a.planeflag[a.nz + z] = 1;
+    } else {
+      const T mod = sqrtT(m2);
+      const T s = mod > a.thr ? T(1) - a.thr / mod : T(0);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) r[part] = s * u[part];
+    }
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      xo[part * n + i] = r[part];
+      if (a.rowflag != nullptr && r[part] != T(0)) {
+        a.rowflag[(size_t)(part * a.nz + z) * a.ny + y] = 1;
+        a.planeflag[part * a.nz + z] = 1;
       }
     }
   }
 }
 
-// Per-block FP64 partials of sum |x| and of the complex TV of x (the solver's
-// iterate x_it before the scalar kernel of its iteration, or x0 outside one).
-struct CObjArgs {
-  const float* x0; const float* x1; const float* x2;
+// Per-block FP64 partials of sum |x| and TV(x) (the solver's iterate x_it
+// before the scalar kernel of its iteration, or x0 outside one).
+template <class T>
+struct ObjPartArgs {
+  const T* x0; const T* x1; const T* x2;
   const SolveState* st;
   double* psum; double* ptv;
   int nx, ny, nz;        // nz: planes of one part
   int tv2;
 };
 
-__global__ void __launch_bounds__(kCThreads) k_cobj(CObjArgs a) {
+template <class T, int NP>
+__global__ void __launch_bounds__(kGThreads) k_gp_obj(ObjPartArgs<T> a) {
   if (done(a.st)) return;
-  __shared__ double red[2][kCThreads / 64];
-  const float* __restrict__ xv = a.st != nullptr ? pick3<const float>(a.x0, a.x1, a.x2, a.st->it % 3) : a.x0;
+  __shared__ double red[2][kGThreads / 64];
+  const T* __restrict__ xv = a.st != nullptr ? pick3<const T>(a.x0, a.x1, a.x2, a.st->it % 3) : a.x0;
   const size_t n = (size_t)a.nx * a.ny * a.nz;
   const size_t plane = (size_t)a.nx * a.ny;
   double s_acc = 0.0, t_acc = 0.0;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
     const int x = (int)(i % a.nx), y = (int)((i / a.nx) % a.ny), z = (int)(i / plane);
-    float g2 = 0.f, m2 = 0.f;
-    for (int part = 0; part < 2; ++part) {
-      const float* u = xv + part * n;
-      const float c = u[i];
-      m2 = fmaf(c, c, m2);
-      const float gx = x + 1 < a.nx ? u[i + 1] - c : 0.f;
-      const float gy = y + 1 < a.ny ? u[i + a.nx] - c : 0.f;
-      const float gz = (!a.tv2 && z + 1 < a.nz) ? u[i + plane] - c : 0.f;
-      g2 = fmaf(gx, gx, fmaf(gy, gy, fmaf(gz, gz, g2)));
+    T g2 = T(0), m2 = T(0);
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      const T* u = xv + part * n;
+      const T c = u[i];
+      m2 = fmaT(c, c, m2);
+      const T gx = x + 1 < a.nx ? u[i + 1] - c : T(0);
+      const T gy = y + 1 < a.ny ? u[i + a.nx] - c : T(0);
+      const T gz = (!a.tv2 && z + 1 < a.nz) ? u[i + plane] - c : T(0);
+      g2 = fmaT(gx, gx, fmaT(gy, gy, fmaT(gz, gz, g2)));
     }
-    s_acc += (double)sqrtf(m2);
-    t_acc += (double)sqrtf(g2);
+    s_acc += (double)sqrtT(m2);
+    t_acc += (double)sqrtT(g2);
   }
   for (int off = 32; off > 0; off >>= 1) {
     s_acc += __shfl_down(s_acc, off, 64);
@@ -187,7 +214,7 @@ __global__ void __launch_bounds__(kCThreads) k_cobj(CObjArgs a) {
   __syncthreads();
   if (threadIdx.x == 0) {
     double s = 0.0, t = 0.0;
-    for (int w = 0; w < kCThreads / 64; ++w) {
+    for (int w = 0; w < kGThreads / 64; ++w) {
       s += red[0][w];
       t += red[1][w];
     }
@@ -196,15 +223,29 @@ __global__ void __launch_bounds__(kCThreads) k_cobj(CObjArgs a) {
   }
 }
 
-int cgrid(size_t n) {
-  const size_t b = (n + kCThreads - 1) / kCThreads;
+int ggrid(size_t n) {
+  const size_t b = (n + kGThreads - 1) / kGThreads;
   return (int)(b > 8192 ? 8192 : (b == 0 ? 1 : b));
+}
+
+template <class T, int NP>
+hipError_t run_gp(GpArgs<T> a, int K, hipStream_t s, int* launches) {
+  const dim3 g(ggrid((size_t)a.nx * a.ny * a.nz)), b(kGThreads);
+  for (int k = 0; k < K; ++k) {
+    a.first = k == 0 ? 1 : 0;
+    hipLaunchKernelGGL((k_gp_u<T, NP>), g, b, 0, s, a);
+    hipLaunchKernelGGL((k_gp_p<T, NP>), g, b, 0, s, a);
+  }
+  a.first = K == 0 ? 1 : 0;
+  hipLaunchKernelGGL((k_gp_final<T, NP>), g, b, 0, s, a);
+  if (launches) *launches = 2 * K + 1;
+  return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t launch_cprox(const ProxArgs& pa, hipStream_t s, int* launches) {
-  CtvArgs a{};
+  GpArgs<float> a{};
   a.v = pa.v;
   a.x = pa.x;
   for (int k = 0; k < 3; ++k) a.vol[k] = pa.vol[k];
@@ -222,20 +263,11 @@ hipError_t launch_cprox(const ProxArgs& pa, hipStream_t s, int* launches) {
   a.tau = (float)tau;
   a.c = K > 0 ? (float)(1.0 / ((a.tv2 ? 8.0 : 12.0) * tau)) : 0.f;
   a.thr = (float)(pa.step * pa.l1);
-  const dim3 g(cgrid((size_t)a.nx * a.ny * a.nz)), b(kCThreads);
-  for (int k = 0; k < K; ++k) {
-    a.first = k == 0 ? 1 : 0;
-    hipLaunchKernelGGL(k_ctv_u, g, b, 0, s, a);
-    hipLaunchKernelGGL(k_ctv_p, g, b, 0, s, a);
-  }
-  a.first = K == 0 ? 1 : 0;
-  hipLaunchKernelGGL(k_ctv_final, g, b, 0, s, a);
-  if (launches) *launches = 2 * K + 1;
-  return hipGetLastError();
+  return run_gp<float, 2>(a, K, s, launches);
 }
 
 hipError_t launch_cobj(const ObjArgs& oa, int nblocks, hipStream_t s) {
-  CObjArgs a{};
+  ObjPartArgs<float> a{};
   a.x0 = oa.x0;
   a.x1 = oa.x1;
   a.x2 = oa.x2;
@@ -246,7 +278,41 @@ hipError_t launch_cobj(const ObjArgs& oa, int nblocks, hipStream_t s) {
   a.ny = oa.ny;
   a.nz = oa.nz / 2;
   a.tv2 = oa.tv2;
-  hipLaunchKernelGGL(k_cobj, dim3(nblocks > 0 ? nblocks : 1), dim3(kCThreads), 0, s, a);
+  hipLaunchKernelGGL((k_gp_obj<float, 2>), dim3(nblocks > 0 ? nblocks : 1), dim3(kGThreads), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_prox64(const Prox64Args& pa, hipStream_t s) {
+  GpArgs<double> a{};
+  a.v = pa.v;
+  a.x = pa.x;
+  a.u = pa.u;
+  for (int k = 0; k < 3; ++k) a.p[k] = pa.p[k];
+  a.nx = pa.nx;
+  a.ny = pa.ny;
+  a.nz = pa.nz;
+  a.tv2 = pa.tv2;
+  a.nonneg = pa.nonneg;
+  const double tau = pa.step * pa.tv;
+  const int K = (tau > 0.0 && pa.inner_iters > 0) ? pa.inner_iters : 0;
+  a.tau = tau;
+  a.c = K > 0 ? 1.0 / ((pa.tv2 ? 8.0 : 12.0) * tau) : 0.0;
+  a.thr = pa.step * pa.l1;
+  return pa.parts == 2 ? run_gp<double, 2>(a, K, s, nullptr) : run_gp<double, 1>(a, K, s, nullptr);
+}
+
+hipError_t launch_obj64(const double* x, int nx, int ny, int nz, int parts, int tv2, double* psum, double* ptv,
+                        int nblocks, hipStream_t s) {
+  ObjPartArgs<double> a{};
+  a.x0 = a.x1 = a.x2 = x;
+  a.psum = psum;
+  a.ptv = ptv;
+  a.nx = nx;
+  a.ny = ny;
+  a.nz = nz;
+  a.tv2 = tv2;
+  if (parts == 2) hipLaunchKernelGGL((k_gp_obj<double, 2>), dim3(nblocks), dim3(kGThreads), 0, s, a);
+  else hipLaunchKernelGGL((k_gp_obj<double, 1>), dim3(nblocks), dim3(kGThreads), 0, s, a);
   return hipGetLastError();
 }
 

@@ -342,4 +342,37 @@ hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fg
 hipError_t launch_cprox(const ProxArgs& a, hipStream_t s, int* launches);
 hipError_t launch_cobj(const ObjArgs& a, int nblocks, hipStream_t s);
 
+// FP64 plans (f64.hip, cplx.hip): plain complex transforms of whole planes,
+// the filter from the same FP64 tables; unfused gradient-projection prox.
+struct Plan64Tables {
+  const double* theta;   // [ny][nx/2 + 1]
+  const double2* zc;     // [nzp] (z_j, carrier phase c_j)
+  const double2* tw_x;   // [nx] exp(-2 pi i k / nx)
+  const double2* tw_y;   // [ny]
+  int nx, ny, m, nzp;    // nzp: planes of every part together
+};
+size_t f64_spectra_bytes(const Plan64Tables& t);
+// b = A x (x: [nzp][ny][nx], b: [ny][nx]); X: [nzp][ny][nx] complex scratch,
+// S: [ny][nx] complex scratch.
+hipError_t forward64(const Plan64Tables& t, const double* x, double* b, double2* X, double2* S, hipStream_t s);
+// x = A^T y, same scratch.
+hipError_t adjoint64(const Plan64Tables& t, const double* y, double* x, double2* X, double2* S, hipStream_t s);
+hipError_t axpby64(double* out, double a, const double* x, double b, const double* y, size_t n, hipStream_t s);
+hipError_t fill64(double* out, double v, size_t n, hipStream_t s);
+// per-block partials of sum (x - y)^2 in part[nblocks]
+hipError_t sqdist64(const double* x, const double* y, size_t n, double* part, int nblocks, hipStream_t s);
+struct Prox64Args {
+  const double* v; double* x;   // [parts][nz][ny][nx]; x may be v
+  double* u;                    // scratch, as v
+  double* p[3];                 // dual components, as v (p[2] unused in 2D)
+  int nx, ny, nz;               // nz: planes of one part
+  int parts;                    // 1: real object, 2: complex object
+  int tv2, nonneg, inner_iters;
+  double step, l1, tv;
+};
+hipError_t launch_prox64(const Prox64Args& a, hipStream_t s);
+// per-block partials of sum |x| and TV(x) in psum / ptv [nblocks]
+hipError_t launch_obj64(const double* x, int nx, int ny, int nz, int parts, int tv2, double* psum, double* ptv,
+                        int nblocks, hipStream_t s);
+
 }  // namespace rihvr

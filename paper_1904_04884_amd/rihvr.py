@@ -350,13 +350,16 @@ def geometry_struct(geom) -> ri_geometry:
 
 
 class Plan:
-    """A plan plus lazily allocated (torch) workspaces for one geometry."""
+    """A plan plus lazily allocated (torch) workspaces for one geometry.
+    dtype RI_F64: every array argument is float64 (the FP64 path)."""
 
-    def __init__(self, geom):
+    def __init__(self, geom, dtype=RI_F32):
         import torch
         self.torch = torch
         self.geom = geom
-        self.handle = ri_plan_create(geometry_struct(geom))
+        self.dtype = int(dtype)
+        self.tdtype = torch.float64 if self.dtype == RI_F64 else torch.float32
+        self.handle = ri_plan_create(geometry_struct(geom), self.dtype)
         self.lipschitz = ri_plan_lipschitz(self.handle)
         self._ws = {}
 
@@ -418,15 +421,15 @@ class Plan:
 
     def _chk(self, t, shape):
         torch = self.torch
-        if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
-            raise ValueError(f"expected contiguous float32 cuda tensor of shape {shape}, got "
+        if not (t.is_cuda and t.dtype == self.tdtype and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"expected contiguous {self.tdtype} cuda tensor of shape {shape}, got "
                              f"{tuple(t.shape)} {t.dtype} {t.device}")
 
     def forward(self, x, out=None):
         torch = self.torch
         g = self.geom
         self._chk(x, self.shape)
-        out = torch.empty((g.ny, g.nx), dtype=torch.float32, device="cuda") if out is None else out
+        out = torch.empty((g.ny, g.nx), dtype=self.tdtype, device="cuda") if out is None else out
         ws, n = self.workspace(RI_OP_FORWARD)
         _check(ri_forward(self.handle, x.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                           _stream_handle(torch)), "ri_forward")
@@ -435,7 +438,7 @@ class Plan:
     def adjoint(self, y, out=None):
         torch = self.torch
         self._chk(y, (self.geom.ny, self.geom.nx))
-        out = torch.empty(self.shape, dtype=torch.float32, device="cuda") if out is None else out
+        out = torch.empty(self.shape, dtype=self.tdtype, device="cuda") if out is None else out
         ws, n = self.workspace(RI_OP_ADJOINT)
         _check(ri_adjoint(self.handle, y.data_ptr(), out.data_ptr(), ws.data_ptr(), ws.numel(),
                           _stream_handle(torch)), "ri_adjoint")
@@ -463,7 +466,7 @@ class Plan:
         self._chk(b, (self.geom.ny, self.geom.nx))
         init = RI_INIT_ZERO
         if x is None:
-            x = torch.empty(self.shape, dtype=torch.float32, device="cuda")
+            x = torch.empty(self.shape, dtype=self.tdtype, device="cuda")
         else:
             self._chk(x, self.shape)
             init = RI_INIT_GIVEN
