@@ -234,6 +234,25 @@ ri_status ri_plan_set_tuning(ri_plan* plan, const ri_tuning* tuning);
  * RI_ERR_INVALID_ARG for a fraction outside [0, 1] or NaN.
  */
 ri_status ri_plan_set_storage(ri_plan* plan, double row_fraction);
+
+/*
+ * The paper regularises each plane with its own 2D TV and computes the prox
+ * one plane at a time, so that its dual needs the memory of one plane (section
+ * "Methodology", the paragraph after Eq. 8).  For RI_TV2D plans, planes > 0
+ * makes the prox (ri_prox_fused_lasso and inside ri_solve) run on groups of
+ * `planes` planes in turn, each group taking all its dual steps before the
+ * next starts, with the dual sets of the workspace holding `planes` planes
+ * instead of nz (the dual shrinks from 4 volumes to 4 planes/nz of one).
+ * Results are bit-identical to planes = 0 (the planes do not interact); the
+ * solver's objective sums the same terms in another grouping (within FP64
+ * rounding).  RI_ERR_INVALID_ARG for planes < 0, for planes > 0 on a plan
+ * without RI_TV2D, with RI_TV_FGP, RI_COMPLEX or RI_F64; ri_solve rejects
+ * RI_SOLVE_DUAL_WARM and row stores with a plane-group dual, ri_solve_batched
+ * such plans.  Drops the plan's cached solve graph; changes the workspace
+ * sizes of RI_OP_PROX, RI_OP_SOLVE and RI_OP_AUTOTUNE.
+ */
+ri_status ri_plan_set_dual_planes(ri_plan* plan, int32_t planes);
+ri_status ri_plan_get_dual_planes(const ri_plan* plan, int32_t* planes);
 ri_status ri_plan_get_storage(const ri_plan* plan, double* row_fraction);
 
 typedef struct {

@@ -91,6 +91,7 @@ struct ri_plan {
   double store_frac = 0.0;   // > 0: row-compressed iterates with room for this fraction of rows
   bool cplx = false;         // complex object: g.nz counts the planes of both parts
   ri_dtype dtype = RI_F32;
+  int dual_planes = 0;       // RI_TV2D: planes whose TV dual is held at a time (0: the volume)
   double2* tw64x = nullptr;  // FP64 plans: exp(-2 pi i k / nx), k < nx
   double2* tw64y = nullptr;  //             exp(-2 pi i k / ny), k < ny
   PlanTables tables() const { return PlanTables{theta, zc, tw_row, tw_col}; }
@@ -321,6 +322,12 @@ static uint32_t store_cap(const ri_plan* p) {
   return (uint32_t)std::max(1.0, std::min(rows, std::ceil(p->store_frac * rows - 1e-6)));
 }
 
+// The grouped per-plane prox applies (RI_TV2D plans with a dual of fewer
+// planes than the volume).
+static bool plane_group(const ri_plan* p) {
+  return (p->g.flags & RI_TV2D) && p->dual_planes > 0 && p->dual_planes < p->g.nz && p->dtype == RI_F32 && !p->cplx;
+}
+
 struct Layout64 {
   size_t X = 0, S = 0, hol = 0, y = 0, xp = 0, v = 0, u = 0, p[3] = {0, 0, 0}, part = 0, psum = 0, ptv = 0;
   int nblk = 0;
@@ -402,7 +409,9 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0, bool d
     // dual components: x, y (and z for the 3D TV); the per-plane 2D TV has no z
     // dual.  FGP keeps two duals per set (r and p); bf16 duals take half the bytes.
     const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
-    const size_t dvol = (p->g.flags & RI_TV_DUAL_BF16) ? vol / 2 : vol;
+    // the grouped per-plane prox holds its dual for dual_planes planes only
+    const size_t dplanes = plane_group(p) ? (size_t)p->dual_planes : nz;
+    const size_t dvol = ((p->g.flags & RI_TV_DUAL_BF16) ? nx * ny * dplanes * 2 : nx * ny * dplanes * 4);
     for (int k = 0; k < nc; ++k) L.pa[k] = take(dvol);
     for (int k = 0; k < nc; ++k) L.pb[k] = take(dvol);
     if (p->g.flags & RI_TV_FGP) {
@@ -434,7 +443,8 @@ static Layout make_layout(const ri_plan* p, ri_op op, int col_blocks = 0, bool d
     L.pdfit = take((size_t)L.n_dfit * sizeof(double));
     L.psum = take((size_t)L.n_obj * sizeof(double));
     L.ptv = take((size_t)L.n_obj * sizeof(double));
-    L.n_prox = tv_blocks_bound((int)nx, (int)ny, (int)nz, p->cus);
+    L.n_prox = plane_group(p) ? tv_group_blocks_bound((int)nx, (int)ny, (int)nz, p->dual_planes, p->cus)
+                              : tv_blocks_bound((int)nx, (int)ny, (int)nz, p->cus);
     L.qsum = take((size_t)L.n_prox * sizeof(double));
     L.qtv = take((size_t)L.n_prox * sizeof(double));
     L.hist = take((size_t)kHistCap * sizeof(double));
@@ -499,6 +509,7 @@ static void prox_duals(const ri_plan* p, const Layout& L, void* ws, ProxArgs* a)
   a->dual_bf16 = (p->g.flags & RI_TV_DUAL_BF16) ? 1 : 0;
   a->fgp = (p->g.flags & RI_TV_FGP) ? 1 : 0;
   a->cus = p->cus;
+  a->group_planes = plane_group(p) ? p->dual_planes : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -919,8 +930,13 @@ extern "C" ri_status ri_prox_fused_lasso(ri_plan* p, const ri_prox_params* pp, d
   float* staged = nullptr;
   if (v == x_out && K > 0) {
     const int npass = prox_passes(K, tau, p->tune.tv_levels, a.fgp != 0);
-    staged = a.dual_bf16 ? at<float>(ws, L.stage) : (((npass - 1) & 1) ? a.pa[0] : a.pb[0]);
-    a.x = staged;
+    if (plane_group(p) && !a.dual_bf16) {
+      // the free dual set holds one group: each group's x is copied over v in turn
+      a.stage_group = ((npass - 1) & 1) ? a.pa[0] : a.pb[0];
+    } else {
+      staged = a.dual_bf16 ? at<float>(ws, L.stage) : (((npass - 1) & 1) ? a.pa[0] : a.pb[0]);
+      a.x = staged;
+    }
   }
   HIP_TRY(launch_prox(a, (hipStream_t)stream, nullptr));
   if (staged != nullptr)
@@ -1080,7 +1096,9 @@ static IterArgs iteration_args(const SolveCtx& c) {
   sa.n_obj = L.n_obj;
   sa.qsum = at<double>(c.ws, L.qsum);
   sa.qtv = at<double>(c.ws, L.qtv);
-  sa.n_prox = tv_final_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks, p->cus);
+  sa.n_prox = plane_group(p) ? tv_group_final_blocks(nx, ny, nz, p->dual_planes, p->tune.tv_levels,
+                                                      p->tune.tv_blocks, p->cus)
+                             : tv_final_blocks(nx, ny, nz, p->tune.tv_levels, p->tune.tv_blocks, p->cus);
   sa.hist = at<double>(c.ws, L.hist);
   if (p->cplx) sa.qsum = sa.qtv = nullptr;   // the objective kernel runs every iteration
   sa.overflow = c.rs.on ? c.rs.overflow : nullptr;
@@ -1206,6 +1224,10 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
     return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_COMPLEX plans");
   if (p->cplx && p->store_frac > 0.0)
     return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_COMPLEX plans");
+  if (plane_group(p) && (sp->flags & RI_SOLVE_DUAL_WARM))
+    return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM needs the whole dual (ri_plan_set_dual_planes 0)");
+  if (plane_group(p) && p->store_frac > 0.0)
+    return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with a plane-group dual");
   return RI_OK;
 }
 
@@ -1551,6 +1573,8 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     if (vs != RI_OK) return vs;
     if (p->cplx) return fail(RI_ERR_INVALID_ARG, "frame %d: RI_COMPLEX plans are solved one by one (ri_solve)", i);
     if (p->dtype == RI_F64) return fail(RI_ERR_INVALID_ARG, "frame %d: RI_F64 plans are solved one by one (ri_solve)", i);
+    if (plane_group(p))
+      return fail(RI_ERR_INVALID_ARG, "frame %d: plane-group duals are solved one by one (ri_solve)", i);
     if (p->device != plans[0]->device) return fail(RI_ERR_INVALID_ARG, "plans on different devices");
     SolveCtx& c = ctx[i];
     c.p = p;
@@ -1787,6 +1811,24 @@ extern "C" ri_status ri_plan_set_storage(ri_plan* p, double row_fraction) {
     return fail(RI_ERR_INVALID_ARG, "row-compressed iterates are not available with RI_F64 plans");
   p->store_frac = row_fraction;
   drop_graph(p);
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_set_dual_planes(ri_plan* p, int32_t planes) {
+  if (!p) return fail(RI_ERR_INVALID_ARG, "plan is NULL");
+  if (planes < 0) return fail(RI_ERR_INVALID_ARG, "planes=%d must be >= 0", planes);
+  if (planes > 0 && !(p->g.flags & RI_TV2D))
+    return fail(RI_ERR_INVALID_ARG, "a dual of a few planes needs the per-plane 2D TV (RI_TV2D)");
+  if (planes > 0 && (p->cplx || p->dtype == RI_F64 || (p->g.flags & RI_TV_FGP)))
+    return fail(RI_ERR_INVALID_ARG, "plane-group duals are for RI_F32 real plans without RI_TV_FGP");
+  p->dual_planes = planes;
+  drop_graph(p);
+  return RI_OK;
+}
+
+extern "C" ri_status ri_plan_get_dual_planes(const ri_plan* p, int32_t* planes) {
+  if (!p || !planes) return fail(RI_ERR_INVALID_ARG, "NULL argument");
+  *planes = p->dual_planes;
   return RI_OK;
 }
 

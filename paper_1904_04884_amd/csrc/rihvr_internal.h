@@ -309,6 +309,9 @@ struct ProxArgs {
   RowStores rs;          // solver with rs.on: v from rs.v, x_{k+1} into store st->scur ^ 1
   int warm;              // solver: the dual starts from the previous prox's (kept in pa / pb,
                          // the sets alternating by outer iteration when the pass count is odd)
+  int group_planes;      // per-plane 2D TV: prox G planes at a time, pa / pb holding G planes (0: all)
+  float* stage_group;    // grouped prox in place: each group's x is written here (G planes) and
+                         // then copied over v (nullable)
 };
 constexpr int kTvLevelsMin = 2, kTvLevelsMax = 4, kTvDefaultLevels = 3;
 constexpr int kTvDefaultBlocks = 1536;
@@ -322,6 +325,11 @@ int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks);
 int tv_pass_blocks(int nx, int ny, int nz, int levels, int blocks);
 int tv_final_blocks(int nx, int ny, int nz, int levels, int blocks, int cus);
 int tv_blocks_bound(int nx, int ny, int nz, int cus);
+// Grouped per-plane prox: final-pass blocks of all groups of G planes (the
+// objective partials of group g start at the sum over the groups before it),
+// and a bound over every tuning.
+int tv_group_final_blocks(int nx, int ny, int nz, int G, int levels, int blocks, int cus);
+int tv_group_blocks_bound(int nx, int ny, int nz, int G, int cus);
 
 // Batched prox: the argument structs of every pass of every frame are built on
 // the host (prox_pass_args) and uploaded; launch p runs pass p of all frames.

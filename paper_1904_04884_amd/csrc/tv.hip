@@ -88,6 +88,7 @@ struct TvPassArgs {
   int nblocks;                    // blocks of the pass (the objective partials are per block)
   float tau, c, thr;
   int gx, gy;                     // tiles along x and y (the grid of one frame)
+  size_t zoff_v, zoff_x;          // grouped per-plane prox: first plane of the group in v and x (elements)
 };
 
 // A register copy the compiler keeps (an identity DPP move).  The prefetched
@@ -172,8 +173,9 @@ __device__ __forceinline__ void tv_pass_body(const TvPassArgs& A, int bx, int by
                                              float* s_fin, double* s_sum) {
   constexpr int Q = kTvQ, NW = kTvWaves, NT = NW * 64;
   constexpr int IX = kTvRX - 2 * H, IY = kTvRY - 2 * H;  // interior (stored) extent
-  const float* __restrict__ v = uniform_ptr(A.v ? A.v : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->prev));
-  float* __restrict__ xo = uniform_ptr(A.x ? A.x : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->next));
+  const float* __restrict__ v =
+      uniform_ptr((A.v ? A.v : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->prev)) + A.zoff_v);
+  float* __restrict__ xo = uniform_ptr((A.x ? A.x : pick3(A.vol[0], A.vol[1], A.vol[2], A.st->next)) + A.zoff_x);
   const int nx = A.nx, ny = A.ny, nz = A.nz;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // dual buffers of this pass: with a warm-started dual the sets alternate
@@ -788,6 +790,17 @@ int tv_blocks_bound(int nx, int ny, int nz, int cus) {
   return tx * ty * std::max(1, nz / 16) + std::max(cus, 0);
 }
 
+int tv_group_final_blocks(int nx, int ny, int nz, int G, int levels, int blocks, int cus) {
+  int total = 0;
+  for (int z0 = 0; z0 < nz; z0 += G) total += tv_final_blocks(nx, ny, std::min(G, nz - z0), levels, blocks, cus);
+  return total;
+}
+
+int tv_group_blocks_bound(int nx, int ny, int nz, int G, int cus) {
+  const int groups = (nz + G - 1) / G;
+  return groups * tv_blocks_bound(nx, ny, std::min(G, nz), cus);
+}
+
 int tv_pass_zchunk(int nx, int ny, int nz, int levels, int blocks) {
   return pass_grid(nx, ny, nz, clamp_levels(levels), blocks > 0 ? blocks : kTvDefaultBlocks).zchunk;
 }
@@ -919,11 +932,51 @@ static void launch_any(bool final_pass, bool tv2, bool fgp, bool bf, bool sp, in
   }
 }
 
+// The per-plane 2D TV couples no planes, so its prox can run on groups of G
+// planes in turn, each group's passes reading and writing a dual of G planes
+// (the paper's plane-by-plane prox, with the memory of G planes instead of the
+// volume).  Each group's final pass writes its objective partials after the
+// previous groups' ones.
+static hipError_t launch_prox_grouped(const ProxArgs& pa, int K, int H, int np, hipStream_t s, int* launches) {
+  const int G = pa.group_planes;
+  const size_t plane = (size_t)pa.nx * pa.ny;
+  std::vector<TvPassArgs> args(np);
+  std::vector<int> nb(np);
+  int off = 0, nl = 0;
+  for (int z0 = 0; z0 < pa.nz; z0 += G) {
+    ProxArgs q = pa;
+    q.nz = std::min(G, pa.nz - z0);
+    q.group_planes = 0;
+    q.rowflag = pa.rowflag ? pa.rowflag + (size_t)z0 * pa.ny : nullptr;
+    q.planeflag = pa.planeflag ? pa.planeflag + z0 : nullptr;
+    q.psum = pa.psum ? pa.psum + off : nullptr;
+    q.ptv = pa.ptv ? pa.ptv + off : nullptr;
+    if (pa.stage_group) q.x = pa.stage_group;
+    const int npass = prox_pass_args(q, args.data(), nb.data());
+    for (int p = 0; p < npass; ++p) {
+      args[p].zoff_v = (size_t)z0 * plane;
+      args[p].zoff_x = pa.stage_group ? 0 : (size_t)z0 * plane;
+      launch_any<false>(args[p].final_ != 0, args[p].tv2 != 0, args[p].fgp != 0, args[p].dual_bf16 != 0,
+                        args[p].rs.on != 0, H, dim3(nb[p]), &args[p], BatchMap{nullptr, 0}, s);
+    }
+    nl += npass;
+    if (pa.stage_group) {
+      const hipError_t e = launch_copy_f32(pa.x + (size_t)z0 * plane, pa.stage_group, (size_t)q.nz * plane, s);
+      if (e != hipSuccess) return e;
+      ++nl;
+    }
+    off += nb[npass - 1];
+  }
+  if (launches) *launches = nl;
+  return hipGetLastError();
+}
+
 hipError_t launch_prox(const ProxArgs& pa, hipStream_t s, int* launches) {
   const double tau = pa.step * pa.tv;
   const int K = (tau > 0.0 && pa.inner_iters > 0) ? pa.inner_iters : 0;
   const int H = prox_levels(pa.levels, pa.fgp != 0);
   const int np = prox_passes(K, tau, H, pa.fgp != 0);
+  if (pa.tv2 && pa.group_planes > 0 && pa.group_planes < pa.nz) return launch_prox_grouped(pa, K, H, np, s, launches);
   std::vector<TvPassArgs> args(np);
   std::vector<int> nb(np);
   const int npass = prox_pass_args(pa, args.data(), nb.data());

@@ -49,7 +49,8 @@ PHASE_NAMES = ("forward", "hologram", "adjoint", "prox", "objective", "other")
 
 EXPORTED = (
     "ri_plan_create", "ri_plan_destroy", "ri_plan_lipschitz", "ri_workspace_size", "ri_workspace_size_op",
-    "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_set_storage", "ri_plan_get_storage", "ri_plan_autotune",
+    "ri_plan_get_tuning", "ri_plan_set_tuning", "ri_plan_set_storage", "ri_plan_get_storage",
+    "ri_plan_set_dual_planes", "ri_plan_get_dual_planes", "ri_plan_autotune",
     "ri_forward", "ri_forward_noalloc", "ri_forward_noalloc_max_scratch", "ri_adjoint", "ri_prox_fused_lasso", "ri_solve", "ri_solve_batched",
     "ri_workspace_size_batched",
     "ri_unet_param_count", "ri_unet_init_params", "ri_unet_workspace_size", "ri_unet_forward",
@@ -152,6 +153,8 @@ def lib():
     L.ri_plan_set_tuning.argtypes = [vp, C.POINTER(ri_tuning)]
     L.ri_plan_set_storage.argtypes = [vp, C.c_double]
     L.ri_plan_get_storage.argtypes = [vp, C.POINTER(C.c_double)]
+    L.ri_plan_set_dual_planes.argtypes = [vp, C.c_int32]
+    L.ri_plan_get_dual_planes.argtypes = [vp, C.POINTER(C.c_int32)]
     L.ri_plan_autotune.argtypes = [vp, C.c_int32, C.c_char_p, vp, sz, vp, C.POINTER(ri_autotune_report)]
     L.ri_forward.argtypes = [vp, vp, vp, vp, sz, vp]
     L.ri_forward_noalloc.argtypes = [vp, vp, vp, vp]
@@ -243,6 +246,16 @@ def ri_plan_set_storage(plan: int, row_fraction: float) -> int:
 def ri_plan_get_storage(plan: int) -> float:
     v = C.c_double()
     _check(lib().ri_plan_get_storage(plan, C.byref(v)), "ri_plan_get_storage")
+    return v.value
+
+
+def ri_plan_set_dual_planes(plan: int, planes: int) -> int:
+    return lib().ri_plan_set_dual_planes(plan, int(planes))
+
+
+def ri_plan_get_dual_planes(plan: int) -> int:
+    v = C.c_int32()
+    _check(lib().ri_plan_get_dual_planes(plan, C.byref(v)), "ri_plan_get_dual_planes")
     return v.value
 
 
@@ -399,6 +412,16 @@ class Plan:
     def tuning(self, t: dict):
         _check(ri_plan_set_tuning(self.handle, ri_tuning(int(t["tv_levels"]), int(t["tv_blocks"]),
                                                          int(t["col_blocks"]))), "ri_plan_set_tuning")
+
+    @property
+    def dual_planes(self) -> int:
+        """Planes whose TV dual the per-plane prox holds at a time (0: all; see
+        ri_plan_set_dual_planes)."""
+        return ri_plan_get_dual_planes(self.handle)
+
+    @dual_planes.setter
+    def dual_planes(self, n: int):
+        _check(ri_plan_set_dual_planes(self.handle, n), "ri_plan_set_dual_planes")
 
     @property
     def row_fraction(self) -> float:

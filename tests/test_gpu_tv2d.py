@@ -159,3 +159,102 @@ def test_batched_mixes_2d_and_3d_frames(torch_cuda):
     finally:
         for p in ps:
             p.close()
+
+
+# ---------------------------------------------------------------------------
+# Plane-group dual (ri_plan_set_dual_planes): the per-plane prox run on groups
+# of G planes with a dual of G planes.  The planes do not interact, so every
+# voxel's arithmetic is the same: bit-identical results.
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(64, 48, 12), (192, 96, 40), (96, 24, 5)])
+@pytest.mark.parametrize("G", [1, 3, 7, 16])
+@pytest.mark.parametrize("levels,k", [(4, 20), (3, 5), (2, 1)])
+def test_prox_plane_groups_bit_identical(torch_cuda, shape, G, levels, k):
+    torch = torch_cuda
+    g = geom2(*shape)
+    rng = np.random.default_rng(sum(shape) + G + k)
+    v = to_dev(torch, 0.3 * rng.standard_normal(g.shape))
+    tuning = {"tv_levels": levels, "tv_blocks": 1536, "col_blocks": 512}
+    whole = rihvr.Plan(g)
+    grouped = rihvr.Plan(g)
+    try:
+        whole.tuning = tuning
+        grouped.tuning = tuning
+        grouped.dual_planes = G
+        for nonneg in (True, False):
+            a = whole.prox(v, 0.6, 0.05, 0.3, k, nonneg)
+            b = grouped.prox(v, 0.6, 0.05, 0.3, k, nonneg)
+            assert torch.equal(a, b), (nonneg, G)
+            w = v.clone()
+            grouped.prox(w, 0.6, 0.05, 0.3, k, nonneg, out=w)      # in place, group by group
+            assert torch.equal(w, a)
+        if G < g.nz:
+            assert rihvr.ri_workspace_size_op(grouped.handle, rihvr.RI_OP_PROX) < \
+                rihvr.ri_workspace_size_op(whole.handle, rihvr.RI_OP_PROX)
+    finally:
+        whole.close()
+        grouped.close()
+
+
+def test_solve_plane_groups(torch_cuda, c1_problem_2d):
+    """Solve with a dual of 4 planes: iterates bit-identical to the whole-volume
+    dual, objective within FP64 summation order, oracle parity."""
+    torch = torch_cuda
+    g, cfg, b, x_ref = c1_problem_2d
+    whole = rihvr.Plan(g)
+    grouped = rihvr.Plan(g)
+    try:
+        grouped.dual_planes = 4
+        xa, ra, _ = whole.solve(to_dev(torch, b), cfg.l1, cfg.tv, cfg.outer_iters, cfg.inner_iters)
+        xb, rb, _ = grouped.solve(to_dev(torch, b), cfg.l1, cfg.tv, cfg.outer_iters, cfg.inner_iters)
+        assert torch.equal(xa, xb)
+        assert rb["objective"] == pytest.approx(ra["objective"], rel=1e-12)
+        assert rel_l2(to_host(xb), x_ref) <= 1e-3
+        # graph and no graph, restart mode
+        xc, _, _ = grouped.solve(to_dev(torch, b), cfg.l1, cfg.tv, 9, 10, flags=rihvr.RI_SOLVE_NO_GRAPH)
+        xd, _, _ = whole.solve(to_dev(torch, b), cfg.l1, cfg.tv, 9, 10)
+        assert torch.equal(xc, xd)
+        vol = g.nx * g.ny * g.nz * 4
+        assert rihvr.ri_workspace_size_op(whole.handle, rihvr.RI_OP_SOLVE) - \
+            rihvr.ri_workspace_size_op(grouped.handle, rihvr.RI_OP_SOLVE) >= 4 * vol * (1 - 4 / g.nz) - (1 << 20)
+    finally:
+        whole.close()
+        grouped.close()
+
+
+def test_plane_groups_rejections(torch_cuda):
+    torch = torch_cuda
+    g3 = scenes.geometry_c1().with_(nx=64, ny=64, nz=8)
+    p = rihvr.Plan(g3)
+    try:
+        assert rihvr.ri_plan_set_dual_planes(p.handle, 2) == rihvr.RI_ERR_INVALID_ARG   # 3D TV couples planes
+    finally:
+        p.close()
+    g2 = g3.with_(tv_dims=2)
+    p = rihvr.Plan(g2)
+    try:
+        assert rihvr.ri_plan_set_dual_planes(p.handle, -1) == rihvr.RI_ERR_INVALID_ARG
+        p.dual_planes = 2
+        assert p.dual_planes == 2
+        b = torch.zeros((g2.ny, g2.nx), dtype=torch.float32, device="cuda")
+        with pytest.raises(rihvr.RihvrError):
+            p.solve(b, 0.01, 0.01, 3, 4, flags=rihvr.RI_SOLVE_DUAL_WARM)
+        p.row_fraction = 0.5
+        with pytest.raises(rihvr.RihvrError):
+            p.solve(b, 0.01, 0.01, 3, 4)
+        p.row_fraction = 0.0
+        params = [p.solve_params(0.01, 0.01, 3, 4)]
+        nbytes = rihvr.ri_workspace_size_batched(1, [p.handle], params)
+        ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        x = torch.empty(p.shape, dtype=torch.float32, device="cuda")
+        st = rihvr.ri_solve_batched(1, [p.handle], params, [b.data_ptr()], [x.data_ptr()], ws.data_ptr(), nbytes,
+                                    torch.cuda.current_stream().cuda_stream, None)
+        assert st == rihvr.RI_ERR_INVALID_ARG
+    finally:
+        p.close()
+    for bad in (g2.with_(tv_fgp=True), g2.with_(complex_object=True)):
+        q = rihvr.Plan(bad)
+        try:
+            assert rihvr.ri_plan_set_dual_planes(q.handle, 2) == rihvr.RI_ERR_INVALID_ARG
+        finally:
+            q.close()
