@@ -326,9 +326,10 @@ def run_compare(args, torch, rihvr, scenes):
     tplans = [rihvr.Plan(g) for g, _, _, _ in tframes]
     ws = warmstart.WarmStart(tplans[0], levels=4, base=16, seed=args.seed)
     pairs = []
-    for p, (g, idx, val, noise) in zip(tplans, tframes):
+    for i, (p, (g, idx, val, noise)) in enumerate(zip(tplans, tframes)):
         pairs.append(ws.make_pair(frame_hologram(torch, p, g, idx, val, noise), cfg.l1, cfg.tv,
                                   args.ws_pair_iters, K, plan=p)[0])
+        p._ws.pop(rihvr.RI_OP_SOLVE, None)   # the pair's solve is done; training needs only A^T
     curve = ws.train(pairs, steps=args.ws_steps, crop=(32, 64, 64), lr=1e-3,
                      log_every=max(1, args.ws_steps // 5))
     torch.cuda.synchronize()
