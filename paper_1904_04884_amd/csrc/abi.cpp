@@ -329,13 +329,14 @@ static bool plane_group(const ri_plan* p) {
 }
 
 struct Layout64 {
-  size_t X = 0, S = 0, hol = 0, y = 0, xp = 0, v = 0, u = 0, p[3] = {0, 0, 0}, part = 0, psum = 0, ptv = 0;
+  size_t X = 0, S = 0, hol = 0, y = 0, xp = 0, v = 0, p[3] = {0, 0, 0}, p2[3] = {0, 0, 0}, part = 0, psum = 0,
+         ptv = 0;
   int nblk = 0;
   size_t total = 0;
 };
 
 // Workspace of an FP64 plan: every plane's complex spectrum and a hologram
-// spectrum (A, A^T), the prox's u and dual, the solver's y, x_{k-1} (then
+// spectrum (A, A^T), the prox's two dual sets, the solver's y, x_{k-1} (then
 // x_{k+1}), v, a hologram and per-block partials.  Volumes hold both parts.
 static Layout64 layout64(const ri_plan* p, ri_op op) {
   Layout64 L;
@@ -352,9 +353,9 @@ static Layout64 layout64(const ri_plan* p, ri_op op) {
     L.S = take(np * sizeof(double2));
   }
   if (op == RI_OP_PROX || op == RI_OP_SOLVE) {
-    L.u = take(vol);
     const int nc = (p->g.flags & RI_TV2D) ? 2 : 3;
     for (int k = 0; k < nc; ++k) L.p[k] = take(vol);
+    for (int k = 0; k < nc; ++k) L.p2[k] = take(vol);
   }
   if (op == RI_OP_SOLVE) {
     L.hol = take(np * sizeof(double));
@@ -594,8 +595,10 @@ static Prox64Args prox64_args(const ri_plan* p, const Layout64& L, void* ws, int
                               double l1, double tv) {
   Prox64Args a{};
   const int parts = p->cplx ? 2 : 1;
-  a.u = at<double>(ws, L.u);
-  for (int k = 0; k < 3; ++k) a.p[k] = L.p[k] ? at<double>(ws, L.p[k]) : nullptr;
+  for (int k = 0; k < 3; ++k) {
+    a.p[k] = L.p[k] ? at<double>(ws, L.p[k]) : nullptr;
+    a.p2[k] = L.p2[k] ? at<double>(ws, L.p2[k]) : nullptr;
+  }
   a.nx = p->g.nx;
   a.ny = p->g.ny;
   a.nz = p->g.nz / parts;

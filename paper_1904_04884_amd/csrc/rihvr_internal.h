@@ -344,8 +344,8 @@ hipError_t launch_tv_pass_batched(int levels, bool final_pass, bool tv2, bool fg
 
 // Complex-valued object (cplx.hip): volumes [2][nz/2][ny][nx] (real parts, then
 // imaginary parts; `nz` in the argument structs counts the planes of both).
-// The fused-lasso prox with the complex TV (GP on a complex dual, pa[] the
-// dual, pb[0] a scratch volume for u) and the complex shrinkage; the solver's
+// The fused-lasso prox with the complex TV (GP on a complex dual, pa[] and
+// pb[] the two dual sets, alternating step by step) and the complex shrinkage; the solver's
 // objective partials of sum |x| and the complex TV in `nblocks` blocks.
 hipError_t launch_cprox(const ProxArgs& a, hipStream_t s, int* launches);
 hipError_t launch_cobj(const ObjArgs& a, int nblocks, hipStream_t s);
@@ -371,8 +371,8 @@ hipError_t fill64(double* out, double v, size_t n, hipStream_t s);
 hipError_t sqdist64(const double* x, const double* y, size_t n, double* part, int nblocks, hipStream_t s);
 struct Prox64Args {
   const double* v; double* x;   // [parts][nz][ny][nx]; x may be v
-  double* u;                    // scratch, as v
   double* p[3];                 // dual components, as v (p[2] unused in 2D)
+  double* p2[3];                // the second dual set (the sets alternate step by step)
   int nx, ny, nz;               // nz: planes of one part
   int parts;                    // 1: real object, 2: complex object
   int tv2, nonneg, inner_iters;
