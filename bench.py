@@ -254,18 +254,29 @@ def run_batched(args, torch, rihvr, scenes):
     ws = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
 
-    def batched():
-        st = rihvr.ri_solve_batched(len(plans), handles, params, [b.data_ptr() for b in bs],
+    params_g = [p.solve_params(cfg.l1, cfg.tv, iters, cfg.inner_iters, flags=rihvr.RI_SOLVE_GROUPED)
+                for p in plans]
+
+    def batched(prm=params):
+        st = rihvr.ri_solve_batched(len(plans), handles, prm, [b.data_ptr() for b in bs],
                                     [x.data_ptr() for x in xs], ws.data_ptr(), ws.numel(), stream, None)
         assert st == rihvr.RI_OK, rihvr.ri_last_error()
 
-    batched()  # warm-up (graph capture, caches)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    batched()
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
-    del ws
+    def timed(prm):
+        batched(prm)  # warm-up (graph capture, caches)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        batched(prm)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    # TV passes as persistent kernels fed by the device work queue (the default)
+    tb = timed(params)
+    x_queue = [x.clone() for x in xs]
+    # one block per tile of every frame
+    tg = timed(params_g)
+    same = all(torch.equal(a, b) for a, b in zip(xs, x_queue))
+    del ws, x_queue
     # the same frames one at a time (each with its own graph)
     for p, b in zip(plans, bs):
         p.solve(b, cfg.l1, cfg.tv, iters, cfg.inner_iters, report=False)
@@ -282,6 +293,8 @@ def run_batched(args, torch, rihvr, scenes):
         "frames": len(frames), "iterations": iters, "voxels": nvox,
         "batched_holograms_per_s": len(frames) / tb, "per_frame_holograms_per_s": len(frames) / ts,
         "speedup": ts / tb, "batched_voxel_iters_per_s": nvox * iters / tb,
+        "grouped_holograms_per_s": len(frames) / tg, "persistent_vs_grouped": tg / tb,
+        "grouped_bit_identical": same,
         "autotune_s": t_tune, "autotuned_shapes": n_timed,
         "sizes": [[g.nx, g.nz] for g, _, _, _ in frames],
     }

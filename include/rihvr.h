@@ -130,6 +130,11 @@ typedef struct {
                                     outer iteration ended with (zero for the first) instead of
                                     from zero: an inexact inner solve that improves across
                                     outer iterations */
+#define RI_SOLVE_GROUPED  0x20u /* ri_solve_batched (params[0].flags): launch each TV pass with
+                                   one block per tile of every frame instead of the default
+                                   persistent kernels (one block per compute unit taking the
+                                   frames' tiles from a device work queue); the same results bit
+                                   for bit.  No effect on ri_solve */
 
 typedef struct {
   double l1, tv;            /* regularisation weights */
@@ -353,8 +358,11 @@ ri_status ri_solve(ri_plan* plan, const ri_solve_params* params, const void* b, 
  * iteration for all frames at a time, each with its own step, momentum,
  * objective and stop flag; a frame that has met its criterion does no further
  * work.  Each kernel of an iteration is launched once per transform size (or
- * once for all frames) and one iteration of all frames is replayed as a HIP
- * graph (unless params[0].flags has RI_SOLVE_NO_GRAPH).  The workspace must
+ * once for all frames); the TV passes, most of the time of an iteration, run
+ * as persistent kernels of one block per compute unit that take the frames'
+ * tiles from a device work queue (RI_SOLVE_GROUPED: one block per tile
+ * instead).  One iteration of all frames is replayed as a HIP graph (unless
+ * params[0].flags has RI_SOLVE_NO_GRAPH).  The workspace must
  * hold ri_workspace_size_batched() bytes.  params[i], b[i], x_inout[i] and
  * reports[i] (nullable array; filled after one synchronisation) belong to
  * frame i.  The x_inout volumes must not overlap each other, any b or ws.

@@ -1216,7 +1216,8 @@ static ri_status validate_solve(ri_plan* p, const ri_solve_params* sp, const flo
   if (!(sp->x0_scale >= 0) || !std::isfinite(sp->x0_scale))
     return fail(RI_ERR_INVALID_ARG, "x0_scale must be finite and >= 0");
   if (sp->f_ref > 0 && !(sp->gap_tol >= 0)) return fail(RI_ERR_INVALID_ARG, "gap_tol must be >= 0");
-  if (sp->flags & ~(RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH | RI_SOLVE_RESTART | RI_SOLVE_TIMING | RI_SOLVE_DUAL_WARM))
+  if (sp->flags & ~(RI_SOLVE_DENSE | RI_SOLVE_NO_GRAPH | RI_SOLVE_RESTART | RI_SOLVE_TIMING | RI_SOLVE_DUAL_WARM |
+                    RI_SOLVE_GROUPED))
     return fail(RI_ERR_INVALID_ARG, "unknown solve flags 0x%x", sp->flags);
   if ((sp->flags & RI_SOLVE_DUAL_WARM) && (p->g.flags & RI_TV_FGP))
     return fail(RI_ERR_INVALID_ARG, "RI_SOLVE_DUAL_WARM is not available with RI_TV_FGP plans");
@@ -1437,6 +1438,7 @@ struct BatchLaunch {
   bool sparse = false;      // TV: frames with row-compressed iterates
   std::vector<int> frames;
   size_t args_off = 0, offs_off = 0;
+  size_t queue_off = 0;     // TV: claim counters of the persistent form
   int nblocks = 0;
 };
 
@@ -1531,6 +1533,7 @@ static size_t batch_tables_bytes(int n, ri_plan* const* plans, const ri_solve_pa
   for (const BatchLaunch& b : batch_launches(n, plans, params)) {
     off = align_up(off + kind_args_size(b.kind) * b.frames.size());
     off = align_up(off + sizeof(uint32_t) * (b.frames.size() + 1));
+    if (b.kind == BK_TV) off = align_up(off + sizeof(uint32_t) * kQueueWords);
   }
   off = align_up(off + sizeof(SolveState*) * n);  // states for the stop count
   off = align_up(off + sizeof(int32_t));           // the count
@@ -1682,6 +1685,10 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
     o[bl.frames.size()] = acc;
     bl.nblocks = (int)acc;
     t = align_up(t + sizeof(uint32_t) * (bl.frames.size() + 1));
+    if (bl.kind == BK_TV) {  // counters staged as zeros
+      bl.queue_off = t;
+      t = align_up(t + sizeof(uint32_t) * kQueueWords);
+    }
   }
   const size_t states_off = t;
   for (int i = 0; i < n; ++i) reinterpret_cast<SolveState**>(host.data() + t)[i] = ctx[i].st;
@@ -1690,12 +1697,17 @@ extern "C" ri_status ri_solve_batched(int32_t n, ri_plan* const* plans, const ri
   HIP_TRY(hipMemcpyAsync(tables, host.data(), tbytes, hipMemcpyHostToDevice, s));
   HIP_TRY(hipStreamSynchronize(s));  // the staging buffer is pageable and local
 
+  const bool persistent = (params[0].flags & RI_SOLVE_GROUPED) == 0;
   auto enqueue_batch_iteration = [&](hipStream_t q) -> hipError_t {
     hipError_t e = hipSuccess;
     bool cleared = false;
     for (const BatchLaunch& bl : launches) {
       if (bl.nblocks == 0) continue;
-      const BatchMap mp{reinterpret_cast<const uint32_t*>(tables + bl.offs_off), (int)bl.frames.size()};
+      BatchMap mp{reinterpret_cast<const uint32_t*>(tables + bl.offs_off), (int)bl.frames.size()};
+      if (persistent && bl.kind == BK_TV) {
+        mp.queue = reinterpret_cast<uint32_t*>(tables + bl.queue_off);
+        mp.grid = std::max(1, plans[0]->cus);
+      }
       const void* a = tables + bl.args_off;
       switch (bl.kind) {
         case BK_OBJ: e = launch_obj_batched((const ObjArgs*)a, mp, bl.nblocks, q); break;

@@ -23,8 +23,8 @@ __device__ __forceinline__ T* uniform_ptr(T* p) {
 // work index such that every XCD gets one contiguous run of indices, so that
 // neighbouring tiles (which share halo rows or cache lines) run on the same
 // XCD at about the same time.  A bijection of [0, n).
+constexpr uint32_t kXcds = 8;
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t id, uint32_t n) {
-  constexpr uint32_t kXcds = 8;
   const uint32_t q = n / kXcds, r = n % kXcds;   // XCD k runs q + (k < r) indices
   const uint32_t k = id % kXcds, j = id / kXcds;
   return k * q + min(k, r) + j;
@@ -123,7 +123,15 @@ bool fft_len_supported(int L);
 struct BatchMap {
   const uint32_t* offs;  // device, n + 1 entries
   int n;
+  // Persistent form (TV passes): kQueueWords words of claim counters, zero at
+  // launch and zero again when the launch ends, and the blocks of the launch.
+  uint32_t* queue = nullptr;
+  int grid = 0;
 };
+// One counter per XCD range and one for the blocks that have finished, each
+// on a 128-byte line of its own.
+constexpr uint32_t kQueueStride = 32;
+constexpr uint32_t kQueueWords = (kXcds + 1) * kQueueStride;
 
 // Row-wise packed R2C of real rows [nrows][2m] -> [nrows][m] complex.  Rows with
 // rowflag == 0 are skipped (nothing written).  mode 0: input x;  mode 1: input

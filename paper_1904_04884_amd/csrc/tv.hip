@@ -638,7 +638,8 @@ __device__ __forceinline__ void tv_pass_entry(const TvPassArgs& A, int bx, int b
   __shared__ double s_red[2][kTvWaves];            // final pass: per-wave sums
   __shared__ float s_fin[FINAL ? 2 * kTvQ * kTvWaves * 64 : 1];    // final pass: PzF, Xp (thread-private)
   __shared__ double s_sum[FINAL ? 2 * kTvWaves * 64 : 1];          // final pass: FP64 sums (thread-private)
-  if (A.st != nullptr && A.st->done) return;
+  // the stop flag read once per wave (a wave-uniform branch)
+  if (A.st != nullptr && __builtin_amdgcn_readfirstlane(A.st->done)) return;
   constexpr int IX = kTvRX - 2 * HT, IY = kTvRY - 2 * HT;
   const int x0 = bx * IX - HT, y0 = by * IY - HT;
   // interior tile: every point of the region and its +-1 neighbours lie inside
@@ -701,10 +702,10 @@ __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass(TvPa
   tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF, SP>(A, w.bx, w.by, w.zb, w.ze, (int)t);
 }
 
+// Work item b of a batched launch: the frame f with offs[f] <= b < offs[f+1]
+// and block b - offs[f] of that frame's pass.
 template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
-__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(const TvPassArgs* __restrict__ args,
-                                                                                  BatchMap map) {
-  const uint32_t b = xcd_tile(blockIdx.x, gridDim.x);
+__device__ __forceinline__ void tv_batch_item(const TvPassArgs* __restrict__ args, const BatchMap& map, uint32_t b) {
   int lo = 0, hi = map.n;  // largest f with offs[f] <= b
   while (hi - lo > 1) {
     const int mid = (lo + hi) >> 1;
@@ -718,6 +719,68 @@ __global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(co
   const int lb = (int)(b - (uint32_t)__builtin_amdgcn_readfirstlane(map.offs[lo]));
   const TvWork w = tv_work(A, (uint32_t)lb);
   tv_pass_entry<FINAL ? H + 1 : H, H, FINAL, TV2, FGP, BF, SP>(A, w.bx, w.by, w.zb, w.ze, lb);
+}
+
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
+__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_b(const TvPassArgs* __restrict__ args,
+                                                                                  BatchMap map) {
+  tv_batch_item<H, FINAL, TV2, FGP, BF, SP>(args, map, xcd_tile(blockIdx.x, gridDim.x));
+}
+
+// Persistent form of the batched pass: a grid of about one block per compute
+// unit takes the launch's work items (every frame's blocks end to end, as
+// above) from a device queue instead of running one item per block.  The items
+// are cut into one contiguous range per XCD, each with a claim counter; a
+// block claims items one at a time with an atomic add, from its own XCD's
+// range first (neighbouring tiles share that XCD's L2), then from the other
+// ranges in turn, so that the blocks that run out of work early take over the
+// tail.  Items are independent and a block runs one whole item between two
+// barriers, so the results do not depend on which block ran which item.  The
+// last block out resets the counters: the next launch, a graph replay
+// included, finds them at zero.
+// The claim takes no branch on the thread index: every thread adds to the
+// counter (thread 0 one, the others zero) and to the LDS word (thread 0 its
+// claim, the others zero).  A branch on thread 0 here, next to the final
+// pass's own thread-0 epilogue at the end of an item, lets the compiler thread
+// the two across the loop's back edge and turn the item loop into an
+// exec-masked loop with the barriers inside, which waves leave after
+// different numbers of trips.
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
+__global__ void __launch_bounds__(kTvWaves * 64, kTvWavesPerSimd) k_tv_pass_q(const TvPassArgs* __restrict__ args,
+                                                                                  BatchMap map) {
+  __shared__ uint32_t s_item;
+  const uint32_t n = __builtin_amdgcn_readfirstlane(map.offs[map.n]);
+  const uint32_t q = n / kXcds, r = n % kXcds, home = blockIdx.x % kXcds;
+  const uint32_t one = threadIdx.x == 0 ? 1u : 0u;
+  s_item = 0u;
+  __syncthreads();
+  for (uint32_t j = 0; j < kXcds; ++j) {
+    const uint32_t k = (home + j) % kXcds;
+    const uint32_t first = k * q + min(k, r), len = q + (k < r ? 1u : 0u);
+    for (;;) {
+      const uint32_t c = atomicAdd(map.queue + k * kQueueStride, one);
+      atomicAdd(&s_item, one * c);
+      __syncthreads();
+      const uint32_t i = __builtin_amdgcn_readfirstlane(s_item);
+      __syncthreads();  // every wave holds the item before the word is cleared
+      s_item = 0u;
+      __syncthreads();  // ... and cleared before the next claim adds to it
+      if (i >= len) break;
+      tv_batch_item<H, FINAL, TV2, FGP, BF, SP>(args, map, first + i);
+    }
+  }
+  // every block passes here once, after its last claim on every counter
+  if (threadIdx.x == 0 && atomicAdd(map.queue + kXcds * kQueueStride, 1u) == gridDim.x - 1)
+    for (uint32_t k = 0; k <= kXcds; ++k) atomicExch(map.queue + k * kQueueStride, 0u);
+}
+
+template <int H, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
+static void launch_batched(dim3 g, const TvPassArgs* a, const BatchMap& map, hipStream_t s) {
+  const dim3 b(kTvWaves * 64);
+  if (map.queue != nullptr)
+    hipLaunchKernelGGL((k_tv_pass_q<H, FINAL, TV2, FGP, BF, SP>), dim3(std::max(1, std::min<int>(g.x, map.grid))), b,
+                       0, s, a, map);
+  else hipLaunchKernelGGL((k_tv_pass_b<H, FINAL, TV2, FGP, BF, SP>), g, b, 0, s, a, map);
 }
 
 // Blocks of one pass: x tiles, y tiles, z chunks.  The z-range is cut into
@@ -881,20 +944,20 @@ template <bool BATCH, bool FINAL, bool TV2, bool FGP, bool BF, bool SP>
 static void launch_k(int H, dim3 g, const TvPassArgs* a, BatchMap map, hipStream_t s) {
   const dim3 b(kTvWaves * 64);
   if constexpr (FGP) {
-    if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, true, BF, false>), g, b, 0, s, a, map);
+    if constexpr (BATCH) launch_batched<2, FINAL, TV2, true, BF, false>(g, a, map, s);
     else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, true, BF, false>), g, b, 0, s, *a);
   } else {
     switch (H) {
       case 2:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<2, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        if constexpr (BATCH) launch_batched<2, FINAL, TV2, false, BF, SP>(g, a, map, s);
         else hipLaunchKernelGGL((k_tv_pass<2, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
       case 3:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<3, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        if constexpr (BATCH) launch_batched<3, FINAL, TV2, false, BF, SP>(g, a, map, s);
         else hipLaunchKernelGGL((k_tv_pass<3, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
       default:
-        if constexpr (BATCH) hipLaunchKernelGGL((k_tv_pass_b<4, FINAL, TV2, false, BF, SP>), g, b, 0, s, a, map);
+        if constexpr (BATCH) launch_batched<4, FINAL, TV2, false, BF, SP>(g, a, map, s);
         else hipLaunchKernelGGL((k_tv_pass<4, FINAL, TV2, false, BF, SP>), g, b, 0, s, *a);
         break;
     }

@@ -42,6 +42,7 @@ RI_SOLVE_NO_GRAPH = 0x2
 RI_SOLVE_RESTART = 0x4
 RI_SOLVE_TIMING = 0x8
 RI_SOLVE_DUAL_WARM = 0x10
+RI_SOLVE_GROUPED = 0x20
 
 RI_OP_FORWARD, RI_OP_ADJOINT, RI_OP_PROX, RI_OP_SOLVE, RI_OP_AUTOTUNE = 0, 1, 2, 3, 4
 RI_NUM_PHASES = 6
