@@ -88,13 +88,16 @@ __device__ __forceinline__ T neg_div(const GpArgs<T>& a, size_t i, size_t o, int
 // One gradient-projection step, streamed along z.  A block of 512 threads
 // owns a 64 x 8 tile of every plane and walks the planes upward (a 64 x 16
 // tile in FP32, two rows per thread, measured 3% slower: half the blocks fit
-// a CU by LDS).  For each plane it stages
-// in LDS the dual it needs (p_x with its -x halo column, p_y with its -y halo
-// row, p_z of this plane and of the one below, all on the tile and its +x / +y
-// halo), forms u = v - tau D^T p once per voxel of the tile and its halo, and
-// then writes the new dual of the plane below, q = p + c D u, p' = q / max(1,
-// |q|), from u at the voxel and its +x, +y and +z neighbours.  It reads the
-// dual set a.p and writes the other set a.q.
+// a CU by LDS).  For each plane it stages in LDS the dual it needs (p_x with
+// its -x halo column, p_y with its -y halo row, p_z of this plane and of the
+// one below, all on the tile and its +x / +y halo), forms u = v - tau D^T p
+// once per voxel of the tile and its halo, and then writes the new dual of the
+// plane below, q = p + c D u, p' = q / max(1, |q|), from u at the voxel and
+// its +x, +y and +z neighbours.  The loads of a plane (its dual stage and v)
+// go to registers two planes ahead and into LDS when the plane's turn comes,
+// so they are in flight while the plane before is computed (132 -> 87 ms per
+// outer iteration at 1024^2 x 256 complex).  It reads the dual set a.p and
+// writes the other set a.q.
 constexpr int kZX = 64, kZT = 512;
 template <class T>
 constexpr int zstep_rows() { return 8; }
@@ -118,59 +121,99 @@ __global__ void __launch_bounds__(kZT) k_gp_zstep(GpArgs<T> a) {
   const bool tv3 = !a.tv2;
   const bool pre = !a.first;   // the dual is read (zero on the first step)
   const T* __restrict__ v = in_of(a);
-  // stage the dual of plane z (p_x, p_y, and p_z into parity slot z & 1)
-  auto stage = [&](int z) {
+  // What a thread loads of plane z: its points of the p_x, p_y and p_z stages
+  // (tile and halo, as laid out in LDS) and of v on the u region, held in
+  // registers so that plane z + 2 is in flight while plane z is computed.
+  constexpr int NXR = (XA + NT - 1) / NT, NYR = (YA + NT - 1) / NT, NUR = (UA + NT - 1) / NT;
+  struct Plane {
+    T px[NXR][NP], py[NYR][NP], pz[NUR][NP], v[NUR][NP];
+  };
+  auto fetch = [&](int z, Plane& r) {
     const size_t base = (size_t)z * plane;
-    for (int k = threadIdx.x; k < XA; k += NT) {
-      const int xx = x0 - 1 + k % XW, yy = y0 + k / XW;
-      const bool ok = xx >= 0 && xx < nx && yy < ny;
+#pragma unroll
+    for (int i = 0; i < NXR; ++i) {
+      const int k = threadIdx.x + i * NT, xx = x0 - 1 + k % XW, yy = y0 + k / XW;
+      const bool ok = pre && k < XA && xx >= 0 && xx < nx && yy < ny;
 #pragma unroll
       for (int part = 0; part < NP; ++part)
-        pxs[part][k] = ok ? a.p[0][part * n + base + (size_t)yy * nx + xx] : T(0);
+        r.px[i][part] = ok ? a.p[0][part * n + base + (size_t)yy * nx + xx] : T(0);
     }
-    for (int k = threadIdx.x; k < YA; k += NT) {
-      const int xx = x0 + k % UW, yy = y0 - 1 + k / UW;
-      const bool ok = xx < nx && yy >= 0 && yy < ny;
+#pragma unroll
+    for (int i = 0; i < NYR; ++i) {
+      const int k = threadIdx.x + i * NT, xx = x0 + k % UW, yy = y0 - 1 + k / UW;
+      const bool ok = pre && k < YA && xx < nx && yy >= 0 && yy < ny;
 #pragma unroll
       for (int part = 0; part < NP; ++part)
-        pys[part][k] = ok ? a.p[1][part * n + base + (size_t)yy * nx + xx] : T(0);
+        r.py[i][part] = ok ? a.p[1][part * n + base + (size_t)yy * nx + xx] : T(0);
     }
-    if (tv3) {
-      for (int k = threadIdx.x; k < UA; k += NT) {
-        const int xx = x0 + k % UW, yy = y0 + k / UW;
-        const bool ok = xx < nx && yy < ny;
 #pragma unroll
-        for (int part = 0; part < NP; ++part)
-          pzs[z & 1][part][k] = ok ? a.p[2][part * n + base + (size_t)yy * nx + xx] : T(0);
+    for (int i = 0; i < NUR; ++i) {
+      const int k = threadIdx.x + i * NT, xx = x0 + k % UW, yy = y0 + k / UW;
+      const bool ok = k < UA && xx < nx && yy < ny;
+      const size_t o = base + (size_t)yy * nx + xx;
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        r.pz[i][part] = (ok && pre && tv3) ? a.p[2][part * n + o] : T(0);
+        r.v[i][part] = ok ? v[part * n + o] : T(0);
       }
     }
   };
-  // u of plane z on the tile and its forward halo into slot z & 1
-  auto form_u = [&](int z) {
-    const size_t base = (size_t)z * plane;
-    for (int k = threadIdx.x; k < UA; k += NT) {
+  // the dual of plane z into LDS (p_z into parity slot z & 1)
+  auto commit = [&](int z, const Plane& r) {
+    if (!pre) return;
+#pragma unroll
+    for (int i = 0; i < NXR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k < XA)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) pxs[part][k] = r.px[i][part];
+    }
+#pragma unroll
+    for (int i = 0; i < NYR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k < YA)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) pys[part][k] = r.py[i][part];
+    }
+    if (tv3) {
+#pragma unroll
+      for (int i = 0; i < NUR; ++i) {
+        const int k = threadIdx.x + i * NT;
+        if (k < UA)
+#pragma unroll
+          for (int part = 0; part < NP; ++part) pzs[z & 1][part][k] = r.pz[i][part];
+      }
+    }
+  };
+  // u of plane z on the tile and its forward halo into slot z & 1 (v from the
+  // registers, the dual from LDS)
+  auto form_u = [&](int z, const Plane& r) {
+#pragma unroll
+    for (int i = 0; i < NUR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k >= UA) continue;
       const int lx = k % UW, ly = k / UW, xx = x0 + lx, yy = y0 + ly;
       const bool ok = xx < nx && yy < ny;
 #pragma unroll
       for (int part = 0; part < NP; ++part) {
-        T u = T(0);
-        if (ok) {
-          u = v[part * n + base + (size_t)yy * nx + xx];
-          if (pre) {
-            T d = (xx + 1 < nx ? pxs[part][ly * XW + lx + 1] : T(0)) - (xx > 0 ? pxs[part][ly * XW + lx] : T(0));
-            d += (yy + 1 < ny ? pys[part][(ly + 1) * UW + lx] : T(0)) - (yy > 0 ? pys[part][ly * UW + lx] : T(0));
-            if (tv3)
-              d += (z + 1 < nz ? pzs[z & 1][part][k] : T(0)) - (z > 0 ? pzs[(z & 1) ^ 1][part][k] : T(0));
-            u = fmaT(a.tau, d, u);
-          }
+        T u = r.v[i][part];
+        if (ok && pre) {
+          T d = (xx + 1 < nx ? pxs[part][ly * XW + lx + 1] : T(0)) - (xx > 0 ? pxs[part][ly * XW + lx] : T(0));
+          d += (yy + 1 < ny ? pys[part][(ly + 1) * UW + lx] : T(0)) - (yy > 0 ? pys[part][ly * UW + lx] : T(0));
+          if (tv3)
+            d += (z + 1 < nz ? pzs[z & 1][part][k] : T(0)) - (z > 0 ? pzs[(z & 1) ^ 1][part][k] : T(0));
+          u = fmaT(a.tau, d, u);
         }
         us[z & 1][part][k] = u;
       }
     }
   };
-  if (pre) stage(0);
+  Plane R;
+  fetch(0, R);
+  commit(0, R);
   __syncthreads();
-  form_u(0);
+  form_u(0, R);
+  if (nz > 1) fetch(1, R);
   for (int z = 0; z < nz; ++z) {
     const int s0 = z & 1, s1 = s0 ^ 1;
     // this thread's dual of plane z, read before plane z + 1 is staged over it
@@ -187,9 +230,10 @@ __global__ void __launch_bounds__(kZT) k_gp_zstep(GpArgs<T> a) {
     }
     __syncthreads();
     if (z + 1 < nz) {
-      if (pre) stage(z + 1);
+      commit(z + 1, R);
       __syncthreads();
-      form_u(z + 1);
+      form_u(z + 1, R);
+      if (z + 2 < nz) fetch(z + 2, R);   // in flight while plane z is computed
     }
     __syncthreads();
 #pragma unroll
