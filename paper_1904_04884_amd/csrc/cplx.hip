@@ -97,7 +97,8 @@ __device__ __forceinline__ T neg_div(const GpArgs<T>& a, size_t i, size_t o, int
 // go to registers two planes ahead and into LDS when the plane's turn comes,
 // so they are in flight while the plane before is computed (132 -> 87 ms per
 // outer iteration at 1024^2 x 256 complex).  It reads the dual set a.p and
-// writes the other set a.q.
+// writes the other set a.q.  FP32 runs it only for an odd last step
+// (k_gp_zstep2 takes the steps in pairs); FP64 runs every step with it.
 constexpr int kZX = 64, kZT = 512;
 template <class T>
 constexpr int zstep_rows() { return 8; }
@@ -264,6 +265,256 @@ __global__ void __launch_bounds__(kZT) k_gp_zstep(GpArgs<T> a) {
   }
 }
 
+// Two gradient-projection steps in one launch, streamed along z like
+// k_gp_zstep: the first step's dual p' never leaves LDS, so a pair of steps
+// reads p and v once and writes p'' once (56 B per complex voxel per two
+// steps instead of per step).  The second step needs p' on the tile and a
+// one-voxel ring around it, which needs u on the tile and a ring of two on the
+// +x / +y side and one on the other sides, which needs p on a ring of two on
+// the -x / -y side.  Regions, relative to the tile origin:
+//   p_x staged  x in [-2, 65], y in [-1, 9]     u, v, p_z   x in [-1, 65], y in [-1, 9]
+//   p_y staged  x in [-1, 65], y in [-2, 9]     p'          x in [-1, 64], y in [-1, 8]
+//   u' = v - tau D^T p'   x in [0, 64], y in [0, 8]          p''   the 64 x 8 tile
+// At plane z the block stages p(z + 1), forms u(z + 1), steps p'(z), forms
+// u'(z) and steps p''(z - 1), with every plane's loads issued into registers
+// two planes ahead.  FP32 only (its LDS, 78 KB, holds two blocks per CU):
+// 87 -> 69 ms per outer iteration at 1024^2 x 256 complex.
+template <class T, int NP>
+__global__ void __launch_bounds__(kZT) k_gp_zstep2(GpArgs<T> a) {
+  if (done(a.st)) return;
+  constexpr int NT = kZT, TW = kZX, TH = kZT / kZX;
+  constexpr int AW = TW + 3, AH = TH + 3, AA = AW * AH;    // u, v, p_z
+  constexpr int XW = TW + 4, XA = XW * AH;                 // p_x
+  constexpr int YW = AW, YH = TH + 4, YA = YW * YH;        // p_y
+  constexpr int BW = TW + 2, BH = TH + 2, BA = BW * BH;    // p'
+  constexpr int CW = TW + 1, CH = TH + 1, CA = CW * CH;    // u'
+  __shared__ T pxs[NP][XA];
+  __shared__ T pys[NP][YA];
+  __shared__ T pzs[2][NP][AA];
+  __shared__ T vs[2][NP][AA];
+  __shared__ T us[2][NP][AA];
+  __shared__ T qxs[NP][BA];
+  __shared__ T qys[NP][BA];
+  __shared__ T qzs[2][NP][BA];
+  __shared__ T ws[2][NP][CA];
+  const int nx = a.nx, ny = a.ny, nz = a.nz;
+  const size_t plane = (size_t)nx * ny, n = plane * nz;
+  const int x0 = blockIdx.x * TW, y0 = blockIdx.y * TH;
+  const bool tv3 = !a.tv2;
+  const bool pre = !a.first;   // p is read (zero before the first step)
+  const T tau = a.tau, cc = a.c;
+  const T* __restrict__ v = in_of(a);
+  auto inside = [&](int gx, int gy) { return gx >= 0 && gx < nx && gy >= 0 && gy < ny; };
+  // a plane's loads, in registers until its turn
+  constexpr int NXR = (XA + NT - 1) / NT, NYR = (YA + NT - 1) / NT, NAR = (AA + NT - 1) / NT;
+  struct Plane {
+    T px[NXR][NP], py[NYR][NP], pz[NAR][NP], v[NAR][NP];
+  };
+  auto fetch = [&](int z, Plane& r) {
+    const size_t base = (size_t)z * plane;
+#pragma unroll
+    for (int i = 0; i < NXR; ++i) {
+      const int k = threadIdx.x + i * NT, gx = x0 + k % XW - 2, gy = y0 + k / XW - 1;
+      const bool ok = pre && k < XA && inside(gx, gy);
+#pragma unroll
+      for (int part = 0; part < NP; ++part)
+        r.px[i][part] = ok ? a.p[0][part * n + base + (size_t)gy * nx + gx] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NYR; ++i) {
+      const int k = threadIdx.x + i * NT, gx = x0 + k % YW - 1, gy = y0 + k / YW - 2;
+      const bool ok = pre && k < YA && inside(gx, gy);
+#pragma unroll
+      for (int part = 0; part < NP; ++part)
+        r.py[i][part] = ok ? a.p[1][part * n + base + (size_t)gy * nx + gx] : T(0);
+    }
+#pragma unroll
+    for (int i = 0; i < NAR; ++i) {
+      const int k = threadIdx.x + i * NT, gx = x0 + k % AW - 1, gy = y0 + k / AW - 1;
+      const bool ok = k < AA && inside(gx, gy);
+      const size_t o = base + (size_t)(ok ? gy : 0) * nx + (ok ? gx : 0);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        r.pz[i][part] = (ok && pre && tv3) ? a.p[2][part * n + o] : T(0);
+        r.v[i][part] = ok ? v[part * n + o] : T(0);
+      }
+    }
+  };
+  auto commit = [&](int z, const Plane& r) {
+    const int sl = z & 1;
+#pragma unroll
+    for (int i = 0; i < NXR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k < XA)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) pxs[part][k] = r.px[i][part];
+    }
+#pragma unroll
+    for (int i = 0; i < NYR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k < YA)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) pys[part][k] = r.py[i][part];
+    }
+#pragma unroll
+    for (int i = 0; i < NAR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k < AA)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) {
+          pzs[sl][part][k] = r.pz[i][part];
+          vs[sl][part][k] = r.v[i][part];
+        }
+    }
+  };
+  // u(z) = v - tau D^T p on the u region
+  auto form_u = [&](int z) {
+    const int sl = z & 1;
+#pragma unroll
+    for (int i = 0; i < NAR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k >= AA) continue;
+      const int lx = k % AW - 1, ly = k / AW - 1, gx = x0 + lx, gy = y0 + ly;
+      const bool in = inside(gx, gy);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        T u = vs[sl][part][k];
+        if (in && pre) {
+          const int ix = (ly + 1) * XW + lx + 2, iy = (ly + 2) * YW + lx + 1;
+          T d = (gx + 1 < nx ? pxs[part][ix] : T(0)) - (gx > 0 ? pxs[part][ix - 1] : T(0));
+          d += (gy + 1 < ny ? pys[part][iy] : T(0)) - (gy > 0 ? pys[part][iy - YW] : T(0));
+          if (tv3) d += (z + 1 < nz ? pzs[sl][part][k] : T(0)) - (z > 0 ? pzs[sl ^ 1][part][k] : T(0));
+          u = fmaT(tau, d, u);
+        }
+        us[sl][part][k] = in ? u : T(0);
+      }
+    }
+  };
+  constexpr int NBR = (BA + NT - 1) / NT, NCR = (CA + NT - 1) / NT;
+  Plane R;
+  fetch(0, R);
+  commit(0, R);
+  __syncthreads();
+  form_u(0);
+  if (nz > 1) fetch(1, R);
+  // this thread's p' of the plane below on the tile (second step's input)
+  const int tx = threadIdx.x % TW, ty = threadIdx.x / TW, gxt = x0 + tx, gyt = y0 + ty;
+  const bool int_ = inside(gxt, gyt);
+  T pp1[3][NP];
+  // p''(m) on the tile from u'(m) (slot m & 1), u'(m + 1) (the other slot, when
+  // hz) and pp1 = p'(m); stored to a.q
+  auto step2_out = [&](int m, bool hz) {
+    const int sl = m & 1;
+    const int kc = ty * CW + tx;
+    T q[3][NP];
+    T n2 = T(0);
+#pragma unroll
+    for (int part = 0; part < NP; ++part) {
+      const T wc = ws[sl][part][kc];
+      const T g[3] = {gxt + 1 < nx ? ws[sl][part][kc + 1] - wc : T(0), gyt + 1 < ny ? ws[sl][part][kc + CW] - wc : T(0),
+                      hz ? ws[sl ^ 1][part][kc] - wc : T(0)};
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        q[d][part] = (d < 2 || tv3) ? fmaT(cc, g[d], pp1[d][part]) : T(0);
+        n2 = fmaT(q[d][part], q[d][part], n2);
+      }
+    }
+    if (int_) {
+      const T sc = n2 > T(1) ? sqrtT(n2) : T(1);
+      const size_t i = (size_t)m * plane + (size_t)gyt * nx + gxt;
+      const int nd = tv3 ? 3 : 2;
+      for (int d = 0; d < nd; ++d)
+#pragma unroll
+        for (int part = 0; part < NP; ++part) a.q[d][part * n + i] = q[d][part] / sc;
+    }
+  };
+  for (int z = 0; z < nz; ++z) {
+    const int sl = z & 1;
+    // p(z) on the p' region, read before plane z + 1 is staged over it
+    T p0[NBR][3][NP];
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) {
+      const int k = threadIdx.x + i * NT, lx = k % BW - 1, ly = k / BW - 1;
+      const bool ok = pre && k < BA;
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        p0[i][0][part] = ok ? pxs[part][(ly + 1) * XW + lx + 2] : T(0);
+        p0[i][1][part] = ok ? pys[part][(ly + 2) * YW + lx + 1] : T(0);
+        p0[i][2][part] = (ok && tv3) ? pzs[sl][part][(ly + 1) * AW + lx + 1] : T(0);
+      }
+    }
+    __syncthreads();
+    if (z + 1 < nz) {
+      commit(z + 1, R);
+      __syncthreads();
+      form_u(z + 1);
+      if (z + 2 < nz) fetch(z + 2, R);   // in flight while this plane is computed
+    }
+    __syncthreads();
+    // first step: p'(z) on the p' region
+    const bool hz1 = tv3 && z + 1 < nz;
+#pragma unroll
+    for (int i = 0; i < NBR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k >= BA) continue;
+      const int lx = k % BW - 1, ly = k / BW - 1, gx = x0 + lx, gy = y0 + ly;
+      const int ku = (ly + 1) * AW + lx + 1;
+      T q[3][NP];
+      T n2 = T(0);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        const T uc = us[sl][part][ku];
+        const T g[3] = {gx + 1 < nx ? us[sl][part][ku + 1] - uc : T(0), gy + 1 < ny ? us[sl][part][ku + AW] - uc : T(0),
+                        hz1 ? us[sl ^ 1][part][ku] - uc : T(0)};
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          q[d][part] = (d < 2 || tv3) ? fmaT(cc, g[d], p0[i][d][part]) : T(0);
+          n2 = fmaT(q[d][part], q[d][part], n2);
+        }
+      }
+      const bool in = inside(gx, gy);
+      const T sc = n2 > T(1) ? sqrtT(n2) : T(1);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        qxs[part][k] = in ? q[0][part] / sc : T(0);
+        qys[part][k] = in ? q[1][part] / sc : T(0);
+        qzs[sl][part][k] = in ? q[2][part] / sc : T(0);
+      }
+    }
+    __syncthreads();
+    // u'(z) = v - tau D^T p' on the u' region
+#pragma unroll
+    for (int i = 0; i < NCR; ++i) {
+      const int k = threadIdx.x + i * NT;
+      if (k >= CA) continue;
+      const int lx = k % CW, ly = k / CW, gx = x0 + lx, gy = y0 + ly;
+      const int kb = (ly + 1) * BW + lx + 1;
+      const bool in = inside(gx, gy);
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        T d = (gx + 1 < nx ? qxs[part][kb] : T(0)) - (gx > 0 ? qxs[part][kb - 1] : T(0));
+        d += (gy + 1 < ny ? qys[part][kb] : T(0)) - (gy > 0 ? qys[part][kb - BW] : T(0));
+        if (tv3) d += (z + 1 < nz ? qzs[sl][part][kb] : T(0)) - (z > 0 ? qzs[sl ^ 1][part][kb] : T(0));
+        ws[sl][part][k] = in ? fmaT(tau, d, vs[sl][part][(ly + 1) * AW + lx + 1]) : T(0);
+      }
+    }
+    __syncthreads();
+    // second step for the plane below, whose u' is complete now
+    if (z > 0) step2_out(z - 1, tv3);
+    // p'(z) on the tile for the next second step
+    {
+      const int kb = (ty + 1) * BW + tx + 1;
+#pragma unroll
+      for (int part = 0; part < NP; ++part) {
+        pp1[0][part] = qxs[part][kb];
+        pp1[1][part] = qys[part][kb];
+        pp1[2][part] = qzs[sl][part][kb];
+      }
+    }
+  }
+  step2_out(nz - 1, false);
+}
+
 // u once more, then the threshold and the flags.  In place is allowed (a
 // voxel reads only its own v).
 template <class T, int NP>
@@ -373,14 +624,28 @@ template <class T, int NP>
 hipError_t run_gp(GpArgs<T> a, int K, hipStream_t s, int* launches) {
   const dim3 g(ggrid((size_t)a.nx * a.ny * a.nz)), b(kGThreads);
   const dim3 gz((a.nx + kZX - 1) / kZX, (a.ny + zstep_rows<T>() - 1) / zstep_rows<T>()), bz(kZT);
-  for (int k = 0; k < K; ++k) {
+  // FP32: pairs of steps in one launch, an odd step last on its own
+  constexpr bool kPairs = sizeof(T) == 4;
+  const dim3 gz2((a.nx + kZX - 1) / kZX, (a.ny + kZT / kZX - 1) / (kZT / kZX));
+  (void)gz2;
+  int nl = 0;
+  for (int k = 0; k < K;) {
     a.first = k == 0 ? 1 : 0;
-    hipLaunchKernelGGL((k_gp_zstep<T, NP>), gz, bz, 0, s, a);
+    int steps = 1;
+    if constexpr (kPairs) {
+      if (K - k >= 2) {
+        hipLaunchKernelGGL((k_gp_zstep2<T, NP>), gz2, bz, 0, s, a);
+        steps = 2;
+      }
+    }
+    if (steps == 1) hipLaunchKernelGGL((k_gp_zstep<T, NP>), gz, bz, 0, s, a);
+    k += steps;
     for (int d = 0; d < 3; ++d) std::swap(a.p[d], a.q[d]);
+    ++nl;
   }
   a.first = K == 0 ? 1 : 0;
   hipLaunchKernelGGL((k_gp_final<T, NP>), g, b, 0, s, a);
-  if (launches) *launches = K + 1;
+  if (launches) *launches = nl + 1;
   return hipGetLastError();
 }
 
