@@ -91,6 +91,28 @@ def test_prox(torch_cuda, shape, dims, k):
         p.close()
 
 
+@pytest.mark.parametrize("shape", [(48, 24, 2), (32, 16, 1), (96, 48, 3), (16, 96, 4)])
+@pytest.mark.parametrize("dims", [3, 2])
+@pytest.mark.parametrize("k", [2, 3, 4])
+def test_prox_paired_steps_ragged(torch_cuda, shape, dims, k):
+    """Dual steps taken two per launch (an odd one alone): a single pair from
+    the zero dual, a pair and a lone step, two pairs; tiles that overhang the
+    volume in x (every plan size is a multiple of 8, the tile height), one to
+    four planes."""
+    torch = torch_cuda
+    g = cgeom(*shape, tv_dims=dims)
+    rng = np.random.default_rng(31 * k + dims + shape[0])
+    v = crandn(rng, g.shape, 0.3)
+    step, l1, tv = 0.6, 0.05, 0.3
+    ref = co.prox_fused_lasso(v, step, l1, tv, k, dims)
+    p = rihvr.Plan(g)
+    try:
+        out = p.prox(to_dev(torch, v), step, l1, tv, k, nonneg=False)
+        assert rel_l2(to_host(out), ref) <= 1e-5
+    finally:
+        p.close()
+
+
 def test_prox_global_phase(torch_cuda):
     """The complex TV and l1 are blind to a global phase: rotating v rotates the
     prox (to FP32 rounding), which separate projections of the two parts
